@@ -1,0 +1,198 @@
+"""Plain FP64 CPU oracle for the direct-summation linking number.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library (``paper_2106_12655_amd``) and never imports it; the two
+meet only through the seeded input generators, which hold none of the method's
+arithmetic.
+
+The arithmetic lives in ``lk_oracle.c`` (plain C, double precision, libm
+``atan2``/``sqrt``), built with gcc by :func:`build`.  Every routine follows a
+passage of Qu & James, "Fast Linking Numbers for Topology Verification of Loopy
+Structures" (SIGGRAPH 2021):
+
+* :func:`term` -- Eq. 4 (per segment-pair signed solid angle / 2 pi), as printed.
+* :func:`term_midpoint` -- the midpoint quadrature of Eq. 2.
+* :func:`pair` -- Eq. 3 / Eq. 5 summed in the order of Alg. 5 (Neumaier sums).
+* :func:`pair_anglesum` -- the angle-summation evaluation of the appendix (Alg. 7).
+* :func:`direct_sum` -- :func:`pair` over a pair list, threaded over pairs.
+* :func:`loop_flags` -- the zero-length-segment test of Alg. 3 plus finiteness.
+* :func:`aabb_pairs` -- brute-force potential link search (Alg. 2 semantics).
+* :func:`crossings` -- brute-force signed crossing count (Sec. 2.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lk_oracle.c")
+_LIB = os.path.join(_HERE, "liblkoracle.so")
+_lock = threading.Lock()
+_lib = None
+
+# Flag bits reported by loop_flags (same meaning as the library's flags).
+FLAG_NONFINITE = 4
+FLAG_BADLOOP = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile lk_oracle.c into liblkoracle.so with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+               "-pthread", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        d, i64, i32, p = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        lib.lko_term.restype = d
+        lib.lko_term.argtypes = [p, p, p, p]
+        lib.lko_term_mid.restype = d
+        lib.lko_term_mid.argtypes = [p, p, p, p]
+        lib.lko_pair.restype = d
+        lib.lko_pair.argtypes = [p, i64, p, i64]
+        lib.lko_pair_anglesum.restype = d
+        lib.lko_pair_anglesum.argtypes = [p, i64, p, i64]
+        lib.lko_direct_sum.restype = ctypes.c_int
+        lib.lko_direct_sum.argtypes = [p, p, i32, p, i64, p, p, ctypes.c_int]
+        lib.lko_loop_flags.restype = ctypes.c_int
+        lib.lko_loop_flags.argtypes = [p, p, i32, d, p]
+        lib.lko_aabb_pairs.restype = i64
+        lib.lko_aabb_pairs.argtypes = [p, p, i32, p, i64]
+        lib.lko_crossings.restype = d
+        lib.lko_crossings.argtypes = [p, i64, p, i64, p, ctypes.POINTER(ctypes.c_int)]
+        lib.lko_set_mutation.restype = None
+        lib.lko_set_mutation.argtypes = [ctypes.c_int]
+        _lib = lib
+        return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_mutation(m: int) -> None:
+    """Plant a deliberate mistake in the oracle (tests of the pins only).
+
+    1 drop a term of D1, 2 wrong sign in the second arctangent, 3 wrong vertex
+    index in c, 4 transposed difference vectors, 5 open (non-cyclic) loop,
+    6 wrong normalisation (4 pi instead of 2 pi).  0 restores the oracle.
+    """
+    _load().lko_set_mutation(int(m))
+
+
+def term(lj, lj1, ki, ki1) -> float:
+    """Eq. 4 for segment (lj, lj1) of gamma_1 and segment (ki, ki1) of gamma_2."""
+    v = [_f64(x).reshape(3) for x in (lj, lj1, ki, ki1)]
+    return _load().lko_term(*[_ptr(x) for x in v])
+
+
+def term_midpoint(lj, lj1, ki, ki1) -> float:
+    """Midpoint quadrature of Eq. 2 for one segment pair."""
+    v = [_f64(x).reshape(3) for x in (lj, lj1, ki, ki1)]
+    return _load().lko_term_mid(*[_ptr(x) for x in v])
+
+
+def pair(L, K) -> float:
+    """Linking number of closed polylines L (gamma_1) and K (gamma_2), Alg. 5."""
+    L = _f64(L).reshape(-1, 3)
+    K = _f64(K).reshape(-1, 3)
+    return _load().lko_pair(_ptr(L), L.shape[0], _ptr(K), K.shape[0])
+
+
+def pair_anglesum(L, K) -> float:
+    """Same value via the angle-summation form of Alg. 7."""
+    L = _f64(L).reshape(-1, 3)
+    K = _f64(K).reshape(-1, 3)
+    return _load().lko_pair_anglesum(_ptr(L), L.shape[0], _ptr(K), K.shape[0])
+
+
+def direct_sum(xyz, offsets, pairs, nthreads: int | None = None):
+    """Real and integer linking numbers for every pair (loop pairs[p,0] is gamma_1).
+
+    ``xyz`` may be float32 or float64; float32 values are promoted exactly.
+    Returns ``(real float64[P], int int32[P])``; invalid pairs give NaN and
+    INT32_MIN.
+    """
+    xyz = _f64(xyz).reshape(-1, 3)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32)).reshape(-1, 2)
+    n = pr.shape[0]
+    real = np.zeros(n, dtype=np.float64)
+    lk = np.zeros(n, dtype=np.int32)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    rc = _load().lko_direct_sum(_ptr(xyz), _ptr(off), off.shape[0] - 1, _ptr(pr), n, _ptr(real),
+                                _ptr(lk), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return real, lk
+
+
+def loop_flags(xyz, offsets, eps: float):
+    """Per-loop flags: FLAG_BADLOOP (<3 vertices or a segment shorter than
+    eps * mean |coordinate|), FLAG_NONFINITE (NaN/Inf coordinate)."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    out = np.zeros(off.shape[0] - 1, dtype=np.uint32)
+    _load().lko_loop_flags(_ptr(xyz), _ptr(off), off.shape[0] - 1, float(eps), _ptr(out))
+    return out
+
+
+def aabb_pairs(xyz, offsets):
+    """All i<j with overlapping closed AABBs, lexicographic, as int32[P,2]."""
+    xyz = _f64(xyz).reshape(-1, 3)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    lib = _load()
+    n = lib.lko_aabb_pairs(_ptr(xyz), _ptr(off), off.shape[0] - 1, None, 0)
+    out = np.zeros((max(n, 1), 2), dtype=np.int32)
+    lib.lko_aabb_pairs(_ptr(xyz), _ptr(off), off.shape[0] - 1, _ptr(out), n)
+    return out[:n]
+
+
+def crossings(L, K, R):
+    """Half the signed crossing count of L and K viewed along z after x -> R x.
+
+    Returns ``(value, degenerate)``; when ``degenerate`` the frame is not a
+    regular projection for this pair and another frame must be drawn.
+    """
+    L = _f64(L).reshape(-1, 3)
+    K = _f64(K).reshape(-1, 3)
+    R = _f64(R).reshape(3, 3)
+    deg = ctypes.c_int(0)
+    v = _load().lko_crossings(_ptr(L), L.shape[0], _ptr(K), K.shape[0], _ptr(R), ctypes.byref(deg))
+    return v, bool(deg.value)
+
+
+def crossings_random(L, K, seed: int = 0, tries: int = 20) -> float:
+    """Crossing count in a seeded random frame (QR of a Gaussian matrix),
+    drawing again whenever the projection is not regular."""
+    rng = np.random.default_rng(seed)
+    for _ in range(tries):
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        v, deg = crossings(L, K, q)
+        if not deg:
+            return v
+    raise RuntimeError("no regular projection found")

@@ -1,0 +1,522 @@
+"""Seeded synthetic inputs for the direct-summation linking-number path.
+
+This module builds geometry only: closed polylines stored as a vertex array
+``xyz[V, 3]`` plus loop offsets ``offsets[L + 1]`` (loop ``l`` owns vertices
+``offsets[l] .. offsets[l+1]-1``; segment ``s`` joins vertex ``s`` to ``s+1``
+cyclically, the first vertex is not repeated).  It evaluates no linking
+number: the expected values it returns come from how each shape is built
+(which ring passes through which, how many clasps a knit row has, how many
+turns a companion curve winds), and the test suite checks those construction
+rules against the oracle on small instances.  Both the HIP path and the oracle
+are fed from here; this module imports neither.
+
+The workloads stand in for the paper's inputs (Sec. 6, Table 1): a small ring
+grid, a 4-in-1 chainmail sheet (the paper's chainmail rows), knit-like tubes of
+closed yarn rows made from periodic cubic B-splines (the paper's StitchMesh
+yarn models, which are not available), and long winding curve pairs (the
+paper's ribbon / woundball stress tests).  None of them reproduces a dataset.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class LoopSet:
+    """Closed polylines plus the linking numbers their construction implies.
+
+    ``exp_pairs``/``exp_lk``: every loop pair whose construction gives a
+    non-zero linking number, sorted lexicographically with i < j; every other
+    pair is expected to be 0.  ``pairs`` is a candidate pair list when the
+    generator knows one (otherwise the caller runs the potential link search).
+    """
+
+    xyz: np.ndarray
+    offsets: np.ndarray
+    exp_pairs: np.ndarray
+    exp_lk: np.ndarray
+    name: str = ""
+    seed: int = 0
+    pairs: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_loops(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def loop(self, i: int) -> np.ndarray:
+        return self.xyz[self.offsets[i]:self.offsets[i + 1]]
+
+    def expected_for(self, pairs: np.ndarray) -> np.ndarray:
+        """Expected integer for each row of ``pairs`` (0 where not listed)."""
+        pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+        L = self.n_loops
+        out = np.zeros(pairs.shape[0], dtype=np.int32)
+        if self.exp_pairs.shape[0] == 0 or pairs.shape[0] == 0:
+            return out
+        ek = self.exp_pairs[:, 0].astype(np.int64) * L + self.exp_pairs[:, 1]
+        qk = pairs[:, 0] * L + pairs[:, 1]
+        pos = np.searchsorted(ek, qk)
+        pos = np.minimum(pos, ek.shape[0] - 1)
+        hit = ek[pos] == qk
+        out[hit] = self.exp_lk[pos[hit]]
+        return out
+
+
+def terms(sizes: np.ndarray, pairs: np.ndarray) -> int:
+    """Number of segment-pair terms of a pair list: sum over pairs of N_a * N_b."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    s = np.asarray(sizes, dtype=np.int64)
+    return int(np.sum(s[pairs[:, 0]] * s[pairs[:, 1]]))
+
+
+def _pack(loops, dtype, exp, name, seed, pairs=None, meta=None) -> LoopSet:
+    sizes = np.array([len(x) for x in loops], dtype=np.int64)
+    off = np.zeros(len(loops) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    xyz = np.ascontiguousarray(np.concatenate(loops, axis=0).astype(dtype))
+    if exp:
+        items = sorted((min(i, j), max(i, j), v) for (i, j), v in exp.items() if v != 0)
+        ep = np.array([[a, b] for a, b, _ in items], dtype=np.int32).reshape(-1, 2)
+        ev = np.array([v for _, _, v in items], dtype=np.int32)
+    else:
+        ep = np.zeros((0, 2), dtype=np.int32)
+        ev = np.zeros(0, dtype=np.int32)
+    return LoopSet(xyz, off, ep, ev, name, seed, pairs, dict(meta or {}))
+
+
+# ----------------------------------------------------------------- rotations
+def rot_x(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+
+
+def rot_y(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+
+
+def rot_z(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def rot_axis(axis, a):
+    """Rodrigues rotation by angle ``a`` about unit vector ``axis``."""
+    k = np.asarray(axis, dtype=np.float64)
+    k = k / np.linalg.norm(k)
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(a) * K + (1 - np.cos(a)) * (K @ K)
+
+
+def random_rotation(rng) -> np.ndarray:
+    """Uniform random proper rotation (QR of a Gaussian matrix)."""
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def circle(n: int, radius: float = 1.0) -> np.ndarray:
+    t = 2 * np.pi * np.arange(n) / n
+    return np.stack([radius * np.cos(t), radius * np.sin(t), np.zeros(n)], axis=1)
+
+
+# ----------------------------------------------------------- closed-form pins
+def hopf(n: int = 64, dtype=np.float64) -> LoopSet:
+    """Two unit circles, A in the xy plane and B in the xz plane through A's
+    centre region: A = (cos t, sin t, 0), B = (1 + cos t, 0, sin t).
+    With these orientations the pair (A, B) has linking number -1."""
+    t = 2 * np.pi * np.arange(n) / n
+    A = np.stack([np.cos(t), np.sin(t), 0 * t], 1)
+    B = np.stack([1 + np.cos(t), 0 * t, np.sin(t)], 1)
+    return _pack([A, B], dtype, {(0, 1): -1}, "hopf", 0, np.array([[0, 1]], np.int32))
+
+
+def torus_link(m: int, n: int, N: int = 400, dtype=np.float64) -> LoopSet:
+    """Torus link: A winds m times toroidally and once poloidally on a torus of
+    radii (3, 0.3); B winds once toroidally and n times poloidally on a torus of
+    radii (3, 0.8).  Linking number -m*n for these orientations (the magnitude
+    is the product rule the paper states for its torus stress test)."""
+    t = 2 * np.pi * np.arange(N) / N
+    A = np.stack([(3 + 0.3 * np.cos(t)) * np.cos(m * t), (3 + 0.3 * np.cos(t)) * np.sin(m * t),
+                  0.3 * np.sin(t)], 1)
+    B = np.stack([(3 + 0.8 * np.cos(n * t)) * np.cos(t), (3 + 0.8 * np.cos(n * t)) * np.sin(t),
+                  0.8 * np.sin(n * t)], 1)
+    return _pack([A, B], dtype, {(0, 1): -m * n}, "torus_%d_%d" % (m, n), 0,
+                  np.array([[0, 1]], np.int32))
+
+
+# ------------------------------------------------------------- ring grid (C1)
+def ring_grid(seed: int = 0, rows: int = 8, cols: int = 8, nseg: int = 32, spacing: float = 1.6,
+              jitter: float = 0.02, dtype=np.float64) -> LoopSet:
+    """Grid of unit rings, ring (r, c) centred at (spacing*c, spacing*r, 0).
+
+    Rings with r + c even lie flat (xy plane); rings with r + c odd are turned
+    +90 degrees about x ((x, y, z) -> (x, -z, y)) so that every horizontal
+    neighbour pair is a Hopf-like link (checkerboard alternation).  Every
+    coordinate gets seeded uniform jitter in [-jitter, jitter].  Horizontal
+    pairs link with -1 when the flat ring is the left one and +1 when the
+    turned ring is; flat diagonal neighbours overlap in their boxes but are
+    not linked.
+    """
+    rng = np.random.default_rng(seed)
+    base = circle(nseg)
+    turn = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], dtype=np.float64)
+    loops = []
+    for r in range(rows):
+        for c in range(cols):
+            P = base @ turn.T if (r + c) % 2 else base.copy()
+            P = P + np.array([spacing * c, spacing * r, 0.0])
+            P = P + rng.uniform(-jitter, jitter, size=P.shape)
+            loops.append(P)
+    exp = {}
+    for r in range(rows):
+        for c in range(cols - 1):
+            i, j = r * cols + c, r * cols + c + 1
+            exp[(i, j)] = -1 if (r + c) % 2 == 0 else 1
+    return _pack(loops, dtype, exp, "ring_grid", seed,
+                 meta={"rows": rows, "cols": cols, "nseg": nseg})
+
+
+# -------------------------------------------------------- 4-in-1 chainmail (C2)
+def chainmail(seed: int = 0, rows: int = 100, cols: int = 140, nseg: int = 64,
+              spacing: float = 1.1, tilt_deg: float = 40.0, sheet_deg: float = 45.0,
+              wobble_deg: float = 5.0, sigma: float = 0.01, dtype=np.float32,
+              pulled: np.ndarray | None = None) -> LoopSet:
+    """European 4-in-1 chainmail sheet of unit rings.
+
+    Ring (r, c) is centred at ((c + (r mod 2)/2) * spacing, r * spacing, 0) and
+    tilted by +tilt about y on even rows and -tilt on odd rows, so that each
+    ring passes through two rings of the row above and two of the row below.
+    The sheet is turned by ``sheet_deg`` about z (this only enlarges the axis-
+    aligned boxes, adding unlinked candidate pairs), then every ring is turned
+    about its centre by a seeded angle in [0, wobble] about a random axis and
+    every coordinate gets Gaussian noise of standard deviation ``sigma``.
+
+    Construction rule for the linking numbers (ring index r * cols + c): ring
+    (r, c) links ring (r+1, c) and ring (r+1, c - 1 + 2 (r mod 2)); the pair has
+    +1 when r is even and -1 when r is odd, all other pairs 0.
+
+    ``pulled``: optional boolean mask over the expected-link list (same order as
+    ``exp_pairs``); for each selected pair the upper ring is pulled through the
+    lower one (its piercing arc detours around the lower ring's wire), which
+    makes that pair's linking number 0 and leaves the others unchanged.
+    """
+    rng = np.random.default_rng(seed)
+    base = circle(nseg)
+    Rs = rot_z(np.deg2rad(sheet_deg))
+    centres, frames = [], []
+    for r in range(rows):
+        for c in range(cols):
+            ctr = np.array([(c + 0.5 * (r % 2)) * spacing, r * spacing, 0.0])
+            R = rot_y(np.deg2rad(tilt_deg if r % 2 == 0 else -tilt_deg))
+            centres.append(Rs @ ctr)
+            frames.append(Rs @ R)
+    centres = np.array(centres)
+    frames = np.array(frames)
+    L = rows * cols
+    axes = rng.standard_normal((L, 3))
+    angs = np.deg2rad(rng.uniform(0.0, wobble_deg, size=L))
+    exp = {}
+    for r in range(rows - 1):
+        for c in range(cols):
+            for cc in (c, c - 1 + 2 * (r % 2)):
+                if 0 <= cc < cols:
+                    exp[(r * cols + c, (r + 1) * cols + cc)] = 1 if r % 2 == 0 else -1
+    keys = sorted(exp)
+    local = [base.copy() for _ in range(L)]
+    if pulled is not None:
+        pulled = np.asarray(pulled, dtype=bool)
+        for k, (i, j) in enumerate(keys):
+            if pulled[k]:
+                local[j] = _pull_through(local[j], centres[i], frames[i], centres[j], frames[j])
+                exp[(i, j)] = 0
+    loops = []
+    for l in range(L):
+        W = rot_axis(axes[l], angs[l]) @ frames[l]
+        P = local[l] @ W.T + centres[l]
+        P = P + rng.normal(0.0, sigma, size=P.shape)
+        loops.append(P)
+    return _pack(loops, dtype, exp, "chainmail", seed,
+                 meta={"rows": rows, "cols": cols, "nseg": nseg, "sigma": sigma})
+
+
+def _pull_through(local_b, ca, Fa, cb, Fb, clearance=0.35, width=0.9):
+    """Detour ring B's arc that pierces ring A's disk around A's wire.
+
+    local_b: B's vertices in B's own frame (unit circle).  A's disk is the unit
+    disk of plane (ca, normal Fa[:, 2]).  The vertices of B near the piercing
+    point are pushed, inside A's plane direction, radially outwards from A's
+    centre until they clear A's wire by ``clearance``, with a smooth falloff
+    over an arc of ``width`` radians, so that B no longer crosses A's disk.
+    """
+    n = local_b.shape[0]
+    world = local_b @ Fb.T + cb
+    na = Fa[:, 2]
+    h = (world - ca) @ na  # signed height over A's plane
+    best, bt = None, None
+    for s in range(n):
+        h0, h1 = h[s], h[(s + 1) % n]
+        if h0 == 0 or h0 * h1 < 0:
+            t = h0 / (h0 - h1) if h0 != h1 else 0.0
+            p = world[s] + t * (world[(s + 1) % n] - world[s])
+            rr = np.linalg.norm((p - ca) - ((p - ca) @ na) * na)
+            if rr < 1.0 and (best is None or rr < best):
+                best, bt = rr, (s, t, p)
+    if bt is None:
+        return local_b
+    s, t, p = bt
+    radial = (p - ca) - ((p - ca) @ na) * na
+    radial = radial / np.linalg.norm(radial)
+    push = 1.0 + clearance - best  # how far the piercing point must move out
+    ang = 2 * np.pi * (np.arange(n) - (s + t)) / n
+    ang = (ang + np.pi) % (2 * np.pi) - np.pi
+    wgt = np.where(np.abs(ang) < width, 0.5 * (1 + np.cos(np.pi * ang / width)), 0.0)
+    moved = world + (push * wgt)[:, None] * radial[None, :]
+    return (moved - cb) @ Fb
+
+
+# ------------------------------------------------------------- knit tubes (C3)
+def bspline_closed(P: np.ndarray, per_span: int) -> np.ndarray:
+    """Uniform periodic cubic B-spline through control polygon P (closed),
+    sampled at ``per_span`` uniform parameter steps per span."""
+    n = P.shape[0]
+    t = np.arange(per_span, dtype=np.float64) / per_span
+    b0 = (1 - t) ** 3 / 6
+    b1 = (3 * t ** 3 - 6 * t ** 2 + 4) / 6
+    b2 = (-3 * t ** 3 + 3 * t ** 2 + 3 * t + 1) / 6
+    b3 = t ** 3 / 6
+    idx = np.arange(n)
+    out = (b0[None, :, None] * P[(idx - 1) % n][:, None, :] + b1[None, :, None] * P[idx][:, None, :]
+           + b2[None, :, None] * P[(idx + 1) % n][:, None, :]
+           + b3[None, :, None] * P[(idx + 2) % n][:, None, :])
+    return out.reshape(n * per_span, 3)
+
+
+_KNIT_D = 1.5      # depth of a stitch dip below the row's baseline (row pitch 1)
+_KNIT_DELTA = 0.45  # radial weave of a dip's two legs
+_KNIT_RMIN = 1.5
+
+
+def knit_row_controls(stitches: int, row: int, radius: float, signs) -> np.ndarray:
+    """Control polygon (4 points per stitch) of one closed yarn row of a tube.
+
+    The row runs once around the tube axis (z) at height ``row``.  At each
+    stitch it dips down below the previous row's baseline; the dip's two legs
+    sit at radius +-DELTA around the tube radius, so the dip clasps the row
+    below.  ``signs[s]`` = +1 puts the descending leg outside, -1 inside;
+    stitches of consecutive rows are staggered by half a stitch.
+    """
+    dphi = 2 * np.pi / stitches
+    pts = []
+    for s in range(stitches):
+        ph = (s + 0.5 * (row % 2)) * dphi
+        sg = float(signs[s])
+        for f, dz, dr in ((-0.25, 0.0, 0.0), (-0.09, -_KNIT_D, sg * _KNIT_DELTA),
+                          (0.09, -_KNIT_D, -sg * _KNIT_DELTA), (0.25, 0.0, 0.0)):
+            phi = ph + f * dphi
+            rho = radius + dr
+            pts.append([rho * np.cos(phi), rho * np.sin(phi), row + dz])
+    return np.array(pts)
+
+
+def knit_tube(stitches: int, rows: int, per_span: int = 32, pattern: str = "alternating",
+              rng=None, flip: set | None = None) -> tuple[list, dict]:
+    """Rows of one knit-like tube (local frame, axis z) and their links.
+
+    Construction rule: rows r-1 and r link with the sum of row r's clasp signs
+    (a clasp with its descending leg outside counts +1).  ``alternating``
+    (the stockinette-like default) alternates the signs, so an even stitch
+    count links 0; ``uniform`` makes every sign +1 (linking number = stitch
+    count).  ``flip``: set of (row, stitch) clasps whose sign is reversed.
+    """
+    radius = max(stitches / (2 * np.pi), _KNIT_RMIN)
+    loops, exp = [], {}
+    for r in range(rows):
+        if pattern == "uniform":
+            sg = np.ones(stitches)
+        else:
+            sg = np.array([(-1.0) ** s for s in range(stitches)])
+        if flip:
+            for s in range(stitches):
+                if (r, s) in flip:
+                    sg[s] = -sg[s]
+        loops.append(bspline_closed(knit_row_controls(stitches, r, radius, sg), per_span))
+        if r > 0:
+            exp[(r - 1, r)] = int(round(sg.sum()))
+    return loops, exp
+
+
+def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512,
+         rows_min: int = 5, rows_max: int = 20, per_span: int = 32, linked_fraction: float = 0.2,
+         tilt_deg: float = 35.0, gap: float = 0.3, dtype=np.float32) -> LoopSet:
+    """Knit-like tubes of closed periodic cubic B-spline yarn rows.
+
+    Each tube has a log-uniform control-point count per row in [cp_min, cp_max]
+    (4 per stitch, an even stitch count) and 5-20 rows; rows are discretised
+    uniformly at ``per_span`` segments per span, so row sizes are very uneven.
+    Tubes are stockinette-like (alternating clasps, linking 0 between rows,
+    the paper's observation for stitch rows) except for a seeded
+    ``linked_fraction`` that use the uniform clasp pattern (linking number =
+    stitch count between consecutive rows).  Every tube is turned by a seeded
+    rotation of up to ``tilt_deg`` off vertical and tubes are packed in a grid
+    whose bounding spheres are ``gap`` apart, so axis-aligned boxes of rows of
+    the same and of neighbouring tubes overlap without the curves coming close.
+    """
+    rng = np.random.default_rng(seed)
+    tubes = []
+    total = 0
+    while total < n_loops:
+        nr = int(rng.integers(rows_min, rows_max + 1))
+        nr = min(nr, n_loops - total)
+        if nr < 2:
+            nr = 2
+        cp = float(np.exp(rng.uniform(np.log(cp_min), np.log(cp_max))))
+        stitches = max(4, 2 * int(round(cp / 8.0)))
+        stitches = min(stitches, cp_max // 4)
+        pattern = "uniform" if rng.uniform() < linked_fraction else "alternating"
+        tubes.append((stitches, nr, pattern))
+        total += nr
+    loops, exp = [], {}
+    # bounding sphere per tube, placed on a square grid (largest first)
+    order = sorted(range(len(tubes)), key=lambda t: -tubes[t][0])
+    radii = []
+    for t in range(len(tubes)):
+        st, nr, _ = tubes[t]
+        rad = max(st / (2 * np.pi), _KNIT_RMIN) + _KNIT_DELTA + 0.5
+        radii.append(float(np.hypot(rad, 0.5 * (nr + _KNIT_D))))
+    side = int(np.ceil(np.sqrt(len(tubes))))
+    place = {}
+    cursor_y = 0.0
+    k = 0
+    while k < len(order):
+        rowt = order[k:k + side]
+        h = max(radii[t] for t in rowt)
+        x = 0.0
+        for t in rowt:
+            x += radii[t]
+            place[t] = np.array([x, cursor_y + h, 0.0])
+            x += radii[t] + gap
+        cursor_y += 2 * h + gap
+        k += side
+    for t in range(len(tubes)):
+        st, nr, pattern = tubes[t]
+        rows, e = knit_tube(st, nr, per_span, pattern)
+        axis = rng.standard_normal(3)
+        axis[2] = 0.0
+        Rt = rot_axis(axis, np.deg2rad(rng.uniform(0.0, tilt_deg))) @ rot_z(rng.uniform(0, 2 * np.pi))
+        mid = np.array([0.0, 0.0, 0.5 * (nr - 1) - 0.5 * _KNIT_D])
+        base = len(loops)
+        for P in rows:
+            loops.append((P - mid) @ Rt.T + place[t])
+        for (a, b), v in e.items():
+            exp[(base + a, base + b)] = v
+    return _pack(loops, dtype, exp, "knit", seed,
+                 meta={"tubes": len(tubes), "per_span": per_span})
+
+
+# --------------------------------------------------------- long loop pairs (C4)
+def _resample_closed(P: np.ndarray, n: int) -> np.ndarray:
+    """Resample a dense closed polyline uniformly in arc length to n points."""
+    Q = np.vstack([P, P[:1]])
+    seg = np.linalg.norm(np.diff(Q, axis=0), axis=1)
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    target = np.arange(n) * (s[-1] / n)
+    out = np.empty((n, 3))
+    for q in range(3):
+        out[:, q] = np.interp(target, s, Q[:, q])
+    return out
+
+
+def winding_pair(seed: int, n_a: int, n_b: int, lk: int, step: float = 1e-3, rho: float = 0.1,
+                 modes: int = 6, dense: int = 4):
+    """One long closed curve C and a companion D winding ``lk`` times around it.
+
+    C is a smooth random closed curve over a star-shaped planar outline
+    r(phi) = R0 (1 + sum a_k cos(k phi + psi_k)) with a random height
+    z(phi); its length is n_a * step.  D = C + rho (cos(theta) u + sin(theta) v)
+    with u the horizontal normal of C, v = t x u and theta = 2 pi lk s / len.
+    With lk = 0, D's top view is a parallel curve of C's simple top view, so
+    the two do not link; each full turn of theta adds one: Lk(C, D) = +lk for
+    this orientation.  D is resampled to n_b segments.
+    """
+    rng = np.random.default_rng(seed)
+    k = np.arange(2, modes + 2)
+    a = rng.uniform(0.0, 0.3, size=k.size) / k
+    psi = rng.uniform(0, 2 * np.pi, size=k.size)
+    b = rng.uniform(0.0, 0.15, size=k.size) / k
+    chi = rng.uniform(0, 2 * np.pi, size=k.size)
+    m = dense * max(n_a, n_b)
+    phi = 2 * np.pi * np.arange(m) / m
+
+    def shape(R0):
+        r = R0 * (1 + np.sum(a[:, None] * np.cos(k[:, None] * phi[None, :] + psi[:, None]), 0))
+        z = R0 * np.sum(b[:, None] * np.cos(k[:, None] * phi[None, :] + chi[:, None]), 0)
+        return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+    P1 = shape(1.0)
+    len1 = np.sum(np.linalg.norm(np.diff(np.vstack([P1, P1[:1]]), axis=0), axis=1))
+    R0 = n_a * step / len1
+    P = shape(R0)
+    C = _resample_closed(P, m)
+    t = np.roll(C, -1, 0) - np.roll(C, 1, 0)
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    u = np.stack([-t[:, 1], t[:, 0], 0 * t[:, 0]], 1)
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    v = np.cross(t, u)
+    theta = 2 * np.pi * lk * np.arange(m) / m
+    D = C + rho * (np.cos(theta)[:, None] * u + np.sin(theta)[:, None] * v)
+    Cn = _resample_closed(C, n_a)
+    Dn = _resample_closed(D, n_b)
+    return Cn, Dn, lk
+
+
+def long_pairs(seed: int = 0, n_pairs: int = 16, n_min: int = 1 << 18, n_max: int = 1 << 20,
+               lk_max: int = 5, step: float = 1e-3, rho: float = 0.1, dtype=np.float32) -> LoopSet:
+    """Long-loop stress test: ``n_pairs`` pairs (C_k, D_k), each loop with a
+    seeded size in [n_min, n_max] segments of length ~step, D_k winding a seeded
+    number of turns in [-lk_max, lk_max] around C_k.  Pairs are placed far
+    apart; the candidate list is the n_pairs (C_k, D_k) pairs."""
+    rng = np.random.default_rng(seed)
+    loops, exp, pairs = [], {}, []
+    x = 0.0
+    for q in range(n_pairs):
+        na = int(rng.integers(n_min, n_max + 1))
+        nb = int(np.clip(na + rng.integers(-na // 16, na // 16 + 1), n_min, n_max))
+        target = int(rng.integers(-lk_max, lk_max + 1))
+        C, D, val = winding_pair(int(rng.integers(1 << 31)), na, nb, target, step, rho)
+        ext = np.max(np.abs(C[:, :2])) + 2 * rho
+        x += ext
+        off = np.array([x, 0.0, 0.0])
+        x += ext + 1.0
+        i = len(loops)
+        loops += [C + off, D + off]
+        pairs.append([i, i + 1])
+        exp[(i, i + 1)] = val
+    return _pack(loops, dtype, exp, "long_pairs", seed, np.array(pairs, np.int32),
+                 meta={"n_pairs": n_pairs})
+
+
+# ------------------------------------------------------------- named configs
+def config(name: str, seed: int = 0, **kw) -> LoopSet:
+    """The five workloads by name: ``ring_grid`` (8x8 rings x 32 segments,
+    FP64), ``chainmail`` (14,000 rings x 64 segments, FP32), ``knit`` (2,000
+    B-spline rows, 512-16,384 segments each, FP32), ``long_pairs`` (16 pairs of
+    2^18-2^20-segment loops, FP32)."""
+    if name == "ring_grid":
+        return ring_grid(seed, **kw)
+    if name == "chainmail":
+        return chainmail(seed, **kw)
+    if name == "knit":
+        return knit(seed, **kw)
+    if name == "long_pairs":
+        return long_pairs(seed, **kw)
+    raise ValueError("unknown config %r" % name)

@@ -1,0 +1,116 @@
+"""Construction rules of the seeded generators, checked against the oracle.
+
+The generators state the linking numbers their shapes are built to have; these
+tests compare those statements with the oracle on instances small enough for
+it, and check the size/shape recipes of the workloads.
+"""
+import numpy as np
+
+import oracle
+from paper_2106_12655_amd import inputs as I
+
+
+def _check_against_oracle(ls, pairs=None):
+    if pairs is None:
+        pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    real, lk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    exp = ls.expected_for(pairs)
+    assert np.array_equal(lk, exp), np.nonzero(lk != exp)
+    assert np.max(np.abs(real - np.round(real))) < 1e-8
+    return pairs, real
+
+
+def test_ring_grid_recipe_and_links():
+    ls = I.ring_grid(0)
+    assert ls.n_loops == 64 and np.all(ls.sizes == 32) and ls.xyz.dtype == np.float64
+    pairs, _ = _check_against_oracle(ls)
+    assert len(pairs) == 105
+    assert len(ls.exp_pairs) == 56
+    assert set(np.unique(ls.exp_lk).tolist()) == {-1, 1}
+
+
+def test_ring_grid_seeds_differ_but_links_do_not():
+    a, b = I.ring_grid(1), I.ring_grid(2)
+    assert not np.array_equal(a.xyz, b.xyz)
+    _check_against_oracle(a)
+    _check_against_oracle(b)
+
+
+def test_chainmail_patch_links():
+    ls = I.chainmail(0, rows=6, cols=7)
+    assert ls.xyz.dtype == np.float32
+    pairs, _ = _check_against_oracle(ls)
+    # interior rings link exactly four neighbours
+    deg = np.zeros(ls.n_loops, int)
+    for i, j in ls.exp_pairs:
+        deg[i] += 1
+        deg[j] += 1
+    interior = [r * 7 + c for r in range(1, 5) for c in range(1, 6)]
+    assert np.all(deg[interior] == 4)
+    # the 45 degree sheet rotation adds unlinked candidates
+    assert len(pairs) > 2 * len(ls.exp_pairs)
+
+
+def test_chainmail_pull_through_unlinks_only_selected():
+    base = I.chainmail(3, rows=5, cols=6)
+    mask = np.zeros(len(base.exp_pairs), bool)
+    mask[[1, 7, 12]] = True
+    ls = I.chainmail(3, rows=5, cols=6, pulled=mask)
+    assert len(ls.exp_pairs) == len(base.exp_pairs) - 3
+    _check_against_oracle(ls)
+
+
+def test_chainmail_full_size_recipe():
+    ls = I.chainmail(0)
+    assert ls.n_loops == 14000 and np.all(ls.sizes == 64)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    assert 60000 < len(pairs) < 80000
+    assert 27000 < len(ls.exp_pairs) < 29000
+    assert abs(I.terms(ls.sizes, pairs) - 2.8e8) < 0.1e8
+
+
+def test_knit_small_tubes():
+    ls = I.knit(0, n_loops=30, cp_max=48, per_span=4, linked_fraction=0.5)
+    _check_against_oracle(ls)
+    assert np.any(ls.exp_lk != 0)
+
+
+def test_knit_tube_patterns():
+    rows, exp = I.knit_tube(6, 3, per_span=6, pattern="uniform")
+    xyz = np.vstack(rows)
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+    real, lk = oracle.direct_sum(xyz, off, [[0, 1], [1, 2], [0, 2]])
+    assert lk.tolist() == [6, 6, 0] and exp == {(0, 1): 6, (1, 2): 6}
+    rows, exp = I.knit_tube(6, 3, per_span=6, flip={(1, 0)})
+    xyz = np.vstack(rows)
+    real, lk = oracle.direct_sum(xyz, off, [[0, 1], [1, 2]])
+    assert lk.tolist() == [exp[(0, 1)], exp[(1, 2)]] and exp[(0, 1)] == -2
+
+
+def test_knit_full_size_recipe():
+    ls = I.knit(0)
+    assert ls.n_loops == 2000
+    s = ls.sizes
+    assert s.min() >= 512 and s.max() <= 16384 and s.max() / s.min() >= 16
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    assert len(pairs) > 5000
+
+
+def test_winding_pairs_small():
+    for lk in (-3, 0, 2, 5):
+        C, D, v = I.winding_pair(11 + lk, 2500, 2600, lk, step=0.02, rho=0.15)
+        assert v == lk
+        assert abs(oracle.pair(C, D) - lk) < 1e-8
+
+
+def test_long_pairs_recipe_small():
+    ls = I.long_pairs(0, n_pairs=3, n_min=1500, n_max=2500, step=0.02, rho=0.15, dtype=np.float64)
+    _check_against_oracle(ls, ls.pairs)
+    assert len(ls.pairs) == 3
+
+
+def test_generators_are_deterministic():
+    a, b = I.chainmail(5, rows=3, cols=3), I.chainmail(5, rows=3, cols=3)
+    assert np.array_equal(a.xyz, b.xyz)
+    a, b = I.knit(5, n_loops=10, cp_max=32, per_span=2), I.knit(5, n_loops=10, cp_max=32, per_span=2)
+    assert np.array_equal(a.xyz, b.xyz)
