@@ -1,0 +1,224 @@
+"""Throughput of the direct-summation linking-number path on one MI355X.
+
+A step is one full lk_direct_sum over every candidate pair of the workload:
+loop validation, planning, the persistent Eq. 4 kernel, rounding/flagging and
+(MIXED) the FP64 refit of ambiguous pairs.  Geometry, offsets and the pair
+list are resident in HBM before the timed region; the potential link search
+runs once before it (reported separately, like the paper's PLS column).
+
+Default workload: the 4-in-1 chainmail sheet (14,000 rings x 64 segments,
+FP32, ~69k candidate pairs, 2.8e8 segment-pair terms) in the mixed-precision
+mode; the plain FP64 mode is timed on the same input and reported beside it.
+
+Prints ONE JSON line.  Options:
+  --steps K --warmup W   timed / untimed steps (default 20 / 3)
+  --config NAME          ring_grid | chainmail | knit | long_pairs
+  --mode mixed|plain     mode of the headline value (default mixed)
+  --no-cpu-baseline      skip the oracle leg
+  --gpus N               only N = 1 is supported (one GPU per process)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_TERM = 90  # arithmetic of Eq. 4 as printed in Alg. 5 (sqrt/atan2 not counted)
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
+
+WORKLOADS = {
+    "ring_grid": "64 rings x 32 segments on an 8x8 grid, FP64, 105 candidate pairs",
+    "chainmail": "4-in-1 chainmail, 14,000 rings x 64 segments, FP32",
+    "knit": "knit-like tubes, 2,000 B-spline rows of 512-16,384 segments, FP32",
+    "long_pairs": "16 pairs of long winding loops, 2^18-2^20 segments each, FP32",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="chainmail", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="mixed", choices=["mixed", "plain"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 companion run")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def time_mode(ctx, xyz, off, pairs, mode, steps, warmup, lkmod):
+    """Eager launches with the library's HIP-event ring around the main kernel
+    (same stream), bracketed by device synchronisation."""
+    import torch
+    out = ctx.direct_sum(xyz, off, pairs, mode)
+    ctx.set_option(lkmod._lib.OPT_TIMING, 0)
+    for _ in range(warmup):
+        ctx.direct_sum(xyz, off, pairs, mode, out=out)
+    ctx.set_option(lkmod._lib.OPT_TIMING, max(steps, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.direct_sum(xyz, off, pairs, mode, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stats()
+    ctx.set_option(lkmod._lib.OPT_TIMING, 0)
+    # graph replay of the same call (the production launch path), for reference
+    for _ in range(2):
+        ctx.direct_sum(xyz, off, pairs, mode, out=out)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.direct_sum(xyz, off, pairs, mode, out=out)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    real, lk, flags = [t.cpu().numpy() for t in out]
+    return {
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "graph_ms_per_step": (g1 - g0) * 1e3 / steps,
+        "kernel_ms": st["kernel_ms"],
+        "refit_kernel_ms": st["refit_kernel_ms"],
+        "refits": int(np.sum(flags.view(np.uint32) & 1)),
+        "real": real,
+        "lk": lk,
+        "flags": flags.view(np.uint32),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2106_12655_amd as lk
+    from paper_2106_12655_amd import inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()  # a real stream: the null stream cannot be captured
+    torch.cuda.set_stream(stream)
+    ls = inputs.config(args.config, args.seed)
+    ctx = lk.Context(0)
+    xyz = torch.from_numpy(ls.xyz).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if ls.pairs is not None:
+        pairs = torch.from_numpy(ls.pairs).cuda()
+    else:
+        pairs = ctx.build_pairs(xyz, off)
+    torch.cuda.synchronize()
+    pls_ms = (time.perf_counter() - t0) * 1e3
+    pr = pairs.cpu().numpy()
+    sizes = ls.sizes
+    T = int(np.sum(sizes[pr[:, 0]].astype(np.int64) * sizes[pr[:, 1]]))
+    exp = ls.expected_for(pr)
+
+    res = time_mode(ctx, xyz, off, pairs, args.mode, args.steps, args.warmup, lk)
+    other = None
+    if not args.no_plain and args.mode == "mixed":
+        other = time_mode(ctx, xyz, off, pairs, "plain", max(args.steps // 2, 1), 1, lk)
+
+    value = T / (res["ms_per_step"] * 1e-3)
+    fp64 = args.mode == "plain"
+    peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
+    achieved = FLOP_PER_TERM * T / (res["kernel_ms"] * 1e-3) / 1e12 if res["kernel_ms"] > 0 else 0.0
+    line = {
+        "metric": "segment-pair evals/s",
+        "value": value,
+        "unit": "segment-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if fp64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.config, "description": WORKLOADS[args.config],
+                   "loops": int(ls.n_loops), "pairs": int(len(pr)), "terms": T,
+                   "mode": args.mode, "seed": args.seed},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "ds_persistent (%s)" % ("FP64" if fp64 else "FP32 terms"),
+                     "kernel_ms": res["kernel_ms"], "flop_per_term": FLOP_PER_TERM},
+        "graph_ms_per_step": res["graph_ms_per_step"],
+        "pls_ms": pls_ms,
+        "refits": res["refits"],
+        "int_mismatch_vs_construction": int(np.sum(res["lk"] != exp)),
+    }
+    if other is not None:
+        line["plain_f64"] = {
+            "value": T / (other["ms_per_step"] * 1e-3),
+            "ms_per_step": other["ms_per_step"],
+            "graph_ms_per_step": other["graph_ms_per_step"],
+            "kernel_ms": other["kernel_ms"],
+            "roofline_frac_fp64": (FLOP_PER_TERM * T / (other["kernel_ms"] * 1e-3) / 1e12
+                                   / PEAK_FP64_TFLOPS) if other["kernel_ms"] > 0 else 0.0,
+            "int_mismatch_vs_mixed": int(np.sum(other["lk"] != res["lk"])),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads)
+        line.update(errs)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(ls, pr, res, other, threads):
+    """Time the FP64 oracle on the host cores over a bounded sample of pairs
+    (the whole pair list when it is small enough), and compare the GPU results
+    on that sample with it."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16) if threads <= 0 else threads
+    sizes = ls.sizes.astype(np.int64)
+    cost = sizes[pr[:, 0]] * sizes[pr[:, 1]]
+    budget = 4.0e9  # terms: ~10-30 s on 16 host cores
+    if cost.sum() <= budget:
+        idx = np.arange(len(pr))
+        sample = "all %d pairs" % len(pr)
+    else:
+        rng = np.random.default_rng(0)
+        order = rng.permutation(len(pr))
+        keep = order[np.cumsum(cost[order]) <= budget]
+        idx = np.sort(keep)
+        sample = "%d of %d pairs (seeded random, %.2e of %.2e terms)" % (
+            len(idx), len(pr), cost[idx].sum(), cost.sum())
+    t0 = time.perf_counter()
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pr[idx], nthreads=cores)
+    dt = time.perf_counter() - t0
+    terms = int(cost[idx].sum())
+    errs = {
+        "err_vs_oracle": {
+            "sample": sample,
+            "mixed_max": float(np.max(np.abs(res["real"][idx] - oreal))) if len(idx) else 0.0,
+            "mixed_p99": float(np.quantile(np.abs(res["real"][idx] - oreal), 0.99)) if len(idx) else 0.0,
+            "int_mismatch": int(np.sum(res["lk"][idx] != olk)),
+        }
+    }
+    if other is not None and len(idx):
+        errs["err_vs_oracle"]["plain_max"] = float(np.max(np.abs(other["real"][idx] - oreal)))
+        errs["err_vs_oracle"]["plain_int_mismatch"] = int(np.sum(other["lk"][idx] != olk))
+    cpu = {"value": terms / dt, "unit": "segment-pairs/s", "cores": cores, "kind": "oracle",
+           "sample": sample, "seconds": dt, "terms": terms}
+    return cpu, errs
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * lk.h -- C ABI of the MI355X direct-summation linking-number library (liblk.so).
+ *
+ * The library evaluates, for every candidate pair of closed polylines, the
+ * exact polyline form of the Gauss linking integral: the sum over all
+ * segment pairs of the signed-solid-angle term of Eq. 4 (Sec. 2.1, "Direct
+ * Summation Methods"; the double sum of Eq. 5 / Alg. 5, Sec. 3.4.2), reduces it
+ * to one real number per loop pair and rounds it to the integer linking
+ * number.  Around that hot path it offers the potential link search of
+ * Alg. 2 (Sec. 3.2) and the before/after comparison with early exit that the
+ * method overview (Sec. 3.1, "Fast Verification") describes.
+ *
+ * Conventions shared by every call
+ *   - Geometry: xyz is a contiguous row-major array of V vertices x 3
+ *     coordinates (float32 or float64, see lk_dtype).  Loop l owns vertices
+ *     loop_offsets[l] .. loop_offsets[l+1]-1 (int64, n_loops+1 entries,
+ *     non-decreasing).  A loop of n vertices is closed: segment s joins vertex
+ *     s to vertex (s+1) mod n; the first vertex is not repeated.
+ *   - Pairs: int32 [n][2] row-major loop indices.  For pair (i, j) loop i plays
+ *     gamma_1 of Eq. 4 (vertices l, index j) and loop j plays gamma_2
+ *     (vertices k, index i).  The linking number is symmetric, so the order
+ *     only fixes which loop is tiled.
+ *   - Memory: every array argument is a DEVICE pointer on the context's device
+ *     unless marked (host).  The caller owns all of them; the library never
+ *     frees or keeps them after the call returns.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Work is enqueued on it; calls return once the work is enqueued
+ *     unless documented to synchronise.  Calls on one context must not overlap
+ *     (one context per host thread, or serialise).
+ *   - Errors: every call returns lk_status.  A non-OK status leaves outputs
+ *     unspecified and sets a message readable with lk_last_error.  Problems of
+ *     individual pairs (bad indices, degenerate loops, non-finite sums) are
+ *     never host errors: they are reported per pair in the flags output.
+ */
+#ifndef LK_H_
+#define LK_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lk_ctx lk_ctx;
+
+typedef enum {
+  LK_OK = 0,
+  LK_EINVAL = -1,    /* bad argument (null pointer, negative size, unknown enum) */
+  LK_ENOMEM = -2,    /* device or host allocation failed */
+  LK_EDEVICE = -3,   /* a HIP runtime call failed */
+  LK_ECAPACITY = -4, /* output buffer too small; the required size is returned */
+  LK_EBUSY = -5,     /* resource in use (server slot table full, stream capturing) */
+  LK_ENOTFOUND = -6  /* unknown request or handle */
+} lk_status;
+
+typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
+
+/* PLAIN_F64: every term, sum and reduction in FP64 (FP32 input is promoted
+ * exactly).  MIXED: terms in FP32, per-thread sums in FP32 over at most one
+ * LDS tile, everything from the per-tile partial upwards in FP64, and every
+ * pair whose |value - round(value)| exceeds the refit threshold (default 0.05)
+ * recomputed entirely in FP64 from the caller's input. */
+typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1 } lk_mode;
+
+/* Per-pair flags (bit set). */
+enum {
+  LK_FLAG_REFIT = 1u,     /* value came from the FP64 refit (MIXED only) */
+  LK_FLAG_AMBIGUOUS = 2u, /* |value - round(value)| > threshold in FP64 too */
+  LK_FLAG_NONFINITE = 4u, /* NaN/Inf in the sum (degenerate or intersecting input) */
+  LK_FLAG_BADPAIR = 8u,   /* i == j or an index outside [0, n_loops) */
+  LK_FLAG_BADLOOP = 16u   /* a loop has < 3 vertices, a non-finite coordinate, or a
+                             segment shorter than eps * xi (Alg. 3 zero-length test,
+                             xi = mean |coordinate| over the call's vertices,
+                             eps = machine epsilon of the input dtype) */
+};
+
+/* Integer reported for pairs whose value is not finite or whose indices are bad. */
+#define LK_INT_INVALID INT32_MIN
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device` (owns workspace, the kernel
+ * configuration table and the captured-graph cache).  *out receives the
+ * handle.  Returns LK_EDEVICE if the device cannot be used. */
+lk_status lk_create(lk_ctx** out, int device);
+
+/* Destroy a context (synchronises its device first).  NULL is ignored. */
+void lk_destroy(lk_ctx* ctx);
+
+/* Message for the last non-OK status returned on this context ("" if none).
+ * The pointer stays valid until the next call on the context. */
+const char* lk_last_error(const lk_ctx* ctx);
+
+/* ---------------------------------------------------- potential link search */
+/* Alg. 2 (Sec. 3.2): every loop pair i < j whose closed axis-aligned boxes
+ * (vertex min/max per loop) overlap on all three axes, in lexicographic order,
+ * written to pairs_out [capacity][2].  Synchronises the stream (the count is
+ * needed on the host).  *n_pairs (host) receives the number of pairs; if it
+ * exceeds `capacity` nothing beyond capacity is written and LK_ECAPACITY is
+ * returned with *n_pairs = required size.  Loops with no vertex get no pair. */
+lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* loop_offsets,
+                         int32_t n_loops, int32_t* pairs_out, int64_t capacity,
+                         int64_t* n_pairs /* host */, void* stream);
+
+/* ------------------------------------------------------------ direct sum */
+/* For each pair p = (i, j):
+ *   lk_real[p] = sum over segments j' of loop i and i' of loop j of the Eq. 4
+ *                term (FP64 result),
+ *   lk_int[p]  = round-half-away-from-zero(lk_real[p]), or LK_INT_INVALID,
+ *   flags[p]   = LK_FLAG_* bits.
+ * lk_real/lk_int/flags are [n_pairs] device arrays; flags may be NULL.
+ * Asynchronous.  The sequence of kernels is captured once per argument set
+ * into a HIP graph and replayed on later identical calls (see LK_OPT_GRAPH).
+ * Results are bitwise reproducible for identical inputs and configuration,
+ * independent of what else runs on the device. */
+lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* loop_offsets,
+                        int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                        double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream);
+
+/* --------------------------------------------------------------- verify */
+/* Compare the current sparse linking matrix (pairs, lk)[n] with the expected
+ * one (exp_pairs, exp_lk)[n_exp]; both pair lists sorted lexicographically
+ * with i < j and no duplicates (Sec. 3.1, "Fast Verification").  A pair only
+ * in the current list is expected to be 0; a pair only in the expected list
+ * counts as 0 now (its boxes separated), so it is a mismatch when its
+ * expected value is non-zero.  Synchronises.  *n_mismatch (host) receives the
+ * number of mismatches; the first min(count, cap) of them in pair order are
+ * written to mismatches [cap][4] as (i, j, got, expected).  With
+ * early_exit != 0 the call stops at the first mismatch in pair order:
+ * *n_mismatch is 0 or 1 and at most that record is written. */
+lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_t n,
+                    const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp, int early_exit,
+                    int64_t* n_mismatch /* host */, int32_t* mismatches, int64_t cap, void* stream);
+
+/* ------------------------------------------------------ options and stats */
+enum {
+  LK_OPT_REFIT_THRESHOLD_PPM = 1, /* refit threshold in millionths (default 50000 = 0.05) */
+  LK_OPT_GRAPH = 2,               /* 1 = capture/replay HIP graphs (default), 0 = eager */
+  LK_OPT_TIMING = 3,              /* n > 0: time the kernels of the next calls with HIP events
+                                     (eager launches, a ring of n calls); 0 = off.  Setting it
+                                     synchronises the device and clears the ring. */
+  LK_OPT_TILE_A = 4,              /* FP32 LDS tile of loop A in vertices (0 = tuned) */
+  LK_OPT_CHUNK_A = 5,             /* vertices of A per work item (0 = tuned) */
+  LK_OPT_WAVES_PER_CU = 6,        /* persistent waves per compute unit (0 = occupancy) */
+  LK_OPT_ATAN = 7                 /* FP32 arctangent: 0 = own minimax, 1 = HIP atan2f */
+};
+
+/* Set an option; returns LK_EINVAL for an unknown key or a bad value. */
+lk_status lk_set_option(lk_ctx* ctx, int key, int64_t value);
+
+typedef struct {
+  int64_t refits;         /* pairs recomputed in FP64 by the last MIXED call */
+  double kernel_ms;       /* mean main-kernel time over the timed calls in the ring */
+  double refit_kernel_ms; /* mean refit-kernel time over the same calls (MIXED) */
+  int32_t timed_calls;    /* number of calls those means cover */
+  int32_t graph_replayed; /* 1 if the last call replayed a captured graph */
+  int32_t tile_a, chunk_a, waves_per_cu, atan_form; /* configuration used */
+} lk_stats;
+
+/* Statistics of the last lk_direct_sum on this context.  Reading refits and
+ * the timings synchronises the stream of that call; the timed calls must all
+ * have been issued on that stream. */
+lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out /* host */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LK_H_ */

@@ -1,0 +1,180 @@
+"""MI355X-native direct summation of the Gauss linking integral.
+
+Python face of liblk.so (include/lk.h).  Every step of the computation runs in
+the HIP kernels of ``csrc/``; this module only marshals torch tensors (device
+memory and the current stream) into the C ABI.  It has no CPU fallback: without
+a built library or a GPU every call raises.
+
+Functions follow the paper's pipeline (Qu & James 2021, Alg. 1):
+``build_pairs`` (potential link search, Alg. 2), ``direct_sum`` (stage 3 by
+direct summation of Eq. 4, Alg. 5) and ``verify`` (the before/after comparison
+with optional early exit, Sec. 3.1).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (FLAG_AMBIGUOUS, FLAG_BADLOOP, FLAG_BADPAIR, FLAG_NONFINITE, FLAG_REFIT,
+                   INT_INVALID, LkError)
+
+__all__ = ["Context", "build_pairs", "direct_sum", "verify", "LkError", "FLAG_REFIT",
+           "FLAG_AMBIGUOUS", "FLAG_NONFINITE", "FLAG_BADPAIR", "FLAG_BADLOOP", "INT_INVALID"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return _lib.F32
+    if t.dtype == torch.float64:
+        return _lib.F64
+    raise TypeError("xyz must be float32 or float64, got %s" % t.dtype)
+
+
+class Context:
+    """One lk_ctx on a HIP device (workspace, graph cache, options)."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.lib = _lib.load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib, None, self.lib.lk_create(ctypes.byref(h), self.device))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        return _lib.check(self.lib, self.h, st)
+
+    def _dev(self, t, dtype=None, name="tensor"):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device.type != "cuda" or (t.device.index or 0) != self.device:
+            raise ValueError("%s must live on cuda:%d" % (name, self.device))
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return t
+
+    def set_option(self, key: int, value: int):
+        self._check(self.lib.lk_set_option(self.h, int(key), int(value)))
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        self._check(self.lib.lk_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    # ------------------------------------------------------------ the calls
+    def build_pairs(self, xyz, offsets, capacity: int | None = None):
+        """Alg. 2: all i<j with overlapping closed AABBs, as int32 [P, 2] on the device."""
+        torch = _torch()
+        self._dev(xyz, None, "xyz")
+        self._dev(offsets, torch.int64, "offsets")
+        L = offsets.numel() - 1
+        n = ctypes.c_int64(0)
+        cap = int(capacity) if capacity is not None else 0
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=xyz.device)
+        st = self.lib.lk_build_pairs(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), L,
+                                     _ptr(out) if cap > 0 else ctypes.c_void_p(0), cap,
+                                     ctypes.byref(n), _stream(self.device))
+        if st == _lib.ECAPACITY and capacity is None:
+            cap = int(n.value)
+            out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=xyz.device)
+            st = self.lib.lk_build_pairs(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), L,
+                                         _ptr(out), cap, ctypes.byref(n), _stream(self.device))
+        self._check(st)
+        return out[: int(n.value)]
+
+    def direct_sum(self, xyz, offsets, pairs, mode: str = "mixed", out=None):
+        """Eq. 4 summed over every segment pair of every loop pair.
+
+        Returns ``(lk_real float64[P], lk_int int32[P], flags int32[P])`` on the
+        device (flags hold the LK_FLAG_* bits).  ``mode`` is ``"mixed"`` (FP32
+        terms, FP64 pair sums and FP64 refit of ambiguous pairs) or ``"plain"``
+        (FP64 throughout).  ``out``: optional preallocated output triple.
+        """
+        torch = _torch()
+        self._dev(xyz, None, "xyz")
+        self._dev(offsets, torch.int64, "offsets")
+        self._dev(pairs, torch.int32, "pairs")
+        P = pairs.shape[0] if pairs.dim() == 2 else 0
+        if pairs.numel() and (pairs.dim() != 2 or pairs.shape[1] != 2):
+            raise ValueError("pairs must be [P, 2]")
+        if out is None:
+            real = torch.empty(P, dtype=torch.float64, device=xyz.device)
+            lk = torch.empty(P, dtype=torch.int32, device=xyz.device)
+            flags = torch.empty(P, dtype=torch.int32, device=xyz.device)
+        else:
+            real, lk, flags = out
+        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        self._check(self.lib.lk_direct_sum(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets),
+                                           offsets.numel() - 1, _ptr(pairs), P, m, _ptr(real),
+                                           _ptr(lk), _ptr(flags), _stream(self.device)))
+        return real, lk, flags
+
+    def verify(self, pairs, lk, exp_pairs, exp_lk, early_exit: bool = False, cap: int = 1024):
+        """Compare (pairs, lk) with (exp_pairs, exp_lk); returns
+        ``(n_mismatch, records int32 [k, 4] on the device)`` with records
+        ``(i, j, got, expected)`` in pair order."""
+        torch = _torch()
+        for t, nme in ((pairs, "pairs"), (lk, "lk"), (exp_pairs, "exp_pairs"), (exp_lk, "exp_lk")):
+            self._dev(t, torch.int32, nme)
+        n = ctypes.c_int64(0)
+        rec = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=lk.device)
+        self._check(self.lib.lk_verify(self.h, _ptr(pairs), _ptr(lk), lk.numel(), _ptr(exp_pairs),
+                                       _ptr(exp_lk), exp_lk.numel(), 1 if early_exit else 0,
+                                       ctypes.byref(n), _ptr(rec) if cap > 0 else ctypes.c_void_p(0),
+                                       int(cap), _stream(self.device)))
+        k = min(int(n.value), int(cap))
+        return int(n.value), rec[:k]
+
+
+_default: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    """The per-device default context."""
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def build_pairs(xyz, offsets, capacity=None):
+    return context(xyz.device.index or 0).build_pairs(xyz, offsets, capacity)
+
+
+def direct_sum(xyz, offsets, pairs, mode="mixed", out=None):
+    return context(xyz.device.index or 0).direct_sum(xyz, offsets, pairs, mode, out)
+
+
+def verify(pairs, lk, exp_pairs, exp_lk, early_exit=False, cap=1024):
+    return context(lk.device.index or 0).verify(pairs, lk, exp_pairs, exp_lk, early_exit, cap)

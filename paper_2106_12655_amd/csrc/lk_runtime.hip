@@ -1,0 +1,484 @@
+// lk_runtime.hip -- the C ABI of liblk.so (include/lk.h): contexts, workspace,
+// argument checking, the kernel sequence of each call and its HIP-graph cache.
+//
+// lk_direct_sum enqueues, on the caller's stream:
+//   loop validation (xi, per-loop flags) -> plan (items per pair) -> scan ->
+//   persistent direct-sum kernel -> finalize (round, flag, refit list)
+//   [MIXED only: plan(refit list) -> scan -> FP64 direct-sum kernel -> finalize]
+// Every launch has a host-known shape; data-dependent counts live in device
+// memory.  The first call with a given argument set is captured into a HIP
+// graph (when the stream allows capture) and replayed by later identical calls.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lk.h"
+#include "lk_internal.h"
+
+namespace {
+
+// Device buffer that only grows; growing invalidates captured graphs.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+using GraphKey = std::tuple<const void*, int, const void*, int32_t, const void*, int64_t, int,
+                            void*, void*, void*, int, int, int, int, int64_t>;
+
+}  // namespace
+
+struct lk_ctx {
+  int device = 0;
+  int n_cu = 0;
+  std::string err;
+  // options
+  double refit_thr = 0.05;
+  bool use_graph = true;
+  bool timing = false;
+  int opt_tile = 0, opt_chunk = 0, opt_waves = 0, opt_atan = 0;
+  // workspace
+  DevBuf loop_flags, xi, counts, prefix, counter, acc, flags, refit_list, refit_n;
+  DevBuf boxes, vcounts, vprefix;
+  uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
+  // graphs
+  struct Cached {
+    hipGraphExec_t exec = nullptr;
+    uint64_t epoch = 0;
+  };
+  std::map<GraphKey, Cached> graphs;
+  // timing: a ring of event quadruples (main start/stop, refit start/stop),
+  // one per timed call, so a run of calls can be averaged without syncing
+  std::vector<hipEvent_t> ring;
+  int ring_pos = 0, ring_count = 0;
+  lk_stats stats;
+  hipStream_t last_stream = nullptr;
+  bool last_mixed = false;
+  bool last_timed = false;
+
+  lk_status fail(lk_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return st;
+  }
+};
+
+#define LK_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ctx->fail(LK_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+namespace {
+
+lk_status ensure(lk_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return LK_OK;
+  size_t want = bytes + bytes / 4;
+  if (b.p) {
+    // buffers may be referenced by work still in flight on any stream
+    if (hipDeviceSynchronize() != hipSuccess) return ctx->fail(LK_EDEVICE, "sync before realloc");
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return ctx->fail(LK_ENOMEM, "hipMalloc(%zu) failed", want);
+  }
+  b.bytes = want;
+  ctx->ws_epoch++;
+  return LK_OK;
+}
+
+int default_tile(bool f64) { return f64 ? 256 : 512; }
+int default_chunk(bool f64) { return f64 ? 2048 : 4096; }
+
+struct Plan {
+  bool in_f64;
+  bool mixed;
+  int tile, chunk, grid, grid64, atan_form;
+};
+
+// Enqueue the whole direct-sum sequence (no graph logic here).
+lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const int64_t* off,
+                             int32_t n_loops, const int32_t* pairs, int64_t n_pairs,
+                             double* lk_real, int32_t* lk_int, uint32_t* flags, hipStream_t s,
+                             hipEvent_t* ev /* 4 events or NULL */) {
+  const bool timed = ev != nullptr;
+  using namespace lk;
+  uint32_t* lf = (uint32_t*)ctx->loop_flags.p;
+  double* xi = (double*)ctx->xi.p;  // [kXiBlocks] partials followed by xi
+  DsArgs A{};
+  A.xyz = xyz;
+  A.off = off;
+  A.pairs = pairs;
+  A.list = nullptr;
+  A.n_list_dev = nullptr;
+  A.n_list = n_pairs;
+  A.prefix = (const int64_t*)ctx->prefix.p;
+  A.counter = (unsigned long long*)ctx->counter.p;
+  A.acc = (unsigned long long*)ctx->acc.p;
+  A.flags = flags;
+  A.tile = P.tile;
+  A.chunk = P.chunk;
+  int64_t* counts = (int64_t*)ctx->counts.p;
+  int64_t* prefix = (int64_t*)ctx->prefix.p;
+  int32_t* rlist = (int32_t*)ctx->refit_list.p;
+  int32_t* rn = (int32_t*)ctx->refit_n.p;
+
+  LK_HIP(launch_loop_flags(xyz, P.in_f64, off, n_loops, xi, xi + kXiBlocks, lf, s));
+  LK_HIP(launch_plan(A, n_loops, lf, counts, false, s));
+  LK_HIP(launch_scan_zero(counts, nullptr, n_pairs, prefix, A.counter, rn, s));
+  if (timed) LK_HIP(hipEventRecord(ev[0], s));
+  LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.grid : P.grid64, s));
+  if (timed) LK_HIP(hipEventRecord(ev[1], s));
+  LK_HIP(launch_finalize(A, ctx->refit_thr, lk_real, lk_int, P.mixed ? rlist : nullptr,
+                         P.mixed ? rn : nullptr, false, s));
+  if (P.mixed) {
+    DsArgs R = A;
+    R.list = rlist;
+    R.n_list_dev = rn;
+    R.tile = default_tile(true);
+    R.chunk = default_chunk(true);
+    LK_HIP(launch_plan(R, n_loops, lf, counts, true, s));
+    LK_HIP(launch_scan(counts, rn, n_pairs, prefix, R.counter, s));
+    if (timed) LK_HIP(hipEventRecord(ev[2], s));
+    LK_HIP(launch_direct_sum(R, P.in_f64, true, 0, P.grid64, s));
+    if (timed) LK_HIP(hipEventRecord(ev[3], s));
+    LK_HIP(launch_finalize(R, ctx->refit_thr, lk_real, lk_int, nullptr, nullptr, true, s));
+  }
+  return LK_OK;
+}
+
+bool check_dtype(int d) { return d == LK_F32 || d == LK_F64; }
+
+lk_status set_device(lk_ctx* ctx) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return ctx->fail(LK_EDEVICE, "hipGetDevice failed");
+  if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+    return ctx->fail(LK_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  return LK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lk_status lk_create(lk_ctx** out, int device) {
+  if (!out) return LK_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LK_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return LK_EDEVICE;
+  lk_ctx* ctx = new (std::nothrow) lk_ctx();
+  if (!ctx) return LK_ENOMEM;
+  ctx->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete ctx;
+    return LK_EDEVICE;
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  memset(&ctx->stats, 0, sizeof(ctx->stats));
+  *out = ctx;
+  return LK_OK;
+}
+
+void lk_destroy(lk_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& kv : ctx->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  DevBuf* bufs[] = {&ctx->loop_flags, &ctx->xi,      &ctx->counts,     &ctx->prefix,
+                    &ctx->counter,    &ctx->acc,     &ctx->flags,      &ctx->refit_list,
+                    &ctx->refit_n,    &ctx->boxes,   &ctx->vcounts,    &ctx->vprefix};
+  for (DevBuf* b : bufs)
+    if (b->p) hipFree(b->p);
+  for (auto& e : ctx->ring)
+    if (e) hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* lk_last_error(const lk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
+  if (!ctx) return LK_EINVAL;
+  switch (key) {
+    case LK_OPT_REFIT_THRESHOLD_PPM:
+      if (v < 0 || v > 500000) return ctx->fail(LK_EINVAL, "refit threshold out of [0, 0.5]");
+      ctx->refit_thr = (double)v * 1e-6;
+      break;
+    case LK_OPT_GRAPH:
+      ctx->use_graph = v != 0;
+      break;
+    case LK_OPT_TIMING: {
+      if (v < 0 || v > 4096) return ctx->fail(LK_EINVAL, "timing ring must be in [0, 4096]");
+      if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(LK_EDEVICE, "hipSetDevice");
+      hipDeviceSynchronize();
+      for (auto& e : ctx->ring)
+        if (e) hipEventDestroy(e);
+      ctx->ring.assign(4 * (size_t)v, nullptr);
+      for (auto& e : ctx->ring)
+        if (hipEventCreate(&e) != hipSuccess) return ctx->fail(LK_EDEVICE, "hipEventCreate");
+      ctx->ring_pos = ctx->ring_count = 0;
+      ctx->timing = v != 0;
+      break;
+    }
+    case LK_OPT_TILE_A:
+      if (v != 0 && (v < 16 || v > lk::kMaxTileF32 || (v & 15)))
+        return ctx->fail(LK_EINVAL, "tile must be 0 or a multiple of 16 in [16, %d]",
+                         lk::kMaxTileF32);
+      ctx->opt_tile = (int)v;
+      break;
+    case LK_OPT_CHUNK_A:
+      if (v != 0 && (v < 16 || v > (1 << 24)))
+        return ctx->fail(LK_EINVAL, "chunk must be 0 or in [16, 2^24]");
+      ctx->opt_chunk = (int)v;
+      break;
+    case LK_OPT_WAVES_PER_CU:
+      if (v < 0 || v > 64) return ctx->fail(LK_EINVAL, "waves per CU must be in [0, 64]");
+      ctx->opt_waves = (int)v;
+      break;
+    case LK_OPT_ATAN:
+      if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "atan form must be 0 or 1");
+      ctx->opt_atan = (int)v;
+      break;
+    default:
+      return ctx->fail(LK_EINVAL, "unknown option %d", key);
+  }
+  // configuration is baked into captured graphs
+  for (auto& kv : ctx->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  ctx->graphs.clear();
+  return LK_OK;
+}
+
+lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                        int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                        double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED) return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
+  if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
+  if (n_pairs < 0) return ctx->fail(LK_EINVAL, "n_pairs must be >= 0");
+  if (n_pairs > 0x7fffffffLL) return ctx->fail(LK_EINVAL, "n_pairs exceeds int32 range");
+  if (!xyz || !off || (n_pairs > 0 && (!pairs || !lk_real || !lk_int)))
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  ctx->stats = lk_stats{};
+  if (n_pairs == 0) return LK_OK;
+
+  const bool in_f64 = dtype == LK_F64;
+  const bool mixed = mode == LK_MIXED;
+  Plan P;
+  P.in_f64 = in_f64;
+  P.mixed = mixed;
+  P.atan_form = ctx->opt_atan;
+  P.tile = mixed ? (ctx->opt_tile ? ctx->opt_tile : default_tile(false)) : default_tile(true);
+  P.chunk = mixed ? (ctx->opt_chunk ? ctx->opt_chunk : default_chunk(false)) : default_chunk(true);
+  if (!mixed && ctx->opt_chunk) P.chunk = ctx->opt_chunk;
+  if (P.chunk % P.tile) P.chunk = ((P.chunk + P.tile - 1) / P.tile) * P.tile;
+  P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.tile, ctx->n_cu, ctx->opt_waves);
+  P.grid64 = lk::direct_sum_grid(in_f64, true, 0, default_tile(true), ctx->n_cu, ctx->opt_waves);
+
+  // workspace
+  if ((st = ensure(ctx, ctx->loop_flags, 4 * (size_t)n_loops)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kXiBlocks + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->counts, 8 * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->counter, 8)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->acc, 16 * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->refit_list, 4 * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->refit_n, 4)) != LK_OK) return st;
+  if (!flags) {
+    if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
+    flags = (uint32_t*)ctx->flags.p;
+  }
+
+  ctx->stats.tile_a = P.tile;
+  ctx->stats.chunk_a = P.chunk;
+  ctx->stats.waves_per_cu = P.grid / (ctx->n_cu > 0 ? ctx->n_cu : 1);
+  ctx->stats.atan_form = P.atan_form;
+  ctx->last_stream = s;
+  ctx->last_mixed = mixed;
+  ctx->last_timed = false;
+
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (s) {
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+  }
+  const bool timed = ctx->timing;
+  const bool graph_ok = ctx->use_graph && !timed && s != nullptr && cap == hipStreamCaptureStatusNone;
+  if (!graph_ok) {
+    hipEvent_t* ev = nullptr;
+    if (timed) {
+      const int slots = (int)(ctx->ring.size() / 4);
+      ev = &ctx->ring[4 * (size_t)(ctx->ring_pos % slots)];
+    }
+    st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
+                            ev);
+    if (timed && st == LK_OK) {
+      const int slots = (int)(ctx->ring.size() / 4);
+      ctx->ring_pos = (ctx->ring_pos + 1) % slots;
+      if (ctx->ring_count < slots) ctx->ring_count++;
+      ctx->last_timed = true;
+    }
+    return st;
+  }
+  GraphKey key{xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int, flags,
+               P.tile, P.chunk, P.grid, P.atan_form, (int64_t)(ctx->refit_thr * 1e9)};
+  auto it = ctx->graphs.find(key);
+  if (it != ctx->graphs.end() && it->second.epoch == ctx->ws_epoch && it->second.exec) {
+    LK_HIP(hipGraphLaunch(it->second.exec, s));
+    ctx->stats.graph_replayed = 1;
+    return LK_OK;
+  }
+  if (it != ctx->graphs.end()) {
+    if (it->second.exec) hipGraphExecDestroy(it->second.exec);
+    ctx->graphs.erase(it);
+  }
+  LK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
+                          nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(s, &g);
+  if (st != LK_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (ce != hipSuccess || !g) return ctx->fail(LK_EDEVICE, "graph capture failed: %s",
+                                               hipGetErrorString(ce));
+  hipGraphExec_t ex = nullptr;
+  hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ie != hipSuccess) return ctx->fail(LK_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
+  if (ctx->graphs.size() > 64) {
+    for (auto& kv : ctx->graphs)
+      if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    ctx->graphs.clear();
+  }
+  ctx->graphs[key] = {ex, ctx->ws_epoch};
+  LK_HIP(hipGraphLaunch(ex, s));
+  return LK_OK;
+}
+
+lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
+  if (!ctx || !out) return LK_EINVAL;
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  if (ctx->last_mixed && ctx->refit_n.p) {
+    LK_HIP(hipStreamSynchronize(ctx->last_stream));
+    int32_t rn = 0;
+    LK_HIP(hipMemcpy(&rn, ctx->refit_n.p, 4, hipMemcpyDeviceToHost));
+    ctx->stats.refits = rn;
+  }
+  if (ctx->timing && ctx->ring_count > 0) {
+    LK_HIP(hipStreamSynchronize(ctx->last_stream));
+    double sum = 0.0, rsum = 0.0;
+    for (int k = 0; k < ctx->ring_count; ++k) {
+      float ms = 0.f;
+      LK_HIP(hipEventElapsedTime(&ms, ctx->ring[4 * k], ctx->ring[4 * k + 1]));
+      sum += ms;
+      if (ctx->last_mixed) {
+        LK_HIP(hipEventElapsedTime(&ms, ctx->ring[4 * k + 2], ctx->ring[4 * k + 3]));
+        rsum += ms;
+      }
+    }
+    ctx->stats.kernel_ms = sum / ctx->ring_count;
+    ctx->stats.refit_kernel_ms = rsum / ctx->ring_count;
+    ctx->stats.timed_calls = ctx->ring_count;
+  }
+  *out = ctx->stats;
+  return LK_OK;
+}
+
+lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                         int32_t n_loops, int32_t* pairs_out, int64_t capacity, int64_t* n_pairs,
+                         void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
+  if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
+  if (capacity < 0) return ctx->fail(LK_EINVAL, "capacity must be >= 0");
+  if (!xyz || !off || !n_pairs || (capacity > 0 && !pairs_out))
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure(ctx, ctx->boxes, 48 * (size_t)n_loops)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->vcounts, 8 * (size_t)n_loops)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->vprefix, 8 * (size_t)(n_loops + 1))) != LK_OK) return st;
+  double* boxes = (double*)ctx->boxes.p;
+  int64_t* cnt = (int64_t*)ctx->vcounts.p;
+  int64_t* pre = (int64_t*)ctx->vprefix.p;
+  LK_HIP(lk::launch_boxes(xyz, dtype == LK_F64, off, n_loops, boxes, s));
+  LK_HIP(lk::launch_pair_count(boxes, n_loops, cnt, s));
+  LK_HIP(lk::launch_scan(cnt, nullptr, n_loops, pre, nullptr, s));
+  int64_t total = 0;
+  LK_HIP(hipMemcpyAsync(&total, pre + n_loops, 8, hipMemcpyDeviceToHost, s));
+  LK_HIP(hipStreamSynchronize(s));
+  *n_pairs = total;
+  if (total > 0 && capacity > 0) {
+    LK_HIP(lk::launch_pair_fill(boxes, n_loops, pre, pairs_out, capacity, s));
+    LK_HIP(hipStreamSynchronize(s));
+  }
+  if (total > capacity)
+    return ctx->fail(LK_ECAPACITY, "%lld pairs do not fit capacity %lld", (long long)total,
+                     (long long)capacity);
+  return LK_OK;
+}
+
+lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_t n,
+                    const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp, int early_exit,
+                    int64_t* n_mismatch, int32_t* mismatches, int64_t cap, void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (n < 0 || n_exp < 0 || cap < 0) return ctx->fail(LK_EINVAL, "negative size");
+  if (!n_mismatch || (n > 0 && (!pairs || !lk)) || (n_exp > 0 && (!exp_pairs || !exp_lk)) ||
+      (cap > 0 && !mismatches))
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  *n_mismatch = 0;
+  const int64_t m = n + n_exp;
+  if (m == 0) return LK_OK;
+  if ((st = ensure(ctx, ctx->vcounts, 8 * (size_t)m)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->vprefix, 8 * (size_t)(m + 1))) != LK_OK) return st;
+  int64_t* flag = (int64_t*)ctx->vcounts.p;
+  int64_t* pre = (int64_t*)ctx->vprefix.p;
+  LK_HIP(lk::launch_verify(pairs, lk, n, exp_pairs, exp_lk, n_exp, flag, s));
+  LK_HIP(lk::launch_scan(flag, nullptr, m, pre, nullptr, s));
+  int64_t total = 0;
+  LK_HIP(hipMemcpyAsync(&total, pre + m, 8, hipMemcpyDeviceToHost, s));
+  LK_HIP(hipStreamSynchronize(s));
+  int64_t c = cap;
+  if (early_exit) {
+    total = total > 0 ? 1 : 0;
+    c = cap < 1 ? cap : 1;
+  }
+  *n_mismatch = total;
+  if (total > 0 && c > 0) {
+    LK_HIP(lk::launch_verify_scatter(pairs, lk, n, exp_pairs, exp_lk, n_exp, pre, mismatches, c, s));
+    LK_HIP(hipStreamSynchronize(s));
+  }
+  return LK_OK;
+}
+
+}  // extern "C"

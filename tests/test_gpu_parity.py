@@ -1,0 +1,251 @@
+"""Parity of the HIP direct sum (through the C ABI) with the FP64 oracle.
+
+Bars: integers bit-exact; plain-FP64 reals within 1e-6 of the oracle (in
+practice ~1e-12); mixed-precision reals within MIXED_TOL (derived in the
+design notes from FP32 term rounding, about 2^-22 relative per term, summed
+over at most a few thousand terms of magnitude <= 1/2 per lane and tile).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12655_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+PLAIN_TOL = 1e-6
+MIXED_TOL = 1e-4
+
+
+def _dev(ls):
+    import torch
+    xyz = torch.from_numpy(np.ascontiguousarray(ls.xyz)).cuda()
+    off = torch.from_numpy(np.ascontiguousarray(ls.offsets)).cuda()
+    return xyz, off
+
+
+def _run(ctx, ls, pairs, mode):
+    import torch
+    xyz, off = _dev(ls)
+    pr = torch.from_numpy(np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))).cuda()
+    real, lk, flags = ctx.direct_sum(xyz, off, pr, mode)
+    torch.cuda.synchronize()
+    return real.cpu().numpy(), lk.cpu().numpy(), flags.cpu().numpy().view(np.uint32)
+
+
+def _smooth_loop(rng, n, centre, modes=3):
+    t = 2 * np.pi * np.arange(n) / n
+    P = np.zeros((n, 3))
+    for k in range(1, modes + 1):
+        a = rng.standard_normal((2, 3)) / k
+        P += np.outer(np.cos(k * t), a[0]) + np.outer(np.sin(k * t), a[1])
+    return P + centre
+
+
+def _compare(ls, pairs, real, lk, tol, label):
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    err = np.abs(real - oreal)
+    print("%s: pairs %d max |err| %.3e" % (label, len(pairs), err.max()), flush=True)
+    assert np.array_equal(lk, olk), label
+    assert err.max() <= tol, label
+    return err.max()
+
+
+def test_ring_grid_both_modes(ctx):
+    ls = I.ring_grid(0)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    exp = ls.expected_for(pairs)
+    for mode, tol in (("plain", PLAIN_TOL), ("mixed", MIXED_TOL)):
+        real, lk, flags = _run(ctx, ls, pairs, mode)
+        _compare(ls, pairs, real, lk, tol, "ring_grid " + mode)
+        assert np.array_equal(lk, exp)
+        assert np.all(flags == 0)
+
+
+def test_closed_form_links(ctx):
+    for ls in (I.hopf(64), I.torus_link(2, 3, 400), I.torus_link(3, -2, 256, dtype=np.float32)):
+        for mode, tol in (("plain", PLAIN_TOL), ("mixed", MIXED_TOL)):
+            real, lk, flags = _run(ctx, ls, ls.pairs, mode)
+            _compare(ls, ls.pairs, real, lk, tol, ls.name + " " + mode)
+            assert lk[0] == ls.exp_lk[0]
+
+
+def test_uneven_sizes_ragged_tails(ctx):
+    # sizes straddle the 64-segment lane block, the LDS tiles and the A chunk
+    sizes = [3, 5, 31, 63, 64, 65, 127, 129, 300, 511, 513, 1025, 4097, 5000]
+    rng = np.random.default_rng(7)
+    loops = [_smooth_loop(rng, n, rng.uniform(-0.4, 0.4, 3)) for n in sizes]
+    ls = I._pack(loops, np.float64, {}, "uneven", 7)
+    L = len(sizes)
+    pairs = np.array([[i, j] for i in range(L) for j in range(L) if i != j and (i + j) % 3 == 0],
+                     dtype=np.int32)
+    for mode, tol in (("plain", PLAIN_TOL), ("mixed", MIXED_TOL)):
+        real, lk, flags = _run(ctx, ls, pairs, mode)
+        _compare(ls, pairs, real, lk, tol, "uneven " + mode)
+    ls32 = I._pack(loops, np.float32, {}, "uneven32", 7)
+    real, lk, flags = _run(ctx, ls32, pairs, "mixed")
+    _compare(ls32, pairs, real, lk, MIXED_TOL, "uneven f32 mixed")
+
+
+def test_chainmail_full_size(ctx):
+    ls = I.chainmail(0)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    exp = ls.expected_for(pairs)
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    assert np.array_equal(olk, exp)
+    for mode, tol in (("plain", PLAIN_TOL), ("mixed", MIXED_TOL)):
+        real, lk, flags = _run(ctx, ls, pairs, mode)
+        err = np.abs(real - oreal)
+        print("chainmail %s: max |err| %.3e p99 %.3e refits %d" % (
+            mode, err.max(), np.quantile(err, 0.99), int(np.sum(flags & 1))), flush=True)
+        assert np.array_equal(lk, olk)
+        assert err.max() <= tol
+
+
+def test_invalid_pairs_and_loops(ctx):
+    rng = np.random.default_rng(1)
+    good = [_smooth_loop(rng, 40, np.zeros(3)), _smooth_loop(rng, 50, np.array([0.3, 0, 0]))]
+    short = good[0][:2].copy()
+    zero = good[0].copy()
+    zero[5] = zero[4]
+    nan = good[1].copy()
+    nan[3, 1] = np.nan
+    ls = I._pack(good + [short, zero], np.float64, {}, "bad", 1)
+    pairs = np.array([[0, 1], [0, 0], [0, 9], [-1, 1], [0, 2], [0, 3]], dtype=np.int32)
+    real, lk, flags = _run(ctx, ls, pairs, "plain")
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    assert lk[0] == olk[0] and flags[0] == 0 and abs(real[0] - oreal[0]) < PLAIN_TOL
+    for p in (1, 2, 3):
+        assert flags[p] & 8 and lk[p] == -(2 ** 31) and np.isnan(real[p])
+    # degenerate loops are flagged but still summed like the oracle does
+    assert flags[4] & 16 and flags[5] & 16
+    assert np.array_equal(lk[4:], olk[4:]) and np.abs(real[4:] - oreal[4:]).max() < PLAIN_TOL
+    real2, lk2, flags2 = _run(ctx, ls, pairs, "mixed")
+    assert np.array_equal(lk2, lk) and np.array_equal(flags2 & 24, flags & 24)
+    # a non-finite coordinate: NONFINITE, invalid integer, in both modes
+    ls = I._pack(good + [nan], np.float64, {}, "nan", 1)
+    pairs = np.array([[0, 1], [0, 2]], dtype=np.int32)
+    for mode in ("plain", "mixed"):
+        real, lk, flags = _run(ctx, ls, pairs, mode)
+        assert flags[1] & 4 and lk[1] == -(2 ** 31) and np.isnan(real[1])
+        assert (flags[0] & 4) == 0
+
+
+def test_empty_pair_list(ctx):
+    import torch
+    ls = I.hopf(16)
+    xyz, off = _dev(ls)
+    pr = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    real, lk, flags = ctx.direct_sum(xyz, off, pr, "mixed")
+    assert real.numel() == 0
+
+
+def test_deterministic_and_graph_equals_eager(ctx):
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    ls = I.chainmail(2, rows=30, cols=30)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    xyz, off = _dev(ls)
+    pr = torch.from_numpy(pairs).cuda()
+    s = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            r, l, f = ctx.direct_sum(xyz, off, pr, "mixed")
+            outs.append(r.clone())
+    torch.cuda.synchronize()
+    assert ctx.stats()["graph_replayed"] == 1
+    ctx.set_option(lk_mod._lib.OPT_GRAPH, 0)
+    try:
+        r, l, f = ctx.direct_sum(xyz, off, pr, "mixed")
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(lk_mod._lib.OPT_GRAPH, 1)
+    for o in outs:
+        assert torch.equal(o, outs[0])
+    assert torch.equal(r, outs[0])
+
+
+def test_refit_everything_equals_plain(ctx):
+    import paper_2106_12655_amd as lk_mod
+    ls = I.chainmail(4, rows=12, cols=12)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    plain = _run(ctx, ls, pairs, "plain")
+    ctx.set_option(lk_mod._lib.OPT_REFIT_THRESHOLD_PPM, 0)
+    try:
+        mixed = _run(ctx, ls, pairs, "mixed")
+        st = ctx.stats()
+    finally:
+        ctx.set_option(lk_mod._lib.OPT_REFIT_THRESHOLD_PPM, 50000)
+    assert st["refits"] == len(pairs)
+    assert np.all(mixed[2] & 1)
+    assert np.array_equal(mixed[0], plain[0])
+    assert np.array_equal(mixed[1], plain[1])
+
+
+def test_build_pairs_matches_oracle(ctx):
+    import torch
+    for ls in (I.ring_grid(0), I.chainmail(0, rows=40, cols=50),
+               I.knit(1, n_loops=60, cp_max=64, per_span=4)):
+        xyz, off = _dev(ls)
+        got = ctx.build_pairs(xyz, off).cpu().numpy()
+        want = oracle.aabb_pairs(ls.xyz, ls.offsets)
+        assert np.array_equal(got, want), ls.name
+    ls = I.ring_grid(0)
+    xyz, off = _dev(ls)
+    import paper_2106_12655_amd as lk_mod
+    with pytest.raises(lk_mod.LkError) as ei:
+        ctx.build_pairs(xyz, off, capacity=10)
+    assert ei.value.status == lk_mod._lib.ECAPACITY
+
+
+def _verify_reference(pairs, lk, ep, elk):
+    cur = {tuple(p): v for p, v in zip(pairs.tolist(), lk.tolist())}
+    exp = {tuple(p): v for p, v in zip(ep.tolist(), elk.tolist())}
+    out = []
+    for k in sorted(set(cur) | set(exp)):
+        got, want = cur.get(k, 0), exp.get(k, 0)
+        if got != want:
+            out.append([k[0], k[1], got, want])
+    return out
+
+
+def test_verify_merge(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    keys = np.unique(rng.integers(0, 400, size=(900, 2)), axis=0)
+    keys = keys[keys[:, 0] < keys[:, 1]]
+    lk = rng.integers(-2, 3, size=len(keys)).astype(np.int32)
+    sel = rng.uniform(size=len(keys)) < 0.7
+    ep, elk = keys[sel], lk[sel].copy()
+    flip = rng.uniform(size=len(elk)) < 0.1
+    elk[flip] += 1
+    cur_sel = rng.uniform(size=len(keys)) < 0.8
+    cp, clk = keys[cur_sel], lk[cur_sel]
+    want = _verify_reference(cp, clk, ep, elk)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a.astype(np.int32))).cuda()
+    n, rec = ctx.verify(t(cp), t(clk), t(ep), t(elk), cap=4096)
+    assert n == len(want)
+    assert rec.cpu().numpy().tolist() == want
+    n1, rec1 = ctx.verify(t(cp), t(clk), t(ep), t(elk), early_exit=True)
+    assert n1 == 1 and rec1.cpu().numpy().tolist() == want[:1]
+    n0, _ = ctx.verify(t(ep), t(elk), t(ep), t(elk))
+    assert n0 == 0
+
+
+def test_knit_full_size_sampled(ctx):
+    ls = I.knit(0)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    exp = ls.expected_for(pairs)
+    real, lk, flags = _run(ctx, ls, pairs, "mixed")
+    frac = np.abs(real - np.round(real))
+    print("knit: pairs %d max frac %.3e refits %d" % (len(pairs), frac.max(), int(np.sum(flags & 1))),
+          flush=True)
+    assert np.array_equal(lk, exp)
+    cost = ls.sizes[pairs[:, 0]].astype(np.int64) * ls.sizes[pairs[:, 1]]
+    pick = np.argsort(cost)[:24]
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs[pick])
+    assert np.array_equal(lk[pick], olk)
+    err = np.abs(real[pick] - oreal)
+    print("knit sampled max |err| %.3e" % err.max(), flush=True)
+    assert err.max() <= MIXED_TOL
