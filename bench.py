@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 companion run")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -109,6 +111,16 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()  # a real stream: the null stream cannot be captured
     torch.cuda.set_stream(stream)
+    if args.copy_probe_mib > 0:
+        # one plain copy kernel that reads and writes exactly this many bytes, so
+        # that profiler byte counters can be scaled against a known transfer
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ls = inputs.config(args.config, args.seed)
     ctx = lk.Context(0)
     xyz = torch.from_numpy(ls.xyz).cuda()

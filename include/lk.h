@@ -141,7 +141,10 @@ enum {
   LK_OPT_TILE_A = 4,              /* FP32 LDS tile of loop A in vertices (0 = tuned) */
   LK_OPT_CHUNK_A = 5,             /* vertices of A per work item (0 = tuned) */
   LK_OPT_WAVES_PER_CU = 6,        /* persistent waves per compute unit (0 = occupancy) */
-  LK_OPT_ATAN = 7                 /* FP32 arctangent: 0 = own minimax, 1 = HIP atan2f */
+  LK_OPT_ATAN = 7,                /* FP32 arctangent: 0 = own minimax, 1 = HIP atan2f */
+  LK_OPT_SEGS_PER_LANE = 8,       /* FP32 kernel: segments of loop B per lane, 1/2/4 (0 = tuned) */
+  LK_OPT_SEGS_PER_LANE_F64 = 9,   /* FP64 kernel: segments of loop B per lane, 1/2 (0 = tuned) */
+  LK_OPT_SMALL_BATCH = 10         /* small pairs claimed per work-counter step, 1..64 (0 = tuned) */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */
@@ -153,7 +156,7 @@ typedef struct {
   double refit_kernel_ms; /* mean refit-kernel time over the same calls (MIXED) */
   int32_t timed_calls;    /* number of calls those means cover */
   int32_t graph_replayed; /* 1 if the last call replayed a captured graph */
-  int32_t tile_a, chunk_a, waves_per_cu, atan_form; /* configuration used */
+  int32_t tile_a, chunk_a, waves_per_cu, atan_form, segs_per_lane; /* configuration used */
 } lk_stats;
 
 /* Statistics of the last lk_direct_sum on this context.  Reading refits and

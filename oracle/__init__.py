@@ -140,7 +140,11 @@ def direct_sum(xyz, offsets, pairs, nthreads: int | None = None):
     real = np.zeros(n, dtype=np.float64)
     lk = np.zeros(n, dtype=np.int32)
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        try:
+            nthreads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            nthreads = os.cpu_count() or 1
+        nthreads = min(nthreads, 16)
     rc = _load().lko_direct_sum(_ptr(xyz), _ptr(off), off.shape[0] - 1, _ptr(pr), n, _ptr(real),
                                 _ptr(lk), int(nthreads))
     if rc != 0:

@@ -21,7 +21,8 @@ PLAIN_F64, MIXED = 0, 1
 FLAG_REFIT, FLAG_AMBIGUOUS, FLAG_NONFINITE, FLAG_BADPAIR, FLAG_BADLOOP = 1, 2, 4, 8, 16
 INT_INVALID = -(2 ** 31)
 OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 3, 4, 5
-OPT_WAVES_PER_CU, OPT_ATAN = 6, 7
+OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
+OPT_SMALL_BATCH = 10
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
            "lk_verify", "lk_set_option", "lk_get_stats"]
@@ -32,7 +33,7 @@ class Stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("refit_kernel_ms", ctypes.c_double),
                 ("timed_calls", ctypes.c_int32), ("graph_replayed", ctypes.c_int32), ("tile_a", ctypes.c_int32),
                 ("chunk_a", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("atan_form", ctypes.c_int32)]
+                ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32)]
 
 
 class LkError(RuntimeError):

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void xi_partial(const Tin* X, const int64_t* o
 }
 
 __global__ __launch_bounds__(256) void xi_final(const double* part, const int64_t* off, int32_t L,
-                                                double* xi) {
+                                                double* xi, int32_t* zero_counts) {
   __shared__ double red[256];
   red[threadIdx.x] = part[threadIdx.x];
   __syncthreads();
@@ -57,6 +57,10 @@ __global__ __launch_bounds__(256) void xi_final(const double* part, const int64_
   if (threadIdx.x == 0) {
     const int64_t nv = off[L] - off[0];
     *xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
+    if (zero_counts) {
+      zero_counts[0] = 0;
+      zero_counts[1] = 0;
+    }
   }
 }
 
@@ -89,8 +93,23 @@ __global__ __launch_bounds__(256) void loop_flags_k(const Tin* X, const int64_t*
 }
 
 // --------------------------------------------------------------- planning
-__global__ __launch_bounds__(256) void plan_k(DsArgs A, int32_t L, const uint32_t* lf,
-                                              int64_t* counts, int refit) {
+// Append to a device list from a wavefront: one atomic per wave, then each
+// lane with `pred` gets base + (number of lower lanes with pred).  All active
+// lanes must call it.
+__device__ __forceinline__ int32_t wave_append(int32_t* count, bool pred) {
+  const unsigned long long m = __ballot(pred);
+  const unsigned long long act = __ballot(1);
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)act) - 1;
+  int32_t base = 0;
+  if (lane == leader && m) base = atomicAdd(count, (int32_t)__popcll(m));
+  base = __shfl(base, leader);
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  return base + (int32_t)__popcll(m & below);
+}
+
+__global__ __launch_bounds__(256) void plan_k(PlanArgs A, int32_t L, const uint32_t* lf, Sched S,
+                                              int refit) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t n = A.n_list;
   if (A.n_list_dev) {
@@ -102,58 +121,139 @@ __global__ __launch_bounds__(256) void plan_k(DsArgs A, int32_t L, const uint32_
   const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
   const bool valid = i >= 0 && j >= 0 && i < L && j < L && i != j;
   int64_t items = 0;
+  WorkRec r{};
   if (valid) {
-    const int64_t na = A.off[i + 1] - A.off[i], nb = A.off[j + 1] - A.off[j];
-    if (na >= 1 && nb >= 1) items = ((nb + kBlockB - 1) / kBlockB) * ((na + A.chunk - 1) / A.chunk);
+    r.oa = A.off[i];
+    r.ob = A.off[j];
+    const int64_t na = A.off[i + 1] - r.oa, nb = A.off[j + 1] - r.ob;
+    r.na = (int32_t)na;
+    r.nb = (int32_t)nb;
+    if (na >= 1 && nb >= 1) items = ((nb + A.bblock - 1) / A.bblock) * ((na + A.chunk - 1) / A.chunk);
   }
+  // loops beyond 2^31 vertices or pairs beyond 2^31 work items are not handled
+  const bool too_big = valid && (A.off[i + 1] - A.off[i] > 0x7fffffffLL ||
+                                 A.off[j + 1] - A.off[j] > 0x7fffffffLL || items > 0x7fffffffLL);
+  if (too_big) items = 0;
   if (refit)
-    A.flags[p] &= ~kFlagNonfinite;
+    A.flags[p] = (A.flags[p] & ~kFlagNonfinite) | (too_big ? kFlagNonfinite : 0u);
   else
-    A.flags[p] = valid ? (lf[i] | lf[j]) : kFlagBadpair;
+    A.flags[p] = valid ? (lf[i] | lf[j] | (too_big ? kFlagBadloop | kFlagNonfinite : 0u))
+                       : kFlagBadpair;
   A.acc[2 * (int64_t)p] = 0ull;
   A.acc[2 * (int64_t)p + 1] = 0ull;
-  counts[q] = items;
+  r.p = p;
+  r.items = (int32_t)items;
+  const bool small = items == 1 && r.na < kSmallA;
+  const bool big = items > 0 && !small;
+  const int32_t ps = wave_append(&S.counts[0], small);
+  const int32_t pb = wave_append(&S.counts[1], big);
+  if (small) S.small[ps] = r;
+  if (big) S.big_in[pb] = r;
 }
 
-// Single-workgroup exclusive scan: each of 1024 threads scans a contiguous
-// chunk, chunk totals are scanned in LDS.  Also zeroes the work counter and an
-// optional int32 (the refit count of the next finalize).
-__global__ __launch_bounds__(1024) void scan_k(const int64_t* counts, const int32_t* n_dev,
-                                               int64_t n_host, int64_t* prefix,
-                                               unsigned long long* counter, int32_t* zero_i32) {
-  __shared__ int64_t sums[1024];
-  int64_t n = n_host;
-  if (n_dev) {
-    const int64_t nd = *n_dev;
-    n = nd < n ? nd : n;
+// Exclusive scan of one value per thread over a 1024-thread workgroup
+// (wavefront shuffles, then the 16 wave totals).  *total receives the sum.
+__device__ int64_t block_excl_scan(int64_t v, int64_t* wsum, int64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = (int64_t)t * per;
-  const int64_t e = (b + per < n) ? b + per : n;
-  int64_t s = 0;
-  for (int64_t k = b; k < e; ++k) s += counts[k];
-  sums[t] = s;
+  if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  for (int w = 1; w < 1024; w <<= 1) {
-    const int64_t add = (t >= w) ? sums[t - w] : 0;
-    __syncthreads();
-    sums[t] += add;
-    __syncthreads();
+  if (wave == 0) {
+    int64_t sw = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int64_t y = __shfl_up(sw, o);
+      if (lane >= o) sw += y;
+    }
+    if (lane < 16) wsum[lane] = sw;
   }
-  int64_t run = sums[t] - s;  // exclusive
-  for (int64_t k = b; k < e; ++k) {
-    prefix[k] = run;
-    run += counts[k];
+  __syncthreads();
+  const int64_t before = wave ? wsum[wave - 1] : 0;
+  *total = wsum[15];
+  __syncthreads();
+  return before + x - v;
+}
+
+// In-place-capable exclusive scan of src[0..n) into dst[0..n], dst[n] = total;
+// 4 consecutive elements per thread per round, so loads are coalesced.
+__device__ int64_t block_scan_array(const int64_t* src, int64_t n, int64_t* dst, int64_t* wsum) {
+  const int t = threadIdx.x;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += 4096) {
+    const int64_t k0 = base + 4 * (int64_t)t;
+    int64_t v[4];
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i] = (k0 + i < n) ? src[k0 + i] : 0;
+      sum += v[i];
+    }
+    int64_t tot = 0;
+    int64_t run = carry + block_excl_scan(sum, wsum, &tot);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (k0 + i < n) dst[k0 + i] = run;
+      run += v[i];
+    }
+    carry += tot;
   }
-  if (t == 1023) prefix[n] = sums[1023];
+  if (t == 0) dst[n] = carry;
+  return carry;
+}
+
+__device__ __forceinline__ int cost_bucket(int32_t items) { return 31 - __clz(items); }
+
+// One workgroup: bucket the big pairs by log2(items), largest bucket first
+// (an LPT order up to a factor of two), then scan their items.
+__global__ __launch_bounds__(1024) void sched_k(Sched S, int32_t* zero_next) {
+  __shared__ int hist[32];
+  __shared__ int cur[32];
+  __shared__ int64_t wsum[16];
+  const int t = threadIdx.x;
+  const int nb = S.counts[1];
+  if (t < 32) hist[t] = 0;
+  __syncthreads();
+  for (int k = t; k < nb; k += 1024) atomicAdd(&hist[cost_bucket(S.big_in[k].items)], 1);
+  __syncthreads();
   if (t == 0) {
-    if (counter) *counter = 0ull;
-    if (zero_i32) *zero_i32 = 0;
+    int run = 0;
+    for (int b = 31; b >= 0; --b) {
+      cur[b] = run;
+      run += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int k = t; k < nb; k += 1024) {
+    const WorkRec r = S.big_in[k];
+    const int pos = atomicAdd(&cur[cost_bucket(r.items)], 1);
+    S.big[pos] = r;
+    S.big_prefix[pos] = r.items;
+  }
+  __syncthreads();
+  const int64_t total = block_scan_array(S.big_prefix, nb, S.big_prefix, wsum);
+  if (t == 0) {
+    *S.big_total = total;
+    *S.counter = 0ull;
+    if (zero_next) {
+      zero_next[0] = 0;
+      zero_next[1] = 0;
+      zero_next[2] = 0;
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void finalize_k(DsArgs A, double thr, double* lk_real,
+// General single-workgroup exclusive scan (pair search, verification).
+__global__ __launch_bounds__(1024) void scan_k(const int64_t* counts, int64_t n, int64_t* prefix) {
+  __shared__ int64_t wsum[16];
+  block_scan_array(counts, n, prefix, wsum);
+}
+
+__global__ __launch_bounds__(256) void finalize_k(PlanArgs A, double thr, double* lk_real,
                                                   int32_t* lk_int, int32_t* refit_list,
                                                   int32_t* refit_n, int refit_pass) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -165,43 +265,46 @@ __global__ __launch_bounds__(256) void finalize_k(DsArgs A, double thr, double* 
   if (q >= n) return;
   const int32_t p = A.list ? A.list[q] : (int32_t)q;
   uint32_t f = A.flags[p];
-  const unsigned long long lo = A.acc[2 * (int64_t)p], hi = A.acc[2 * (int64_t)p + 1];
-  const double v = (double)(long long)hi + (double)lo * 5.421010862427522170e-20;  // 2^-64
+  unsigned long long lo = A.acc[2 * (int64_t)p], hi = A.acc[2 * (int64_t)p + 1];
+  // 128-bit two's complement -> sign and magnitude -> double (one rounding of
+  // the fraction word, one of the sum)
+  const bool neg = (long long)hi < 0;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const double mag = (double)hi + (double)lo * 5.421010862427522170e-20;  // 2^-64
+  const double v = neg ? -mag : mag;
+  bool requeue = false;
   if (f & kFlagBadpair) {
     lk_real[p] = __builtin_nan("");
     lk_int[p] = kIntInvalid;
-    return;
-  }
-  if (refit_pass) f |= kFlagRefit;
-  const bool bad = (f & kFlagNonfinite) || !isfinite(v) || fabs(v) > 2.0e9;
-  if (bad) {
-    f |= kFlagNonfinite;
-    lk_real[p] = __builtin_nan("");
-    lk_int[p] = kIntInvalid;
-    if (refit_list) refit_list[atomicAdd(refit_n, 1)] = p;
   } else {
-    const double r = round(v);  // half away from zero
-    const double frac = fabs(v - r);
-    lk_real[p] = v;
-    lk_int[p] = (int32_t)r;
-    if (frac > thr) {
-      if (refit_list)
-        refit_list[atomicAdd(refit_n, 1)] = p;
-      else
-        f |= kFlagAmbiguous;
+    if (refit_pass) f |= kFlagRefit;
+    const bool bad = (f & kFlagNonfinite) || !isfinite(v) || fabs(v) > 2.0e9;
+    if (bad) {
+      f |= kFlagNonfinite;
+      lk_real[p] = __builtin_nan("");
+      lk_int[p] = kIntInvalid;
+      requeue = refit_list != nullptr;
+    } else {
+      const double r = round(v);  // half away from zero
+      const double frac = fabs(v - r);
+      lk_real[p] = v;
+      lk_int[p] = (int32_t)r;
+      if (frac > thr) {
+        if (refit_list)
+          requeue = true;
+        else
+          f |= kFlagAmbiguous;
+      }
     }
+    A.flags[p] = f;
   }
-  A.flags[p] = f;
-}
-
-__global__ __launch_bounds__(256) void fill_i32_k(int32_t* p, int64_t n, int32_t v) {
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
-    p[k] = v;
-}
-
-__global__ __launch_bounds__(256) void copy_u32_k(const uint32_t* s, uint32_t* d, int64_t n) {
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
-    d[k] = s[k];
+  if (refit_list) {
+    const int32_t pos = wave_append(refit_n, requeue);
+    if (requeue) refit_list[pos] = p;
+  }
 }
 
 // ------------------------------------------------------ potential link search
@@ -359,55 +462,43 @@ __global__ __launch_bounds__(256) void verify_scatter_k(const int32_t* pr, const
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_loop_flags(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
-                             double* xi_partials, double* xi, uint32_t* lf, hipStream_t s) {
+                             double* xi_partials, double* xi, uint32_t* lf, int32_t* zero_counts,
+                             hipStream_t s) {
   const int lb = blocks_for((int64_t)n_loops * 64, 256, 8192);
   if (in_f64) {
     xi_partial<double><<<kXiBlocks, 256, 0, s>>>((const double*)xyz, off, n_loops, xi_partials);
-    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi);
+    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi, zero_counts);
     loop_flags_k<double><<<lb, 256, 0, s>>>((const double*)xyz, off, n_loops, xi, DBL_EPSILON, lf);
   } else {
     xi_partial<float><<<kXiBlocks, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials);
-    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi);
+    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi, zero_counts);
     loop_flags_k<float><<<lb, 256, 0, s>>>((const float*)xyz, off, n_loops, xi,
                                            (double)FLT_EPSILON, lf);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const DsArgs& a, int32_t n_loops, const uint32_t* lf, int64_t* counts,
+hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const uint32_t* lf, const Sched& sc,
                        bool refit, hipStream_t s) {
-  plan_k<<<blocks_for(a.n_list, 256), 256, 0, s>>>(a, n_loops, lf, counts, refit ? 1 : 0);
+  plan_k<<<blocks_for(a.n_list, 256), 256, 0, s>>>(a, n_loops, lf, sc, refit ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const int64_t* counts, const int32_t* n_dev, int64_t n, int64_t* prefix,
-                       unsigned long long* counter, hipStream_t s) {
-  scan_k<<<1, 1024, 0, s>>>(counts, n_dev, n, prefix, counter, nullptr);
+hipError_t launch_sched(const Sched& sc, int32_t* zero_next, hipStream_t s) {
+  sched_k<<<1, 1024, 0, s>>>(sc, zero_next);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_zero(const int64_t* counts, const int32_t* n_dev, int64_t n,
-                            int64_t* prefix, unsigned long long* counter, int32_t* zero_i32,
-                            hipStream_t s) {
-  scan_k<<<1, 1024, 0, s>>>(counts, n_dev, n, prefix, counter, zero_i32);
+hipError_t launch_scan(const int64_t* counts, int64_t n, int64_t* prefix, hipStream_t s) {
+  scan_k<<<1, 1024, 0, s>>>(counts, n, prefix);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DsArgs& a, double thr, double* lk_real, int32_t* lk_int,
+hipError_t launch_finalize(const PlanArgs& a, double thr, double* lk_real, int32_t* lk_int,
                            int32_t* refit_list, int32_t* refit_n, bool refit_pass,
                            hipStream_t s) {
   finalize_k<<<blocks_for(a.n_list, 256), 256, 0, s>>>(a, thr, lk_real, lk_int, refit_list,
                                                        refit_n, refit_pass ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
-  fill_i32_k<<<blocks_for(n, 256, 4096), 256, 0, s>>>(p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s) {
-  copy_u32_k<<<blocks_for(n, 256, 4096), 256, 0, s>>>(src, dst, n);
   return hipGetLastError();
 }
 

@@ -101,209 +101,378 @@ __device__ __forceinline__ V3<Tc> load_vertex(const Tin* X, int64_t v) {
   return {(Tc)X[3 * v], (Tc)X[3 * v + 1], (Tc)X[3 * v + 2]};
 }
 
-// Segment of loop B owned by a lane.
-template <typename T>
-struct Seg {
-  V3<T> k0, k1, s;  // k_i, k_{i+1}, s_i = k_{i+1} - k_i
+// The R consecutive segments of loop B owned by a lane: vertices k_0..k_R and
+// segment vectors s_r = k_{r+1} - k_r.  Segments past the end of the item are
+// evaluated on repeated vertices and masked out.
+template <typename T, int R>
+struct Segs {
+  V3<T> k[R + 1];
+  V3<T> s[R];
+  bool valid[R];
 };
 
-// Walk state at vertex l_j of loop A.
-template <typename T>
+// Walk state at vertex l_j of loop A, for all R + 1 vertices of the lane:
+// V_r = l_j - k_r, N_r = |V_r|, E_r = N_r N_{r+1} + V_r . V_{r+1}.
+template <typename T, int R>
 struct Walk {
-  V3<T> l;     // l_j
-  V3<T> a, b;  // l_j - k_i, l_j - k_{i+1}
-  T na, nb, e; // |a|, |b|, |a||b| + a.b
+  V3<T> l;
+  V3<T> V[R + 1];
+  T N[R + 1];
+  T E[R];
 };
 
-template <typename T>
-__device__ __forceinline__ void walk_init(Walk<T>& w, const V3<T>& l, const Seg<T>& g) {
+template <typename T, int R>
+__device__ __forceinline__ void walk_init(Walk<T, R>& w, const V3<T>& l, const Segs<T, R>& g) {
   w.l = l;
-  w.a = l - g.k0;
-  w.b = l - g.k1;
-  w.na = fsqrt(dot(w.a, w.a));
-  w.nb = fsqrt(dot(w.b, w.b));
-  w.e = w.na * w.nb + dot(w.a, w.b);
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    w.V[r] = l - g.k[r];
+    w.N[r] = fsqrt(dot(w.V[r], w.V[r]));
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) w.E[r] = w.N[r] * w.N[r + 1] + dot(w.V[r], w.V[r + 1]);
 }
 
-// One Eq. 4 term for segment (l_j, l_{j+1}) against the lane's segment;
-// returns 2 pi times the term and advances the walk to l_{j+1}.
-template <typename T, int AT>
-__device__ __forceinline__ T walk_step(Walk<T>& w, const V3<T>& l1, const Seg<T>& g) {
-  const V3<T> c = l1 - g.k1;
-  const V3<T> d = l1 - g.k0;
-  const T nc = fsqrt(dot(c, c));
-  const T nd = fsqrt(dot(d, d));
+// The Eq. 4 terms of segment (l_j, l_{j+1}) against the lane's R segments;
+// returns 2 pi times their (masked) sum and advances the walk to l_{j+1}.
+// For segment r: a = V_r, b = V_{r+1} (at l_j), c = v_{r+1}, d = v_r (at
+// l_{j+1}); a.b enters through E_r, and the "vertical" products V_r . v_r are
+// shared by segments r - 1 and r.
+template <typename T, int AT, int R>
+__device__ __forceinline__ T walk_step(Walk<T, R>& w, const V3<T>& l1, const Segs<T, R>& g) {
+  V3<T> v[R + 1];
+  T n[R + 1], vert[R + 1];
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    v[r] = l1 - g.k[r];
+    n[r] = fsqrt(dot(v[r], v[r]));
+    vert[r] = dot(w.V[r], v[r]);
+  }
   const V3<T> sj = l1 - w.l;
-  const T p = dot(w.a, cross(sj, g.s));
-  const T bc = dot(w.b, c);
-  const T ca = dot(c, w.a);
-  const T ad = dot(w.a, d);
-  const T f = nd * nc + dot(d, c);
-  const T d1 = nc * w.e + bc * w.na + ca * w.nb;
-  const T d2 = w.na * f + ad * nc + ca * nd;
-  const T th = angle<T, AT>(p * (d1 + d2), d1 * d2 - p * p);
+  T sum = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const V3<T>& a = w.V[r];
+    const V3<T>& c = v[r + 1];
+    const V3<T>& d = v[r];
+    const T na = w.N[r], nb = w.N[r + 1], nc = n[r + 1], nd = n[r];
+    const T p = dot(a, cross(sj, g.s[r]));
+    const T ca = dot(c, a);
+    const T f = nd * nc + dot(d, c);
+    const T d1 = nc * w.E[r] + vert[r + 1] * na + ca * nb;
+    const T d2 = na * f + vert[r] * nc + ca * nd;
+    const T th = angle<T, AT>(p * (d1 + d2), d1 * d2 - p * p);
+    sum += g.valid[r] ? th : (T)0;
+    w.E[r] = f;
+  }
   w.l = l1;
-  w.a = d;
-  w.b = c;
-  w.na = nd;
-  w.nb = nc;
-  w.e = f;
-  return th;
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    w.V[r] = v[r];
+    w.N[r] = n[r];
+  }
+  return sum;
 }
 
 // 128-bit two's-complement fixed point with 64 fraction bits, accumulated with
 // 64-bit integer atomics: integer addition is associative, so the pair sum is
-// the same whatever order the work items finish in.  Bits below 2^-64 of each
-// item's partial are dropped (deterministically).
-__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
-  const double fl = floor(v);
-  const long long hi = (long long)fl;
-  const double fr = v - fl;  // exact, in [0, 1)
-  const unsigned long long lo = (unsigned long long)(fr * 18446744073709551616.0);
-  const unsigned long long old = atomicAdd(&acc[0], lo);
-  const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
-  atomicAdd(&acc[1], (unsigned long long)hi + carry);
+// the same whatever order the work items finish in.  The conversion is exact
+// except for bits below 2^-64, which are dropped by an arithmetic shift (always
+// towards -infinity, so deterministically).  |v| < 2^50 is required.
+__device__ __forceinline__ void to_fixed(double v, unsigned long long& lo, unsigned long long& hi) {
+  lo = 0ull;
+  hi = 0ull;
+  if (v == 0.0) return;
+  int e = 0;
+  const double f = frexp(v, &e);                   // v = f 2^e, 0.5 <= |f| < 1
+  const long long m = (long long)ldexp(f, 53);     // exact: |m| < 2^53
+  const int s = e + 11;                            // v 2^64 = m 2^s
+  if (s > 0) {
+    lo = (unsigned long long)m << s;
+    hi = (unsigned long long)(m >> (64 - s));
+  } else if (s == 0) {
+    lo = (unsigned long long)m;
+    hi = m < 0 ? ~0ull : 0ull;
+  } else if (s > -64) {
+    const long long t = m >> (-s);
+    lo = (unsigned long long)t;
+    hi = t < 0 ? ~0ull : 0ull;
+  } else {
+    lo = m < 0 ? ~0ull : 0ull;
+    hi = lo;
+  }
 }
 
-template <typename Tin, typename Tc, int AT>
+__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
+  unsigned long long lo, hi;
+  to_fixed(v, lo, hi);
+  if (lo == 0ull && hi == 0ull) return;
+  const unsigned long long old = atomicAdd(&acc[0], lo);
+  const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+  atomicAdd(&acc[1], hi + carry);
+}
+
+// Where the lanes of one work item sit: B block [b0, b0 + nbh) of loop B split
+// into `slots` lanes of R segments; if that leaves lanes over, they form
+// `groups` that split the item's A range [a0, a0 + nah) into [js, je).
+struct Layout {
+  int64_t b0, a0;
+  int nbh, nah, bi, js, je;
+  bool active;
+};
+
+template <int R>
+__device__ __forceinline__ Layout layout(const WorkRec& r, int64_t local, int chunk, int lane) {
+  constexpr int kB = kWave * R;
+  Layout L;
+  const int64_t nbb = (r.nb + kB - 1) / kB;
+  L.b0 = (local % nbb) * kB;
+  L.a0 = (local / nbb) * (int64_t)chunk;
+  L.nbh = (int)((r.nb - L.b0) < kB ? (r.nb - L.b0) : kB);
+  L.nah = (int)((r.na - L.a0) < chunk ? (r.na - L.a0) : chunk);
+  const int slots = (L.nbh + R - 1) / R;
+  const int groups = kWave / slots;
+  L.bi = lane % slots;
+  const int g = lane / slots;
+  L.active = g < groups;
+  L.js = (int)(((int64_t)L.nah * g) / groups);
+  L.je = (int)(((int64_t)L.nah * (g + 1)) / groups);
+  return L;
+}
+
+// Vertex k_{b0 + bi R + r} of loop B for r = 0..R (cyclic; padding lanes
+// repeat the last vertex and are masked by Segs::valid).
+template <typename Tin, typename Tc, int R>
+__device__ __forceinline__ void load_b(const Tin* X, const WorkRec& w, const Layout& L,
+                                       V3<Tc>* k) {
+  const int first = L.bi * R;
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    int64_t i = L.b0 + first + r;
+    if (i >= w.nb) i -= w.nb;
+    if (i >= w.nb) i = w.nb - 1;
+    k[r] = load_vertex<Tc>(X, w.ob + i);
+  }
+}
+
+template <typename Tc, int R>
+__device__ __forceinline__ void make_segs(const V3<Tc>* k, const Layout& L, Segs<Tc, R>& sg) {
+  const int first = L.bi * R;
+#pragma unroll
+  for (int r = 0; r <= R; ++r) sg.k[r] = k[r];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    sg.s[r] = sg.k[r + 1] - sg.k[r];
+    sg.valid[r] = first + r < L.nbh;
+  }
+}
+
+// Walk segments [jlo, jhi) of the item's A range, whose vertices t0 .. are in
+// LDS; starts the walk when jlo is the lane's first segment.
+template <typename Tc, int AT, int R>
+__device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, int jhi, int js,
+                                          Walk<Tc, R>& wk, const Segs<Tc, R>& sg, double& acc) {
+  if (jlo == js) {
+    const Vtx<Tc> v0 = lds[jlo - t0];
+    walk_init(wk, V3<Tc>{v0.x, v0.y, v0.z}, sg);
+  }
+#pragma unroll 4
+  for (int j = jlo; j < jhi; ++j) {
+    const Vtx<Tc> v1 = lds[j - t0 + 1];
+    acc += (double)walk_step<Tc, AT, R>(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg);
+  }
+}
+
+// Wave sum of the lanes' partials and its fixed-point addition to the pair.
+// `whole`: this item is the pair's only item, so the (zeroed) accumulator is
+// simply overwritten and no atomic round trip is needed.
+__device__ __forceinline__ void finish_item(double acc, int32_t p, int lane, const DsArgs& A,
+                                            bool whole) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) {
+    const double v = acc * kInvTwoPi;
+    if (!(fabs(v) < 1.0e14)) {
+      atomicOr(&A.flags[p], 4u);  // NaN / Inf / absurd magnitude
+    } else if (whole) {
+      unsigned long long lo, hi;
+      to_fixed(v, lo, hi);
+      A.acc[2 * (int64_t)p] = lo;
+      A.acc[2 * (int64_t)p + 1] = hi;
+    } else {
+      fixed_add(&A.acc[2 * (int64_t)p], v);
+    }
+  }
+}
+
+__device__ __forceinline__ WorkRec shfl_rec(const WorkRec& r, int src) {
+  WorkRec o;
+  o.oa = __shfl(r.oa, src);
+  o.ob = __shfl(r.ob, src);
+  o.na = __shfl(r.na, src);
+  o.nb = __shfl(r.nb, src);
+  o.p = __shfl(r.p, src);
+  o.items = 1;
+  return o;
+}
+
+template <typename Tin, typename Tc, int AT, int R>
 __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Vtx<Tc>* lds = reinterpret_cast<Vtx<Tc>*>(lds_raw);
   const int lane = threadIdx.x;
   const Tin* X = static_cast<const Tin*>(A.xyz);
-  int64_t n_list = A.n_list;
-  if (A.n_list_dev) {
-    const int64_t nd = *A.n_list_dev;
-    n_list = nd < n_list ? nd : n_list;
-  }
-  const int64_t total = A.prefix[n_list];
+  const int64_t big_total = *A.s.big_total;
+  const int64_t n_big = A.s.counts[1];
+  const int64_t n_small = A.s.counts[0];
+  const int64_t total = big_total + (n_small + A.batch - 1) / A.batch;
 
+  // the next work index is fetched one item ahead so the atomic's latency
+  // overlaps the current item's arithmetic
+  unsigned long long wnext = 0;
+  if (lane == 0) wnext = atomicAdd(A.s.counter, 1ull);
   for (;;) {
-    unsigned long long wi = 0;
-    if (lane == 0) wi = atomicAdd(A.counter, 1ull);
-    const int64_t w = (int64_t)__shfl(wi, 0);
+    const int64_t w = (int64_t)__shfl(wnext, 0);
     if (w >= total) break;
+    if (lane == 0) wnext = atomicAdd(A.s.counter, 1ull);
 
-    // list position q with prefix[q] <= w < prefix[q + 1]
-    int64_t lo = 0, hi = n_list;
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (A.prefix[mid] <= w)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    const int64_t q = lo;
-    const int32_t p = A.list ? A.list[q] : (int32_t)q;
-    const int32_t ia = A.pairs[2 * p], ib = A.pairs[2 * p + 1];
-    const int64_t oa = A.off[ia], na = A.off[ia + 1] - oa;
-    const int64_t ob = A.off[ib], nb = A.off[ib + 1] - ob;
-    const int64_t local = w - A.prefix[q];
-    const int64_t nbb = (nb + kBlockB - 1) / kBlockB;
-    const int64_t b0 = (local % nbb) * kBlockB;
-    const int64_t a0 = (local / nbb) * (int64_t)A.chunk;
-    const int nbh = (int)((nb - b0) < kBlockB ? (nb - b0) : kBlockB);
-    const int nah = (int)((na - a0) < A.chunk ? (na - a0) : A.chunk);
-    const int groups = kWave / nbh;
-    const int bi = lane % nbh;
-    const int g = lane / nbh;
-    const bool active = g < groups;
-    const int js = (int)(((int64_t)nah * g) / groups);
-    const int je = (int)(((int64_t)nah * (g + 1)) / groups);
-
-    Seg<Tc> sg;
-    {
-      const int64_t i0 = b0 + bi;
-      const int64_t i1 = (i0 + 1 == nb) ? 0 : i0 + 1;
-      sg.k0 = load_vertex<Tc>(X, ob + i0);
-      sg.k1 = load_vertex<Tc>(X, ob + i1);
-      sg.s = sg.k1 - sg.k0;
-    }
-    Walk<Tc> wk;
-    double acc = 0.0;
-    for (int t0 = 0; t0 < nah; t0 += A.tile) {
-      const int tl = (nah - t0) < A.tile ? (nah - t0) : A.tile;
-      __syncthreads();
-      for (int v = lane; v <= tl; v += kWave) {
-        int64_t idx = a0 + t0 + v;
-        if (idx >= na) idx -= na;  // closing vertex of the loop
-        const V3<Tc> x = load_vertex<Tc>(X, oa + idx);
-        lds[v] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
+    if (w < big_total) {
+      // one item of a big pair: position with big_prefix[pos] <= w < big_prefix[pos + 1]
+      int64_t lo = 0, hi = n_big;
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (A.s.big_prefix[mid] <= w)
+          lo = mid;
+        else
+          hi = mid;
       }
-      __syncthreads();
-      const int jlo = js > t0 ? js : t0;
-      const int jhi = je < t0 + tl ? je : t0 + tl;
-      Tc part = 0;
-      if (active && jlo < jhi) {
-        if (jlo == js) {
-          const Vtx<Tc> v0 = lds[jlo - t0];
-          walk_init(wk, V3<Tc>{v0.x, v0.y, v0.z}, sg);
+      const WorkRec r = A.s.big[lo];
+      const Layout L = layout<R>(r, w - A.s.big_prefix[lo], A.chunk, lane);
+      V3<Tc> kv[R + 1];
+      load_b<Tin, Tc, R>(X, r, L, kv);
+      Segs<Tc, R> sg;
+      make_segs<Tc, R>(kv, L, sg);
+      Walk<Tc, R> wk;
+      double acc = 0.0;
+      for (int t0 = 0; t0 < L.nah; t0 += A.tile) {
+        const int tl = (L.nah - t0) < A.tile ? (L.nah - t0) : A.tile;
+        __syncthreads();
+        for (int v = lane; v <= tl; v += kWave) {
+          int64_t idx = L.a0 + t0 + v;
+          if (idx >= r.na) idx -= r.na;  // closing vertex of the loop
+          const V3<Tc> x = load_vertex<Tc>(X, r.oa + idx);
+          lds[v] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
         }
-#pragma unroll 4
-        for (int j = jlo; j < jhi; ++j) {
-          const Vtx<Tc> v1 = lds[j - t0 + 1];
-          part += walk_step<Tc, AT>(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg);
-        }
+        __syncthreads();
+        const int jlo = L.js > t0 ? L.js : t0;
+        const int jhi = L.je < t0 + tl ? L.je : t0 + tl;
+        if (L.active && jlo < jhi) walk_tile<Tc, AT, R>(lds, t0, jlo, jhi, L.js, wk, sg, acc);
       }
-      acc += (double)part;
-    }
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) {
-      const double v = acc * kInvTwoPi;
-      if (fabs(v) < 1.0e15)
-        fixed_add(&A.acc[2 * (int64_t)p], v);
-      else
-        atomicOr(&A.flags[p], 4u);  // NaN / Inf / absurd magnitude
+      finish_item(acc, r.p, lane, A, r.items == 1);
+    } else {
+      // a batch of small pairs (one item each, loop A of at most kSmallA - 1
+      // segments): records are read once per batch, and the next pair's
+      // vertices are loaded into registers while the current pair computes
+      const int64_t m0 = (w - big_total) * (int64_t)A.batch;
+      const int cnt = (int)((n_small - m0) < A.batch ? (n_small - m0) : A.batch);
+      WorkRec mine{};
+      if (lane < cnt) mine = A.s.small[m0 + lane];
+      WorkRec cur = shfl_rec(mine, 0);
+      Layout L = layout<R>(cur, 0, A.chunk, lane);
+      V3<Tc> kv[R + 1], a_lo, a_hi;
+      load_b<Tin, Tc, R>(X, cur, L, kv);
+      a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
+      a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
+      for (int m = 0; m < cnt; ++m) {
+        __syncthreads();
+        if (lane <= cur.na) lds[lane] = Vtx<Tc>{a_lo.x, a_lo.y, a_lo.z, (Tc)0};
+        if (lane + kWave <= cur.na) lds[lane + kWave] = Vtx<Tc>{a_hi.x, a_hi.y, a_hi.z, (Tc)0};
+        Segs<Tc, R> sg;
+        make_segs<Tc, R>(kv, L, sg);
+        const Layout Lc = L;
+        const int32_t pc = cur.p;
+        if (m + 1 < cnt) {
+          cur = shfl_rec(mine, m + 1);
+          L = layout<R>(cur, 0, A.chunk, lane);
+          load_b<Tin, Tc, R>(X, cur, L, kv);
+          a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
+          a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
+        }
+        __syncthreads();
+        Walk<Tc, R> wk;
+        double acc = 0.0;
+        if (Lc.active && Lc.js < Lc.je) walk_tile<Tc, AT, R>(lds, 0, Lc.js, Lc.je, Lc.js, wk, sg, acc);
+        finish_item(acc, pc, lane, A, true);
+      }
     }
   }
 }
 
-template <typename Tin, typename Tc, int AT>
+template <typename Tc>
 size_t lds_bytes(int tile) {
-  return (size_t)(tile + 1) * sizeof(Vtx<Tc>);
+  const int n = tile + 1 > kSmallA ? tile + 1 : kSmallA;
+  return (size_t)n * sizeof(Vtx<Tc>);
 }
 
-template <typename Tin, typename Tc, int AT>
+template <typename Tin, typename Tc, int AT, int R>
 hipError_t launch_t(const DsArgs& a, int grid, hipStream_t s) {
-  const size_t shm = lds_bytes<Tin, Tc, AT>(a.tile);
-  ds_persistent<Tin, Tc, AT><<<dim3(grid), dim3(kWave), shm, s>>>(a);
+  const size_t shm = lds_bytes<Tc>(a.tile);
+  ds_persistent<Tin, Tc, AT, R><<<dim3(grid), dim3(kWave), shm, s>>>(a);
   return hipGetLastError();
 }
 
-template <typename Tin, typename Tc, int AT>
+template <typename Tin, typename Tc, int AT, int R>
 int grid_t(int tile, int n_cu, int waves_per_cu) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT>, kWave,
-                                                   lds_bytes<Tin, Tc, AT>(tile)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT, R>, kWave,
+                                                   lds_bytes<Tc>(tile)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (waves_per_cu > 0 && waves_per_cu < per_cu) per_cu = waves_per_cu;
   return per_cu * n_cu;
 }
 
-}  // namespace
+// Kernel variants: input type x arithmetic x arctangent form x segments per lane.
+struct Variant {
+  hipError_t (*launch)(const DsArgs&, int, hipStream_t);
+  int (*grid)(int, int, int);
+};
 
-hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,
-                             int grid, hipStream_t s) {
-  if (compute_f64) {
-    return in_f64 ? launch_t<double, double, 0>(a, grid, s) : launch_t<float, double, 0>(a, grid, s);
-  }
-  if (atan_form == 1)
-    return in_f64 ? launch_t<double, float, 1>(a, grid, s) : launch_t<float, float, 1>(a, grid, s);
-  return in_f64 ? launch_t<double, float, 0>(a, grid, s) : launch_t<float, float, 0>(a, grid, s);
+template <typename Tin, typename Tc, int AT, int R>
+constexpr Variant variant() {
+  return Variant{launch_t<Tin, Tc, AT, R>, grid_t<Tin, Tc, AT, R>};
 }
 
-int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int tile, int n_cu,
+Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
+  if (compute_f64) {
+    if (segs >= 2) return in_f64 ? variant<double, double, 0, 2>() : variant<float, double, 0, 2>();
+    return in_f64 ? variant<double, double, 0, 1>() : variant<float, double, 0, 1>();
+  }
+  if (atan_form == 1) {
+    if (segs >= 4) return in_f64 ? variant<double, float, 1, 4>() : variant<float, float, 1, 4>();
+    if (segs >= 2) return in_f64 ? variant<double, float, 1, 2>() : variant<float, float, 1, 2>();
+    return in_f64 ? variant<double, float, 1, 1>() : variant<float, float, 1, 1>();
+  }
+  if (segs >= 4) return in_f64 ? variant<double, float, 0, 4>() : variant<float, float, 0, 4>();
+  if (segs >= 2) return in_f64 ? variant<double, float, 0, 2>() : variant<float, float, 0, 2>();
+  return in_f64 ? variant<double, float, 0, 1>() : variant<float, float, 0, 1>();
+}
+
+}  // namespace
+
+int segs_supported(bool compute_f64, int segs) {
+  if (compute_f64) return segs >= 2 ? 2 : 1;
+  return segs >= 4 ? 4 : (segs >= 2 ? 2 : 1);
+}
+
+hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,
+                             int segs, int grid, hipStream_t s) {
+  return pick(in_f64, compute_f64, atan_form, segs).launch(a, grid, s);
+}
+
+int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int segs, int tile, int n_cu,
                     int waves_per_cu) {
-  if (compute_f64)
-    return in_f64 ? grid_t<double, double, 0>(tile, n_cu, waves_per_cu)
-                  : grid_t<float, double, 0>(tile, n_cu, waves_per_cu);
-  if (atan_form == 1)
-    return in_f64 ? grid_t<double, float, 1>(tile, n_cu, waves_per_cu)
-                  : grid_t<float, float, 1>(tile, n_cu, waves_per_cu);
-  return in_f64 ? grid_t<double, float, 0>(tile, n_cu, waves_per_cu)
-                : grid_t<float, float, 0>(tile, n_cu, waves_per_cu);
+  return pick(in_f64, compute_f64, atan_form, segs).grid(tile, n_cu, waves_per_cu);
 }
 
 }  // namespace lk

@@ -42,9 +42,10 @@ struct lk_ctx {
   double refit_thr = 0.05;
   bool use_graph = true;
   bool timing = false;
-  int opt_tile = 0, opt_chunk = 0, opt_waves = 0, opt_atan = 0;
+  int opt_tile = 0, opt_chunk = 0, opt_waves = 0, opt_atan = 0, opt_segs = 0, opt_segs64 = 0;
+  int opt_batch = 0;
   // workspace
-  DevBuf loop_flags, xi, counts, prefix, counter, acc, flags, refit_list, refit_n;
+  DevBuf loop_flags, xi, recs, big_prefix, meta, acc, flags, refit_list;
   DevBuf boxes, vcounts, vprefix;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
   // graphs
@@ -108,8 +109,41 @@ int default_chunk(bool f64) { return f64 ? 2048 : 4096; }
 struct Plan {
   bool in_f64;
   bool mixed;
-  int tile, chunk, grid, grid64, atan_form;
+  int tile, chunk, grid, grid64, grid_refit, atan_form;
+  int segs, segs64;  // segments of loop B per lane, FP32 and FP64 kernels
 };
+
+constexpr int kDefaultSegs32 = 4;
+constexpr int kDefaultSegs64 = 2;
+constexpr int kDefaultBatch = 4;
+
+// Small device-side counters of one call, in one buffer (byte offsets).
+constexpr size_t kMetaCountsMain = 0;    // int32[2]: n_small, n_big (main pass)
+constexpr size_t kMetaCountsRefit = 8;   // int32[2]: n_small, n_big (refit pass)
+constexpr size_t kMetaRefitN = 16;       // int32: pairs queued for refit (follows the above)
+constexpr size_t kMetaBigTotalMain = 24; // int64
+constexpr size_t kMetaBigTotalRefit = 32;
+constexpr size_t kMetaCounterMain = 40;  // uint64 work counters
+constexpr size_t kMetaCounterRefit = 48;
+constexpr size_t kMetaBytes = 64;
+
+template <typename T>
+T* meta_at(lk_ctx* ctx, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ctx->meta.p) + off);
+}
+
+lk::Sched make_sched(lk_ctx* ctx, int64_t n_pairs, bool refit) {
+  lk::Sched S;
+  lk::WorkRec* recs = (lk::WorkRec*)ctx->recs.p;
+  S.small = recs;
+  S.big_in = recs + n_pairs;
+  S.big = recs + 2 * n_pairs;
+  S.big_prefix = (int64_t*)ctx->big_prefix.p;
+  S.counts = meta_at<int32_t>(ctx, refit ? kMetaCountsRefit : kMetaCountsMain);
+  S.big_total = meta_at<int64_t>(ctx, refit ? kMetaBigTotalRefit : kMetaBigTotalMain);
+  S.counter = meta_at<unsigned long long>(ctx, refit ? kMetaCounterRefit : kMetaCounterMain);
+  return S;
+}
 
 // Enqueue the whole direct-sum sequence (no graph logic here).
 lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const int64_t* off,
@@ -120,42 +154,52 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   using namespace lk;
   uint32_t* lf = (uint32_t*)ctx->loop_flags.p;
   double* xi = (double*)ctx->xi.p;  // [kXiBlocks] partials followed by xi
+  int32_t* rlist = (int32_t*)ctx->refit_list.p;
+  int32_t* rn = meta_at<int32_t>(ctx, kMetaRefitN);
+  unsigned long long* acc = (unsigned long long*)ctx->acc.p;
+
+  PlanArgs M{};
+  M.off = off;
+  M.pairs = pairs;
+  M.list = nullptr;
+  M.n_list_dev = nullptr;
+  M.n_list = n_pairs;
+  M.acc = acc;
+  M.flags = flags;
+  M.chunk = P.chunk;
+  M.bblock = lk::kWave * (P.mixed ? P.segs : P.segs64);
   DsArgs A{};
   A.xyz = xyz;
-  A.off = off;
-  A.pairs = pairs;
-  A.list = nullptr;
-  A.n_list_dev = nullptr;
-  A.n_list = n_pairs;
-  A.prefix = (const int64_t*)ctx->prefix.p;
-  A.counter = (unsigned long long*)ctx->counter.p;
-  A.acc = (unsigned long long*)ctx->acc.p;
+  A.s = make_sched(ctx, n_pairs, false);
+  A.acc = acc;
   A.flags = flags;
   A.tile = P.tile;
   A.chunk = P.chunk;
-  int64_t* counts = (int64_t*)ctx->counts.p;
-  int64_t* prefix = (int64_t*)ctx->prefix.p;
-  int32_t* rlist = (int32_t*)ctx->refit_list.p;
-  int32_t* rn = (int32_t*)ctx->refit_n.p;
+  A.batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
 
-  LK_HIP(launch_loop_flags(xyz, P.in_f64, off, n_loops, xi, xi + kXiBlocks, lf, s));
-  LK_HIP(launch_plan(A, n_loops, lf, counts, false, s));
-  LK_HIP(launch_scan_zero(counts, nullptr, n_pairs, prefix, A.counter, rn, s));
+  LK_HIP(launch_loop_flags(xyz, P.in_f64, off, n_loops, xi, xi + kXiBlocks, lf, A.s.counts, s));
+  LK_HIP(launch_plan(M, n_loops, lf, A.s, false, s));
+  LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
   if (timed) LK_HIP(hipEventRecord(ev[0], s));
-  LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.grid : P.grid64, s));
+  LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
+                           P.mixed ? P.grid : P.grid64, s));
   if (timed) LK_HIP(hipEventRecord(ev[1], s));
-  LK_HIP(launch_finalize(A, ctx->refit_thr, lk_real, lk_int, P.mixed ? rlist : nullptr,
+  LK_HIP(launch_finalize(M, ctx->refit_thr, lk_real, lk_int, P.mixed ? rlist : nullptr,
                          P.mixed ? rn : nullptr, false, s));
   if (P.mixed) {
-    DsArgs R = A;
+    PlanArgs R = M;
     R.list = rlist;
     R.n_list_dev = rn;
-    R.tile = default_tile(true);
     R.chunk = default_chunk(true);
-    LK_HIP(launch_plan(R, n_loops, lf, counts, true, s));
-    LK_HIP(launch_scan(counts, rn, n_pairs, prefix, R.counter, s));
+    R.bblock = lk::kWave * P.segs64;
+    DsArgs B = A;
+    B.s = make_sched(ctx, n_pairs, true);
+    B.tile = default_tile(true);
+    B.chunk = default_chunk(true);
+    LK_HIP(launch_plan(R, n_loops, lf, B.s, true, s));
+    LK_HIP(launch_sched(B.s, nullptr, s));
     if (timed) LK_HIP(hipEventRecord(ev[2], s));
-    LK_HIP(launch_direct_sum(R, P.in_f64, true, 0, P.grid64, s));
+    LK_HIP(launch_direct_sum(B, P.in_f64, true, 0, P.segs64, P.grid_refit, s));
     if (timed) LK_HIP(hipEventRecord(ev[3], s));
     LK_HIP(launch_finalize(R, ctx->refit_thr, lk_real, lk_int, nullptr, nullptr, true, s));
   }
@@ -202,9 +246,9 @@ void lk_destroy(lk_ctx* ctx) {
   hipDeviceSynchronize();
   for (auto& kv : ctx->graphs)
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-  DevBuf* bufs[] = {&ctx->loop_flags, &ctx->xi,      &ctx->counts,     &ctx->prefix,
-                    &ctx->counter,    &ctx->acc,     &ctx->flags,      &ctx->refit_list,
-                    &ctx->refit_n,    &ctx->boxes,   &ctx->vcounts,    &ctx->vprefix};
+  DevBuf* bufs[] = {&ctx->loop_flags, &ctx->xi,    &ctx->recs,       &ctx->big_prefix,
+                    &ctx->meta,       &ctx->acc,   &ctx->flags,      &ctx->refit_list,
+                    &ctx->boxes,      &ctx->vcounts, &ctx->vprefix};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -256,6 +300,20 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "atan form must be 0 or 1");
       ctx->opt_atan = (int)v;
       break;
+    case LK_OPT_SEGS_PER_LANE:
+      if (v != 0 && v != 1 && v != 2 && v != 4)
+        return ctx->fail(LK_EINVAL, "segments per lane must be 0, 1, 2 or 4");
+      ctx->opt_segs = (int)v;
+      break;
+    case LK_OPT_SMALL_BATCH:
+      if (v < 0 || v > 64) return ctx->fail(LK_EINVAL, "small-pair batch must be in [0, 64]");
+      ctx->opt_batch = (int)v;
+      break;
+    case LK_OPT_SEGS_PER_LANE_F64:
+      if (v != 0 && v != 1 && v != 2)
+        return ctx->fail(LK_EINVAL, "FP64 segments per lane must be 0, 1 or 2");
+      ctx->opt_segs64 = (int)v;
+      break;
     default:
       return ctx->fail(LK_EINVAL, "unknown option %d", key);
   }
@@ -294,18 +352,23 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   P.chunk = mixed ? (ctx->opt_chunk ? ctx->opt_chunk : default_chunk(false)) : default_chunk(true);
   if (!mixed && ctx->opt_chunk) P.chunk = ctx->opt_chunk;
   if (P.chunk % P.tile) P.chunk = ((P.chunk + P.tile - 1) / P.tile) * P.tile;
-  P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.tile, ctx->n_cu, ctx->opt_waves);
-  P.grid64 = lk::direct_sum_grid(in_f64, true, 0, default_tile(true), ctx->n_cu, ctx->opt_waves);
+  P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32);
+  P.segs64 = lk::segs_supported(true, ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64);
+  P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.segs, P.tile, ctx->n_cu,
+                               ctx->opt_waves);
+  P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, default_tile(true), ctx->n_cu,
+                                 ctx->opt_waves);
+  // refits are rare: a small persistent grid keeps the empty refit pass cheap
+  P.grid_refit = 2 * ctx->n_cu < P.grid64 ? 2 * ctx->n_cu : P.grid64;
 
   // workspace
   if ((st = ensure(ctx, ctx->loop_flags, 4 * (size_t)n_loops)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kXiBlocks + 1))) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->counts, 8 * (size_t)n_pairs)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->counter, 8)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->recs, 3 * sizeof(lk::WorkRec) * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->big_prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->meta, kMetaBytes)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->acc, 16 * (size_t)n_pairs)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->refit_list, 4 * (size_t)n_pairs)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->refit_n, 4)) != LK_OK) return st;
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
     flags = (uint32_t*)ctx->flags.p;
@@ -315,6 +378,7 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   ctx->stats.chunk_a = P.chunk;
   ctx->stats.waves_per_cu = P.grid / (ctx->n_cu > 0 ? ctx->n_cu : 1);
   ctx->stats.atan_form = P.atan_form;
+  ctx->stats.segs_per_lane = mixed ? P.segs : P.segs64;
   ctx->last_stream = s;
   ctx->last_mixed = mixed;
   ctx->last_timed = false;
@@ -342,7 +406,9 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
     return st;
   }
   GraphKey key{xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int, flags,
-               P.tile, P.chunk, P.grid, P.atan_form, (int64_t)(ctx->refit_thr * 1e9)};
+               P.tile, P.chunk, P.grid,
+               ctx->opt_batch * 1024 + P.atan_form * 16 + P.segs * 4 + P.segs64,
+               (int64_t)(ctx->refit_thr * 1e9)};
   auto it = ctx->graphs.find(key);
   if (it != ctx->graphs.end() && it->second.epoch == ctx->ws_epoch && it->second.exec) {
     LK_HIP(hipGraphLaunch(it->second.exec, s));
@@ -382,10 +448,10 @@ lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
   if (!ctx || !out) return LK_EINVAL;
   lk_status st = set_device(ctx);
   if (st != LK_OK) return st;
-  if (ctx->last_mixed && ctx->refit_n.p) {
+  if (ctx->last_mixed && ctx->meta.p) {
     LK_HIP(hipStreamSynchronize(ctx->last_stream));
     int32_t rn = 0;
-    LK_HIP(hipMemcpy(&rn, ctx->refit_n.p, 4, hipMemcpyDeviceToHost));
+    LK_HIP(hipMemcpy(&rn, meta_at<int32_t>(ctx, kMetaRefitN), 4, hipMemcpyDeviceToHost));
     ctx->stats.refits = rn;
   }
   if (ctx->timing && ctx->ring_count > 0) {
@@ -429,7 +495,7 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
   int64_t* pre = (int64_t*)ctx->vprefix.p;
   LK_HIP(lk::launch_boxes(xyz, dtype == LK_F64, off, n_loops, boxes, s));
   LK_HIP(lk::launch_pair_count(boxes, n_loops, cnt, s));
-  LK_HIP(lk::launch_scan(cnt, nullptr, n_loops, pre, nullptr, s));
+  LK_HIP(lk::launch_scan(cnt, n_loops, pre, s));
   int64_t total = 0;
   LK_HIP(hipMemcpyAsync(&total, pre + n_loops, 8, hipMemcpyDeviceToHost, s));
   LK_HIP(hipStreamSynchronize(s));
@@ -464,7 +530,7 @@ lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_
   int64_t* flag = (int64_t*)ctx->vcounts.p;
   int64_t* pre = (int64_t*)ctx->vprefix.p;
   LK_HIP(lk::launch_verify(pairs, lk, n, exp_pairs, exp_lk, n_exp, flag, s));
-  LK_HIP(lk::launch_scan(flag, nullptr, m, pre, nullptr, s));
+  LK_HIP(lk::launch_scan(flag, m, pre, s));
   int64_t total = 0;
   LK_HIP(hipMemcpyAsync(&total, pre + m, 8, hipMemcpyDeviceToHost, s));
   LK_HIP(hipStreamSynchronize(s));
