@@ -436,13 +436,26 @@ def _resample_closed(P: np.ndarray, n: int) -> np.ndarray:
     return out
 
 
+def _star_outline(phi, a, psi, b, chi, k, petals, amp, pphase):
+    """Unit-scale star-shaped outline: polar radius and height as functions of
+    the angle phi (arrays evaluated mode by mode to keep memory flat)."""
+    r = 1.0 + amp * np.cos(petals * phi + pphase)
+    z = np.zeros_like(phi)
+    for q in range(k.size):
+        r += a[q] * np.cos(k[q] * phi + psi[q])
+        z += b[q] * np.cos(k[q] * phi + chi[q])
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+
 def winding_pair(seed: int, n_a: int, n_b: int, lk: int, step: float = 1e-3, rho: float = 0.1,
-                 modes: int = 6, dense: int = 4):
+                 modes: int = 6, dense: int = 2):
     """One long closed curve C and a companion D winding ``lk`` times around it.
 
-    C is a smooth random closed curve over a star-shaped planar outline
-    r(phi) = R0 (1 + sum a_k cos(k phi + psi_k)) with a random height
-    z(phi); its length is n_a * step.  D = C + rho (cos(theta) u + sin(theta) v)
+    C is a smooth random closed curve over a star-shaped top view: polar
+    radius R0 (1 + amp cos(K phi) + sum_k a_k cos(k phi + psi_k)) with K petals
+    (which keeps a long curve compact) and a random smooth height z(phi); its
+    length is n_a * step and the petal count is lowered until the radius of
+    curvature stays above 4 rho.  D = C + rho (cos(theta) u + sin(theta) v)
     with u the horizontal normal of C, v = t x u and theta = 2 pi lk s / len.
     With lk = 0, D's top view is a parallel curve of C's simple top view, so
     the two do not link; each full turn of theta adds one: Lk(C, D) = +lk for
@@ -450,23 +463,32 @@ def winding_pair(seed: int, n_a: int, n_b: int, lk: int, step: float = 1e-3, rho
     """
     rng = np.random.default_rng(seed)
     k = np.arange(2, modes + 2)
-    a = rng.uniform(0.0, 0.3, size=k.size) / k
+    a = rng.uniform(0.0, 0.15, size=k.size) / k
     psi = rng.uniform(0, 2 * np.pi, size=k.size)
     b = rng.uniform(0.0, 0.15, size=k.size) / k
     chi = rng.uniform(0, 2 * np.pi, size=k.size)
+    amp = 0.25
+    pphase = rng.uniform(0, 2 * np.pi)
+    length = n_a * step
+    # pick the petal count on a coarse sampling: largest K whose curve, scaled
+    # to the target length, keeps every radius of curvature above 4 rho
+    coarse = 2 * np.pi * np.arange(20000) / 20000
+    petals = 24
+    while True:
+        P = _star_outline(coarse, a, psi, b, chi, k, petals, amp, pphase)
+        Q = np.vstack([P, P[:1]])
+        R0 = length / np.sum(np.linalg.norm(np.diff(Q, axis=0), axis=1))
+        X = R0 * P
+        d1 = (np.roll(X, -1, 0) - np.roll(X, 1, 0)) / 2
+        d2 = np.roll(X, -1, 0) - 2 * X + np.roll(X, 1, 0)
+        curv = np.linalg.norm(np.cross(d1, d2), axis=1) / np.linalg.norm(d1, axis=1) ** 3
+        if petals <= 3 or 1.0 / curv.max() > 4 * rho:
+            break
+        petals -= 1
     m = dense * max(n_a, n_b)
     phi = 2 * np.pi * np.arange(m) / m
-
-    def shape(R0):
-        r = R0 * (1 + np.sum(a[:, None] * np.cos(k[:, None] * phi[None, :] + psi[:, None]), 0))
-        z = R0 * np.sum(b[:, None] * np.cos(k[:, None] * phi[None, :] + chi[:, None]), 0)
-        return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
-
-    P1 = shape(1.0)
-    len1 = np.sum(np.linalg.norm(np.diff(np.vstack([P1, P1[:1]]), axis=0), axis=1))
-    R0 = n_a * step / len1
-    P = shape(R0)
-    C = _resample_closed(P, m)
+    C = R0 * _star_outline(phi, a, psi, b, chi, k, petals, amp, pphase)
+    C = _resample_closed(C, m)
     t = np.roll(C, -1, 0) - np.roll(C, 1, 0)
     t /= np.linalg.norm(t, axis=1)[:, None]
     u = np.stack([-t[:, 1], t[:, 0], 0 * t[:, 0]], 1)
@@ -483,20 +505,23 @@ def long_pairs(seed: int = 0, n_pairs: int = 16, n_min: int = 1 << 18, n_max: in
                lk_max: int = 5, step: float = 1e-3, rho: float = 0.1, dtype=np.float32) -> LoopSet:
     """Long-loop stress test: ``n_pairs`` pairs (C_k, D_k), each loop with a
     seeded size in [n_min, n_max] segments of length ~step, D_k winding a seeded
-    number of turns in [-lk_max, lk_max] around C_k.  Pairs are placed far
-    apart; the candidate list is the n_pairs (C_k, D_k) pairs."""
+    number of turns in [-lk_max, lk_max] around C_k.  Pairs sit on a square
+    grid around the origin (coordinates stay small, so FP32 resolves the
+    steps); the candidate list is the n_pairs (C_k, D_k) pairs."""
     rng = np.random.default_rng(seed)
-    loops, exp, pairs = [], {}, []
-    x = 0.0
+    made = []
     for q in range(n_pairs):
         na = int(rng.integers(n_min, n_max + 1))
         nb = int(np.clip(na + rng.integers(-na // 16, na // 16 + 1), n_min, n_max))
         target = int(rng.integers(-lk_max, lk_max + 1))
         C, D, val = winding_pair(int(rng.integers(1 << 31)), na, nb, target, step, rho)
-        ext = np.max(np.abs(C[:, :2])) + 2 * rho
-        x += ext
-        off = np.array([x, 0.0, 0.0])
-        x += ext + 1.0
+        made.append((C, D, val))
+    ext = max(float(np.max(np.abs(np.vstack([C[:, :2], D[:, :2]])))) for C, D, _ in made)
+    side = int(np.ceil(np.sqrt(n_pairs)))
+    pitch = 2 * ext + 1.0
+    loops, exp, pairs = [], {}, []
+    for q, (C, D, val) in enumerate(made):
+        off = np.array([(q % side - 0.5 * (side - 1)) * pitch, (q // side - 0.5 * (side - 1)) * pitch, 0.0])
         i = len(loops)
         loops += [C + off, D + off]
         pairs.append([i, i + 1])

@@ -255,3 +255,31 @@ def test_knit_full_size_sampled(ctx):
     err = np.abs(real[pick] - oreal)
     print("knit sampled max |err| %.3e" % err.max(), flush=True)
     assert err.max() <= MIXED_TOL
+
+
+def test_long_pairs_full_size(ctx):
+    """16 pairs of 2^18-2^20-segment loops (~6e12 terms): integers equal the
+    construction; the FP64 plain path on the three smallest pairs agrees with
+    the mixed path; no pair needs a refit."""
+    import torch
+    ls = I.long_pairs(0)
+    xyz, off = _dev(ls)
+    pr = torch.from_numpy(ls.pairs).cuda()
+    real, lk, flags = ctx.direct_sum(xyz, off, pr, "mixed")
+    torch.cuda.synchronize()
+    real, lk, flags = real.cpu().numpy(), lk.cpu().numpy(), flags.cpu().numpy().view(np.uint32)
+    exp = ls.expected_for(ls.pairs)
+    frac = np.abs(real - np.round(real))
+    print("long pairs mixed: lk %s max frac %.3e refits %d" % (lk.tolist(), frac.max(),
+                                                              int(np.sum(flags & 1))), flush=True)
+    assert np.array_equal(lk, exp)
+    cost = ls.sizes[ls.pairs[:, 0]].astype(np.int64) * ls.sizes[ls.pairs[:, 1]]
+    pick = np.argsort(cost)[:3]
+    sub = torch.from_numpy(np.ascontiguousarray(ls.pairs[pick])).cuda()
+    preal, plk, pflags = ctx.direct_sum(xyz, off, sub, "plain")
+    torch.cuda.synchronize()
+    preal = preal.cpu().numpy()
+    err = np.abs(real[pick] - preal)
+    print("long pairs mixed vs plain FP64 (3 smallest): max |diff| %.3e" % err.max(), flush=True)
+    assert np.array_equal(plk.cpu().numpy(), exp[pick])
+    assert err.max() < 1e-3

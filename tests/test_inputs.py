@@ -114,3 +114,12 @@ def test_generators_are_deterministic():
     assert np.array_equal(a.xyz, b.xyz)
     a, b = I.knit(5, n_loops=10, cp_max=32, per_span=2), I.knit(5, n_loops=10, cp_max=32, per_span=2)
     assert np.array_equal(a.xyz, b.xyz)
+
+
+def test_winding_pair_full_length_coarse():
+    # the long-loop recipe at its real length (1000 units) but coarse steps:
+    # the petal outline keeps the construction rule Lk = number of turns
+    C, D, v = I.winding_pair(104, 20000, 21000, -4, step=0.05, rho=0.1)
+    xyz = np.vstack([C, D])
+    real, lk = oracle.direct_sum(xyz, [0, len(C), len(C) + len(D)], [[0, 1]])
+    assert lk[0] == v == -4 and abs(real[0] - v) < 1e-8
