@@ -159,6 +159,104 @@ typedef struct {
   int32_t tile_a, chunk_a, waves_per_cu, atan_form, segs_per_lane; /* configuration used */
 } lk_stats;
 
+/* ------------------------------------------------------------ autotuner */
+typedef struct {
+  int32_t segs_per_lane;     /* FP32 kernel: segments of loop B per lane */
+  int32_t segs_per_lane_f64; /* FP64 kernel: segments of loop B per lane */
+  int32_t tile_a;            /* LDS tile of loop A (vertices) */
+  int32_t chunk_a;           /* vertices of loop A per work item */
+  int32_t small_batch;       /* small pairs per work-counter step */
+  int32_t waves_per_cu;      /* persistent waves per CU (0 = occupancy limit) */
+  int32_t evaluated;         /* configurations timed (0 when read from the cache) */
+  int32_t from_cache;        /* 1 if the configuration came from the cache file */
+  double best_ms;            /* main-kernel time of the chosen configuration */
+  double start_ms;           /* main-kernel time of the configuration tuning started from */
+} lk_tuning;
+
+/* Choose the kernel configuration (work split and tile shapes) for a
+ * workload: times the main direct-sum kernel of this exact call (eager, HIP
+ * events, on `stream`) over a coordinate-descent search of segments per lane,
+ * small-pair batch, LDS tile, A chunk and waves per CU, applies the fastest to
+ * the context (as if set with lk_set_option) and returns it in *out (host).
+ * cache_path (host string, may be NULL): a text file of earlier results keyed
+ * by GPU architecture, mode, dtype and the workload's size profile; a hit is
+ * applied without timing, a new result is appended.  Synchronises; the
+ * output arrays of the call are used as scratch (their contents afterwards
+ * are those of a valid lk_direct_sum). */
+lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* loop_offsets,
+                      int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                      double* lk_real, int32_t* lk_int, uint32_t* flags, const char* cache_path,
+                      lk_tuning* out /* host */, void* stream);
+
+/* Reserve workspace for calls of up to max_loops loops, max_pairs pairs and
+ * max_verify verify entries (n + n_exp), so that later calls within those
+ * sizes never allocate device memory or synchronise the device for growth. */
+lk_status lk_reserve(lk_ctx* ctx, int32_t max_loops, int64_t max_pairs, int64_t max_verify);
+
+/* -------------------------------------------------------------- serving */
+/* A verification server for streams of timesteps (the per-frame use of
+ * Sec. 3.1's certificate comparison: compute the linking matrix of a new
+ * state and compare it with the stored one).  Requests are queued, admitted
+ * in arrival order when a slot is free and the device-memory budget allows,
+ * and run concurrently on the slots (one context, HIP stream and host thread
+ * each), so work of requests that arrive while others run overlaps on the
+ * device.  Each request runs lk_build_pairs, lk_direct_sum and lk_verify
+ * against its session's expected matrix.  A request's results do not depend
+ * on what else runs (fixed configuration, fixed-point pair sums). */
+typedef struct lk_server lk_server;
+
+enum { LK_MEM_HOST = 0, LK_MEM_DEVICE = 1 };
+
+typedef struct {
+  int64_t id;          /* request id */
+  int32_t status;      /* lk_status of the request's calls */
+  int32_t slot;        /* slot that ran it */
+  int64_t n_pairs;     /* candidate pairs found */
+  int64_t n_mismatch;  /* pairs whose integer differs from the session's expectation */
+  int64_t n_flagged;   /* pairs with NONFINITE, BADPAIR, BADLOOP or AMBIGUOUS set */
+  int64_t refits;      /* pairs recomputed in FP64 */
+  double terms;        /* segment-pair terms evaluated */
+  int64_t bytes;       /* device bytes charged to the budget while it ran */
+  double t_submit;     /* seconds (server clock) when submitted */
+  double t_admit;      /* ... when admitted to a slot */
+  double t_done;       /* ... when its results were on the host */
+} lk_result;
+
+/* Create a server on `device` with `slots` concurrent slots (1..8), a device
+ * memory budget in bytes for request data (0 = 80% of free memory), the
+ * direct-sum mode of every request, and per-slot workspace reserved for up to
+ * max_loops loops and max_pairs candidate pairs per request. */
+lk_status lk_server_create(lk_server** out, int device, int32_t slots, int64_t mem_budget,
+                           int mode, int32_t max_loops, int64_t max_pairs);
+/* Stop accepting, finish queued and running requests, free everything. */
+void lk_server_destroy(lk_server* srv);
+const char* lk_server_last_error(const lk_server* srv);
+
+/* A session: the loop structure (offsets, host) and the expected sparse
+ * linking matrix (sorted pairs and values, host) of one simulated object stay
+ * resident on the device for all its timesteps.  Its bytes count against the
+ * budget until it is closed. */
+lk_status lk_server_open_session(lk_server* srv, const int64_t* loop_offsets, int32_t n_loops,
+                                 const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp,
+                                 int64_t* session /* host */);
+lk_status lk_server_close_session(lk_server* srv, int64_t session);
+
+/* Queue one timestep of a session: xyz [V][3] (V = the session's vertex
+ * count) of `dtype`, in host memory (copied to the device when the request
+ * runs) or device memory (used in place).  The caller keeps xyz valid until
+ * the request is done.  Returns immediately with the request id; LK_ECAPACITY
+ * if the request can never fit the budget. */
+lk_status lk_server_submit(lk_server* srv, int64_t session, const void* xyz, int dtype,
+                           int where, int64_t* request_id /* host */);
+
+/* Wait up to timeout_ms (< 0: forever) for a request; LK_EBUSY on timeout.
+ * Fills *res; optionally copies up to `cap` of its pairs, integers, reals and
+ * (up to cap) mismatch records (i, j, got, expected) into host buffers (any
+ * may be NULL).  A request's results can be fetched once. */
+lk_status lk_server_wait(lk_server* srv, int64_t request_id, int32_t timeout_ms, lk_result* res,
+                         int32_t* pairs_out, int32_t* lk_out, double* real_out,
+                         int32_t* mismatches_out, int64_t cap);
+
 /* Statistics of the last lk_direct_sum on this context.  Reading refits and
  * the timings synchronises the stream of that call; the timed calls must all
  * have been issued on that stream. */

@@ -141,6 +141,28 @@ class Context:
                                            _ptr(lk), _ptr(flags), _stream(self.device)))
         return real, lk, flags
 
+    def autotune(self, xyz, offsets, pairs, mode: str = "mixed", cache_path: str | None = None,
+                 out=None) -> dict:
+        """Time kernel configurations on this call and keep the fastest
+        (lk_autotune); returns the chosen configuration and its timings."""
+        torch = _torch()
+        self._dev(xyz, None, "xyz")
+        self._dev(offsets, torch.int64, "offsets")
+        self._dev(pairs, torch.int32, "pairs")
+        P = pairs.shape[0]
+        if out is None:
+            out = (torch.empty(P, dtype=torch.float64, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device))
+        t = _lib.Tuning()
+        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        self._check(self.lib.lk_autotune(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets),
+                                         offsets.numel() - 1, _ptr(pairs), P, m, _ptr(out[0]),
+                                         _ptr(out[1]), _ptr(out[2]),
+                                         cache_path.encode() if cache_path else None,
+                                         ctypes.byref(t), _stream(self.device)))
+        return {k: getattr(t, k) for k, _ in t._fields_}
+
     def verify(self, pairs, lk, exp_pairs, exp_lk, early_exit: bool = False, cap: int = 1024):
         """Compare (pairs, lk) with (exp_pairs, exp_lk); returns
         ``(n_mismatch, records int32 [k, 4] on the device)`` with records

@@ -25,7 +25,11 @@ OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 
 OPT_SMALL_BATCH = 10
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
-           "lk_verify", "lk_set_option", "lk_get_stats"]
+           "lk_verify", "lk_set_option", "lk_get_stats", "lk_autotune", "lk_reserve",
+           "lk_server_create", "lk_server_destroy", "lk_server_last_error",
+           "lk_server_open_session", "lk_server_close_session", "lk_server_submit",
+           "lk_server_wait"]
+MEM_HOST, MEM_DEVICE = 0, 1
 
 
 class Stats(ctypes.Structure):
@@ -34,6 +38,23 @@ class Stats(ctypes.Structure):
                 ("timed_calls", ctypes.c_int32), ("graph_replayed", ctypes.c_int32), ("tile_a", ctypes.c_int32),
                 ("chunk_a", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("segs_per_lane", ctypes.c_int32), ("segs_per_lane_f64", ctypes.c_int32),
+                ("tile_a", ctypes.c_int32), ("chunk_a", ctypes.c_int32),
+                ("small_batch", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("evaluated", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("start_ms", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("n_pairs", ctypes.c_int64), ("n_mismatch", ctypes.c_int64),
+                ("n_flagged", ctypes.c_int64), ("refits", ctypes.c_int64),
+                ("terms", ctypes.c_double), ("bytes", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
 class LkError(RuntimeError):
@@ -51,6 +72,12 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblk.so is not built (%s); run `python -m "
                                "paper_2106_12655_amd.build`" % LIB_PATH)
+        # One HIP runtime per process: torch ships its own libamdhip64 and
+        # loads it into the global symbol scope, so importing torch first makes
+        # liblk.so's HIP calls bind to that same runtime (device memory and
+        # stream handles are then shared objects).  Loading liblk.so first
+        # would start a second runtime that torch's cannot coexist with.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         p, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
         lib.lk_create.argtypes = [ctypes.POINTER(p), ctypes.c_int]
@@ -71,6 +98,27 @@ def load():
         lib.lk_set_option.restype = st
         lib.lk_get_stats.argtypes = [p, ctypes.POINTER(Stats)]
         lib.lk_get_stats.restype = st
+        lib.lk_autotune.argtypes = [p, p, ctypes.c_int, p, i32, p, i64, ctypes.c_int, p, p, p,
+                                    ctypes.c_char_p, ctypes.POINTER(Tuning), p]
+        lib.lk_autotune.restype = st
+        lib.lk_reserve.argtypes = [p, i32, i64, i64]
+        lib.lk_reserve.restype = st
+        lib.lk_server_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, i32, i64, ctypes.c_int,
+                                         i32, i64]
+        lib.lk_server_create.restype = st
+        lib.lk_server_destroy.argtypes = [p]
+        lib.lk_server_destroy.restype = None
+        lib.lk_server_last_error.argtypes = [p]
+        lib.lk_server_last_error.restype = ctypes.c_char_p
+        lib.lk_server_open_session.argtypes = [p, p, i32, p, p, i64, ctypes.POINTER(ctypes.c_int64)]
+        lib.lk_server_open_session.restype = st
+        lib.lk_server_close_session.argtypes = [p, i64]
+        lib.lk_server_close_session.restype = st
+        lib.lk_server_submit.argtypes = [p, i64, p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int64)]
+        lib.lk_server_submit.restype = st
+        lib.lk_server_wait.argtypes = [p, i64, i32, ctypes.POINTER(Result), p, p, p, p, i64]
+        lib.lk_server_wait.restype = st
         _lib = lib
         return lib
 

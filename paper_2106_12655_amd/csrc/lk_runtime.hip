@@ -12,7 +12,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -206,6 +209,39 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   return LK_OK;
 }
 
+// Kernel configuration of a call from the context's options (0 = default).
+Plan make_plan(lk_ctx* ctx, bool in_f64, bool mixed) {
+  Plan P;
+  P.in_f64 = in_f64;
+  P.mixed = mixed;
+  P.atan_form = ctx->opt_atan;
+  const int tmax = mixed ? lk::kMaxTileF32 : lk::kMaxTileF64;
+  P.tile = ctx->opt_tile ? (ctx->opt_tile < tmax ? ctx->opt_tile : tmax) : default_tile(!mixed);
+  P.chunk = ctx->opt_chunk ? ctx->opt_chunk : default_chunk(!mixed);
+  if (P.chunk % P.tile) P.chunk = ((P.chunk + P.tile - 1) / P.tile) * P.tile;
+  P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32);
+  P.segs64 = lk::segs_supported(true, ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64);
+  P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.segs, P.tile, ctx->n_cu,
+                               ctx->opt_waves);
+  P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, mixed ? default_tile(true) : P.tile,
+                                 ctx->n_cu, ctx->opt_waves);
+  // refits are rare: a small persistent grid keeps the empty refit pass cheap
+  P.grid_refit = 2 * ctx->n_cu < P.grid64 ? 2 * ctx->n_cu : P.grid64;
+  return P;
+}
+
+lk_status ensure_workspace(lk_ctx* ctx, int32_t n_loops, int64_t n_pairs) {
+  lk_status st;
+  if ((st = ensure(ctx, ctx->loop_flags, 4 * (size_t)n_loops)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kXiBlocks + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->recs, 3 * sizeof(lk::WorkRec) * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->big_prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->meta, kMetaBytes)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->acc, 16 * (size_t)n_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->refit_list, 4 * (size_t)n_pairs)) != LK_OK) return st;
+  return LK_OK;
+}
+
 bool check_dtype(int d) { return d == LK_F32 || d == LK_F64; }
 
 lk_status set_device(lk_ctx* ctx) {
@@ -344,31 +380,8 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
 
   const bool in_f64 = dtype == LK_F64;
   const bool mixed = mode == LK_MIXED;
-  Plan P;
-  P.in_f64 = in_f64;
-  P.mixed = mixed;
-  P.atan_form = ctx->opt_atan;
-  P.tile = mixed ? (ctx->opt_tile ? ctx->opt_tile : default_tile(false)) : default_tile(true);
-  P.chunk = mixed ? (ctx->opt_chunk ? ctx->opt_chunk : default_chunk(false)) : default_chunk(true);
-  if (!mixed && ctx->opt_chunk) P.chunk = ctx->opt_chunk;
-  if (P.chunk % P.tile) P.chunk = ((P.chunk + P.tile - 1) / P.tile) * P.tile;
-  P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32);
-  P.segs64 = lk::segs_supported(true, ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64);
-  P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.segs, P.tile, ctx->n_cu,
-                               ctx->opt_waves);
-  P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, default_tile(true), ctx->n_cu,
-                                 ctx->opt_waves);
-  // refits are rare: a small persistent grid keeps the empty refit pass cheap
-  P.grid_refit = 2 * ctx->n_cu < P.grid64 ? 2 * ctx->n_cu : P.grid64;
-
-  // workspace
-  if ((st = ensure(ctx, ctx->loop_flags, 4 * (size_t)n_loops)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kXiBlocks + 1))) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->recs, 3 * sizeof(lk::WorkRec) * (size_t)n_pairs)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->big_prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->meta, kMetaBytes)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->acc, 16 * (size_t)n_pairs)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->refit_list, 4 * (size_t)n_pairs)) != LK_OK) return st;
+  const Plan P = make_plan(ctx, in_f64, mixed);
+  if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
     flags = (uint32_t*)ctx->flags.p;
@@ -376,7 +389,7 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
 
   ctx->stats.tile_a = P.tile;
   ctx->stats.chunk_a = P.chunk;
-  ctx->stats.waves_per_cu = P.grid / (ctx->n_cu > 0 ? ctx->n_cu : 1);
+  ctx->stats.waves_per_cu = (mixed ? P.grid : P.grid64) / (ctx->n_cu > 0 ? ctx->n_cu : 1);
   ctx->stats.atan_form = P.atan_form;
   ctx->stats.segs_per_lane = mixed ? P.segs : P.segs64;
   ctx->last_stream = s;
@@ -547,4 +560,196 @@ lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_
   return LK_OK;
 }
 
+lk_status lk_reserve(lk_ctx* ctx, int32_t max_loops, int64_t max_pairs, int64_t max_verify) {
+  if (!ctx) return LK_EINVAL;
+  if (max_loops < 1 || max_pairs < 1 || max_verify < 0)
+    return ctx->fail(LK_EINVAL, "bad reservation sizes");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  if ((st = ensure_workspace(ctx, max_loops, max_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->flags, 4 * (size_t)max_pairs)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->boxes, 48 * (size_t)max_loops)) != LK_OK) return st;
+  const int64_t nv = max_verify > max_loops ? max_verify : max_loops;
+  if ((st = ensure(ctx, ctx->vcounts, 8 * (size_t)nv)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->vprefix, 8 * (size_t)(nv + 1))) != LK_OK) return st;
+  return LK_OK;
+}
+
+lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                      int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                      double* lk_real, int32_t* lk_int, uint32_t* flags, const char* cache_path,
+                      lk_tuning* out, void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (!out) return ctx->fail(LK_EINVAL, "null output");
+  if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED) return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
+  if (n_loops < 1 || n_pairs < 1 || n_pairs > 0x7fffffffLL)
+    return ctx->fail(LK_EINVAL, "need n_loops >= 1 and 1 <= n_pairs < 2^31");
+  if (!xyz || !off || !pairs || !lk_real || !lk_int)
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const bool in_f64 = dtype == LK_F64;
+  const bool mixed = mode == LK_MIXED;
+  *out = lk_tuning{};
+
+  // workload profile, read once from the device
+  std::vector<int64_t> ho((size_t)n_loops + 1);
+  std::vector<int32_t> hp(2 * (size_t)n_pairs);
+  LK_HIP(hipStreamSynchronize(s));
+  LK_HIP(hipMemcpy(ho.data(), off, 8 * ho.size(), hipMemcpyDeviceToHost));
+  LK_HIP(hipMemcpy(hp.data(), pairs, 4 * hp.size(), hipMemcpyDeviceToHost));
+  double terms = 0.0, max_terms = 0.0;
+  int64_t n_small = 0, n_big = 0;
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    const int32_t i = hp[2 * q], j = hp[2 * q + 1];
+    if (i < 0 || j < 0 || i >= n_loops || j >= n_loops || i == j) continue;
+    const double na = (double)(ho[i + 1] - ho[i]), nb = (double)(ho[j + 1] - ho[j]);
+    terms += na * nb;
+    max_terms = std::max(max_terms, na * nb);
+    if (na < lk::kSmallA && nb <= 256) ++n_small; else ++n_big;
+  }
+  hipDeviceProp_t prop;
+  LK_HIP(hipGetDeviceProperties(&prop, ctx->device));
+  char key[512];
+  snprintf(key, sizeof(key), "%s|mode%d|dtype%d|L%d|P%lld|V%lld|T%.3e|max%.3e|small%lld",
+           prop.gcnArchName, mode, dtype, n_loops, (long long)n_pairs,
+           (long long)(ho[n_loops] - ho[0]), terms, max_terms, (long long)n_small);
+
+  auto apply = [&](const lk_tuning& t) {
+    ctx->opt_segs = t.segs_per_lane;
+    ctx->opt_segs64 = t.segs_per_lane_f64;
+    ctx->opt_tile = t.tile_a;
+    ctx->opt_chunk = t.chunk_a;
+    ctx->opt_batch = t.small_batch;
+    ctx->opt_waves = t.waves_per_cu;
+    for (auto& kv : ctx->graphs)
+      if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    ctx->graphs.clear();
+  };
+
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      lk_tuning t{};
+      if (ls >> k >> t.segs_per_lane >> t.segs_per_lane_f64 >> t.tile_a >> t.chunk_a >>
+          t.small_batch >> t.waves_per_cu >> t.best_ms >> t.start_ms) {
+        if (k == key) {
+          t.from_cache = 1;
+          apply(t);
+          *out = t;
+          return LK_OK;
+        }
+      }
+    }
+  }
+
+  if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
+  if (!flags) {
+    if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
+    flags = (uint32_t*)ctx->flags.p;
+  }
+  hipEvent_t ev[4];
+  for (auto& e : ev) LK_HIP(hipEventCreate(&e));
+  struct Guard {
+    hipEvent_t* e;
+    ~Guard() {
+      for (int k = 0; k < 4; ++k) hipEventDestroy(e[k]);
+    }
+  } guard{ev};
+
+  // start from the current options, filled with the defaults
+  lk_tuning cur{};
+  cur.segs_per_lane = ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32;
+  cur.segs_per_lane_f64 = ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64;
+  cur.tile_a = ctx->opt_tile ? ctx->opt_tile : default_tile(!mixed);
+  cur.chunk_a = ctx->opt_chunk ? ctx->opt_chunk : default_chunk(!mixed);
+  cur.small_batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
+  cur.waves_per_cu = ctx->opt_waves;
+  int evaluated = 0;
+  auto measure = [&](const lk_tuning& t, double* ms) -> lk_status {
+    apply(t);
+    const Plan P = make_plan(ctx, in_f64, mixed);
+    double best = 1e30;
+    int reps = 3;
+    for (int r = 0; r <= reps; ++r) {
+      lk_status e = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
+                                       flags, s, ev);
+      if (e != LK_OK) return e;
+      LK_HIP(hipStreamSynchronize(s));
+      float k = 0.f;
+      LK_HIP(hipEventElapsedTime(&k, ev[0], ev[1]));
+      if (r == 0) {
+        if (k > 50.f) reps = 1;  // long calls: one timed repetition after the warm-up
+        continue;
+      }
+      best = std::min(best, (double)k);
+    }
+    ++evaluated;
+    *ms = best;
+    return LK_OK;
+  };
+  double cur_ms = 0.0;
+  if ((st = measure(cur, &cur_ms)) != LK_OK) return st;
+  const double start_ms = cur_ms;
+
+  auto sweep = [&](int32_t lk_tuning::*field, std::initializer_list<int32_t> values) -> lk_status {
+    for (int32_t v : values) {
+      if (cur.*field == v) continue;
+      lk_tuning t = cur;
+      t.*field = v;
+      double ms = 0.0;
+      lk_status e = measure(t, &ms);
+      if (e != LK_OK) return e;
+      if (ms < cur_ms * 0.99) {  // keep a change only for a clear gain
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+    return LK_OK;
+  };
+  if (mixed) {
+    if ((st = sweep(&lk_tuning::segs_per_lane, {1, 2, 4})) != LK_OK) return st;
+  } else {
+    if ((st = sweep(&lk_tuning::segs_per_lane_f64, {1, 2})) != LK_OK) return st;
+  }
+  if (n_small > 0 && (st = sweep(&lk_tuning::small_batch, {1, 2, 4, 8, 16})) != LK_OK) return st;
+  if (n_big > 0) {
+    if (mixed) {
+      if ((st = sweep(&lk_tuning::tile_a, {256, 512, 1024})) != LK_OK) return st;
+    } else {
+      if ((st = sweep(&lk_tuning::tile_a, {128, 256, 512})) != LK_OK) return st;
+    }
+    if ((st = sweep(&lk_tuning::chunk_a, {1024, 2048, 4096, 8192, 16384})) != LK_OK) return st;
+  }
+  if ((st = sweep(&lk_tuning::waves_per_cu, {0, 8, 12})) != LK_OK) return st;
+
+  cur.best_ms = cur_ms;
+  cur.start_ms = start_ms;
+  cur.evaluated = evaluated;
+  apply(cur);
+  // leave the outputs as a valid result of the chosen configuration
+  {
+    const Plan P = make_plan(ctx, in_f64, mixed);
+    if ((st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
+                                 flags, s, nullptr)) != LK_OK)
+      return st;
+    LK_HIP(hipStreamSynchronize(s));
+  }
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << key << " " << cur.segs_per_lane << " " << cur.segs_per_lane_f64 << " " << cur.tile_a
+      << " " << cur.chunk_a << " " << cur.small_batch << " " << cur.waves_per_cu << " "
+      << cur.best_ms << " " << cur.start_ms << "\n";
+  }
+  *out = cur;
+  return LK_OK;
+}
+
 }  // extern "C"
+

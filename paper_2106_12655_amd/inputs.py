@@ -189,8 +189,9 @@ def ring_grid(seed: int = 0, rows: int = 8, cols: int = 8, nseg: int = 32, spaci
 # -------------------------------------------------------- 4-in-1 chainmail (C2)
 def chainmail(seed: int = 0, rows: int = 100, cols: int = 140, nseg: int = 64,
               spacing: float = 1.1, tilt_deg: float = 40.0, sheet_deg: float = 45.0,
+              row_pitch: float | None = None,
               wobble_deg: float = 5.0, sigma: float = 0.01, dtype=np.float32,
-              pulled: np.ndarray | None = None) -> LoopSet:
+              pulled_rings=None, noise_seed: int | None = None) -> LoopSet:
     """European 4-in-1 chainmail sheet of unit rings.
 
     Ring (r, c) is centred at ((c + (r mod 2)/2) * spacing, r * spacing, 0) and
@@ -205,10 +206,13 @@ def chainmail(seed: int = 0, rows: int = 100, cols: int = 140, nseg: int = 64,
     (r, c) links ring (r+1, c) and ring (r+1, c - 1 + 2 (r mod 2)); the pair has
     +1 when r is even and -1 when r is odd, all other pairs 0.
 
-    ``pulled``: optional boolean mask over the expected-link list (same order as
-    ``exp_pairs``); for each selected pair the upper ring is pulled through the
-    lower one (its piercing arc detours around the lower ring's wire), which
-    makes that pair's linking number 0 and leaves the others unchanged.
+    ``pulled_rings``: ring indices of the first or last row to pull out of the
+    sheet: each slides rigidly outwards in its own plane (away from the
+    sheet, parallel to its same-row neighbours) through the wires of the two
+    rings it hangs from, until it clears them by 0.4; both of its links become
+    0 and no other pair changes.  ``meta["pulled"]`` lists the changed pairs.
+    ``noise_seed``: seed of the per-vertex noise (default ``seed``), so that
+    timesteps of one sheet share its structure and differ in the noise.
     """
     rng = np.random.default_rng(seed)
     base = circle(nseg)
@@ -216,7 +220,7 @@ def chainmail(seed: int = 0, rows: int = 100, cols: int = 140, nseg: int = 64,
     centres, frames = [], []
     for r in range(rows):
         for c in range(cols):
-            ctr = np.array([(c + 0.5 * (r % 2)) * spacing, r * spacing, 0.0])
+            ctr = np.array([(c + 0.5 * (r % 2)) * spacing, r * (row_pitch or spacing), 0.0])
             R = rot_y(np.deg2rad(tilt_deg if r % 2 == 0 else -tilt_deg))
             centres.append(Rs @ ctr)
             frames.append(Rs @ R)
@@ -233,55 +237,86 @@ def chainmail(seed: int = 0, rows: int = 100, cols: int = 140, nseg: int = 64,
                     exp[(r * cols + c, (r + 1) * cols + cc)] = 1 if r % 2 == 0 else -1
     keys = sorted(exp)
     local = [base.copy() for _ in range(L)]
-    if pulled is not None:
-        pulled = np.asarray(pulled, dtype=bool)
-        for k, (i, j) in enumerate(keys):
-            if pulled[k]:
-                local[j] = _pull_through(local[j], centres[i], frames[i], centres[j], frames[j])
-                exp[(i, j)] = 0
+    shift = np.zeros((L, 3))
+    changed = []
+    if pulled_rings is not None:
+        out_dir = Rs @ np.array([0.0, 1.0, 0.0])
+        for b in sorted(set(int(x) for x in pulled_rings)):
+            r, c = divmod(b, cols)
+            if r not in (0, rows - 1) or rows < 2:
+                continue  # only edge rings can slide out of the sheet
+            partners = [i for (i, j) in keys if j == b] + [j for (i, j) in keys if i == b]
+            near = np.nonzero(np.linalg.norm(centres - centres[b], axis=1) < 4.5)[0]
+            others = [int(x) for x in near if x != b and x not in partners]
+            d = _slide_out(local[b], centres[b], frames[b], partners, others, centres, frames,
+                           out_dir if r == rows - 1 else -out_dir)
+            if d is None:
+                continue
+            shift[b] = d
+            for q in partners:
+                key = (min(b, q), max(b, q))
+                exp[key] = 0
+                changed.append(key)
+    nrng = rng if noise_seed is None else np.random.default_rng(noise_seed)
     loops = []
     for l in range(L):
         W = rot_axis(axes[l], angs[l]) @ frames[l]
-        P = local[l] @ W.T + centres[l]
-        P = P + rng.normal(0.0, sigma, size=P.shape)
+        P = local[l] @ W.T + centres[l] + shift[l]
+        P = P + nrng.normal(0.0, sigma, size=P.shape)
         loops.append(P)
     return _pack(loops, dtype, exp, "chainmail", seed,
-                 meta={"rows": rows, "cols": cols, "nseg": nseg, "sigma": sigma})
+                 meta={"rows": rows, "cols": cols, "nseg": nseg, "sigma": sigma,
+                       "pulled": np.array(sorted(changed), np.int32).reshape(-1, 2)})
 
 
-def _pull_through(local_b, ca, Fa, cb, Fb, clearance=0.35, width=0.9):
-    """Detour ring B's arc that pierces ring A's disk around A's wire.
+def _circle_distance(P, c, n):
+    """Distance from points P to the unit circle with centre c and normal n."""
+    d = P - c
+    h = d @ n
+    r = np.linalg.norm(d - np.outer(h, n), axis=1)
+    return np.sqrt(h * h + (r - 1.0) ** 2)
 
-    local_b: B's vertices in B's own frame (unit circle).  A's disk is the unit
-    disk of plane (ca, normal Fa[:, 2]).  The vertices of B near the piercing
-    point are pushed, inside A's plane direction, radially outwards from A's
-    centre until they clear A's wire by ``clearance``, with a smooth falloff
-    over an arc of ``width`` radians, so that B no longer crosses A's disk.
-    """
-    n = local_b.shape[0]
+
+def _disk_crossings_signed(world, ca, na):
+    """Signed count of the closed polyline's crossings of the unit disk
+    (centre ca, normal na), and the smallest |radius - 1| of any crossing of
+    the disk's plane (how close a crossing comes to the rim)."""
+    n = world.shape[0]
+    h = (world - ca) @ na
+    h1 = np.roll(h, -1)
+    idx = np.nonzero(h * h1 < 0)[0]
+    if idx.size == 0:
+        return 0, np.inf
+    t = h[idx] / (h[idx] - h1[idx])
+    p = world[idx] + t[:, None] * (np.roll(world, -1, 0)[idx] - world[idx])
+    q = p - ca
+    rr = np.linalg.norm(q - np.outer(q @ na, na), axis=1)
+    inside = rr < 1.0
+    sign = np.where(h1[idx] > h[idx], 1, -1)
+    return int(np.sum(sign[inside])), float(np.min(np.abs(rr - 1.0)))
+
+
+def _slide_out(local_b, cb, Fb, partners, others, centres, frames, direction, keep=0.4):
+    """Slide ring B rigidly along `direction` (in its own plane) until it no
+    longer crosses the disks of its `partners` and stays `keep` away from them
+    and from every ring in `others`.  Returns the offset, or None."""
     world = local_b @ Fb.T + cb
-    na = Fa[:, 2]
-    h = (world - ca) @ na  # signed height over A's plane
-    best, bt = None, None
-    for s in range(n):
-        h0, h1 = h[s], h[(s + 1) % n]
-        if h0 == 0 or h0 * h1 < 0:
-            t = h0 / (h0 - h1) if h0 != h1 else 0.0
-            p = world[s] + t * (world[(s + 1) % n] - world[s])
-            rr = np.linalg.norm((p - ca) - ((p - ca) @ na) * na)
-            if rr < 1.0 and (best is None or rr < best):
-                best, bt = rr, (s, t, p)
-    if bt is None:
-        return local_b
-    s, t, p = bt
-    radial = (p - ca) - ((p - ca) @ na) * na
-    radial = radial / np.linalg.norm(radial)
-    push = 1.0 + clearance - best  # how far the piercing point must move out
-    ang = 2 * np.pi * (np.arange(n) - (s + t)) / n
-    ang = (ang + np.pi) % (2 * np.pi) - np.pi
-    wgt = np.where(np.abs(ang) < width, 0.5 * (1 + np.cos(np.pi * ang / width)), 0.0)
-    moved = world + (push * wgt)[:, None] * radial[None, :]
-    return (moved - cb) @ Fb
+    for dist in np.arange(0.5, 3.01, 0.1):
+        W = world + dist * direction
+        ok = True
+        for c in partners:
+            k, rim = _disk_crossings_signed(W, centres[c], frames[c][:, 2])
+            if k != 0 or rim < 0.1 or _circle_distance(W, centres[c], frames[c][:, 2]).min() < keep:
+                ok = False
+                break
+        if ok:
+            for c in others:
+                if _circle_distance(W, centres[c], frames[c][:, 2]).min() < keep:
+                    ok = False
+                    break
+        if ok:
+            return dist * direction
+    return None
 
 
 # ------------------------------------------------------------- knit tubes (C3)
@@ -357,7 +392,8 @@ def knit_tube(stitches: int, rows: int, per_span: int = 32, pattern: str = "alte
 
 def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512,
          rows_min: int = 5, rows_max: int = 20, per_span: int = 32, linked_fraction: float = 0.2,
-         tilt_deg: float = 35.0, gap: float = 0.3, dtype=np.float32) -> LoopSet:
+         tilt_deg: float = 35.0, gap: float = 0.3, dtype=np.float32, sigma: float = 0.0,
+         pull=None, noise_seed: int | None = None) -> LoopSet:
     """Knit-like tubes of closed periodic cubic B-spline yarn rows.
 
     Each tube has a log-uniform control-point count per row in [cp_min, cp_max]
@@ -370,6 +406,13 @@ def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512
     rotation of up to ``tilt_deg`` off vertical and tubes are packed in a grid
     whose bounding spheres are ``gap`` apart, so axis-aligned boxes of rows of
     the same and of neighbouring tubes overlap without the curves coming close.
+
+    ``pull``: global loop indices of rows whose first clasp is pulled through
+    (its sign reversed), which changes the row's linking number with the row
+    below by -2 times the clasp's sign; the expected values include the change.
+    ``sigma``: per-vertex Gaussian noise added after construction (seeded by
+    ``noise_seed``, default ``seed``); keep it well below the 0.13 clearance
+    between clasping rows.
     """
     rng = np.random.default_rng(seed)
     tubes = []
@@ -407,9 +450,12 @@ def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512
             x += radii[t] + gap
         cursor_y += 2 * h + gap
         k += side
+    pull = set(int(x) for x in (pull or ()))
     for t in range(len(tubes)):
         st, nr, pattern = tubes[t]
-        rows, e = knit_tube(st, nr, per_span, pattern)
+        first = sum(tubes[u][1] for u in range(t))
+        flips = {(g - first, 0) for g in pull if first < g < first + nr}
+        rows, e = knit_tube(st, nr, per_span, pattern, flip=flips or None)
         axis = rng.standard_normal(3)
         axis[2] = 0.0
         Rt = rot_axis(axis, np.deg2rad(rng.uniform(0.0, tilt_deg))) @ rot_z(rng.uniform(0, 2 * np.pi))
@@ -419,8 +465,12 @@ def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512
             loops.append((P - mid) @ Rt.T + place[t])
         for (a, b), v in e.items():
             exp[(base + a, base + b)] = v
+    if sigma > 0:
+        nrng = np.random.default_rng(seed if noise_seed is None else noise_seed)
+        loops = [P + nrng.normal(0.0, sigma, size=P.shape) for P in loops]
     return _pack(loops, dtype, exp, "knit", seed,
-                 meta={"tubes": len(tubes), "per_span": per_span})
+                 meta={"tubes": len(tubes), "per_span": per_span,
+                       "row_starts": [sum(tubes[u][1] for u in range(t)) for t in range(len(tubes))]})
 
 
 # --------------------------------------------------------- long loop pairs (C4)

@@ -283,3 +283,26 @@ def test_long_pairs_full_size(ctx):
     print("long pairs mixed vs plain FP64 (3 smallest): max |diff| %.3e" % err.max(), flush=True)
     assert np.array_equal(plk.cpu().numpy(), exp[pick])
     assert err.max() < 1e-3
+
+
+def test_autotune_picks_a_valid_configuration(ctx, tmp_path):
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    ls = I.chainmail(6, rows=40, cols=40)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    xyz, off = _dev(ls)
+    pr = torch.from_numpy(pairs).cuda()
+    tctx = lk_mod.Context(0)
+    cache = str(tmp_path / "tune.txt")
+    t1 = tctx.autotune(xyz, off, pr, "mixed", cache_path=cache)
+    print("autotune:", t1, flush=True)
+    assert t1["evaluated"] >= 3 and t1["from_cache"] == 0
+    assert t1["best_ms"] <= t1["start_ms"] * 1.05
+    real, lk, flags = tctx.direct_sum(xyz, off, pr, "mixed")
+    torch.cuda.synchronize()
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    assert np.array_equal(lk.cpu().numpy(), olk)
+    assert np.abs(real.cpu().numpy() - oreal).max() < MIXED_TOL
+    t2 = lk_mod.Context(0).autotune(xyz, off, pr, "mixed", cache_path=cache)
+    assert t2["from_cache"] == 1 and t2["segs_per_lane"] == t1["segs_per_lane"]
+    tctx.close()

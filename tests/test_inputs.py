@@ -52,11 +52,24 @@ def test_chainmail_patch_links():
 
 
 def test_chainmail_pull_through_unlinks_only_selected():
-    base = I.chainmail(3, rows=5, cols=6)
-    mask = np.zeros(len(base.exp_pairs), bool)
-    mask[[1, 7, 12]] = True
-    ls = I.chainmail(3, rows=5, cols=6, pulled=mask)
-    assert len(ls.exp_pairs) == len(base.exp_pairs) - 3
+    # edge rings slid out of the sheet: exactly their two links become 0, with
+    # the serving noise level (0.05) on the wider row pitch
+    rows, cols = 6, 7
+    pick = [2, 5, (rows - 1) * cols + 1, (rows - 1) * cols + 4, 3 * cols + 2]  # last one is interior
+    ls = I.chainmail(3, rows=rows, cols=cols, row_pitch=1.25, sigma=0.05, noise_seed=8,
+                     pulled_rings=pick)
+    assert len(ls.meta["pulled"]) == 8
+    base = I.chainmail(3, rows=rows, cols=cols, row_pitch=1.25, sigma=0.0)
+    _check_against_oracle(ls)  # every candidate pair as constructed
+    gone = {tuple(x) for x in base.exp_pairs.tolist()} - {tuple(x) for x in ls.exp_pairs.tolist()}
+    assert gone == {tuple(x) for x in ls.meta["pulled"].tolist()}
+    for i, j in gone:  # pulled pairs are unlinked (their boxes may no longer overlap)
+        assert abs(oracle.pair(ls.loop(i), ls.loop(j))) < 1e-9
+
+
+def test_chainmail_serving_noise_is_safe_on_wide_pitch():
+    # per-vertex noise 0.05 keeps every construction value on the 1.25 pitch
+    ls = I.chainmail(4, rows=12, cols=12, nseg=48, row_pitch=1.25, sigma=0.05, noise_seed=2)
     _check_against_oracle(ls)
 
 
