@@ -13,7 +13,7 @@ Structures" (SIGGRAPH 2021):
 
 * :func:`term` -- Eq. 4 (per segment-pair signed solid angle / 2 pi), as printed.
 * :func:`term_midpoint` -- the midpoint quadrature of Eq. 2.
-* :func:`pair` -- Eq. 3 / Eq. 5 summed in the order of Alg. 5 (Neumaier sums).
+* :func:`pair` -- Eq. 3 summed in the order of Alg. 5 (Neumaier sums).
 * :func:`pair_anglesum` -- the angle-summation evaluation of the appendix (Alg. 7).
 * :func:`direct_sum` -- :func:`pair` over a pair list, threaded over pairs.
 * :func:`loop_flags` -- the zero-length-segment test of Alg. 3 plus finiteness.

@@ -13,7 +13,7 @@
  *                     triangles (a,b,c) and (c,d,a)), divided by 2*pi.
  *   - lko_term_mid:   the midpoint quadrature of Eq. 2 for the same pair
  *                     (inexact; used only as a far-field / sign pin).
- *   - lko_pair:       the double sum of Eq. 3 / Eq. 5 in the order of Alg. 5:
+ *   - lko_pair:       the double sum of Eq. 3 in the order of Alg. 5:
  *                     outer index i over loop k (gamma_2), inner j over loop l
  *                     (gamma_1), with a Neumaier-compensated sum over j per
  *                     row and a Neumaier sum over fixed blocks of rows.
