@@ -4,7 +4,7 @@
  * The library evaluates, for every candidate pair of closed polylines, the
  * exact polyline form of the Gauss linking integral: the sum over all
  * segment pairs of the signed-solid-angle term of Eq. 4 (Sec. 2.1, "Direct
- * Summation Methods"; the double sum of Eq. 5 / Alg. 5, Sec. 3.4.2), reduces it
+ * Summation Methods"; the double sum of Eq. 3 / Alg. 5, Sec. 3.4.2), reduces it
  * to one real number per loop pair and rounds it to the integer linking
  * number.  Around that hot path it offers the potential link search of
  * Alg. 2 (Sec. 3.2) and the before/after comparison with early exit that the
@@ -141,7 +141,9 @@ enum {
   LK_OPT_TILE_A = 4,              /* FP32 LDS tile of loop A in vertices (0 = tuned) */
   LK_OPT_CHUNK_A = 5,             /* vertices of A per work item (0 = tuned) */
   LK_OPT_WAVES_PER_CU = 6,        /* persistent waves per compute unit (0 = occupancy) */
-  LK_OPT_ATAN = 7,                /* FP32 arctangent: 0 = own minimax, 1 = HIP atan2f */
+  LK_OPT_ATAN = 7,                /* FP32 arctangent: 0 = own minimax, the R terms of a step
+                                     in phases; 1 = HIP atan2f; 2 = own minimax, term by
+                                     term (same values as 0, another instruction order) */
   LK_OPT_SEGS_PER_LANE = 8,       /* FP32 kernel: segments of loop B per lane, 1/2/4 (0 = tuned) */
   LK_OPT_SEGS_PER_LANE_F64 = 9,   /* FP64 kernel: segments of loop B per lane, 1/2 (0 = tuned) */
   LK_OPT_SMALL_BATCH = 10         /* small pairs claimed per work-counter step, 1..64 (0 = tuned) */
@@ -171,12 +173,14 @@ typedef struct {
   int32_t from_cache;        /* 1 if the configuration came from the cache file */
   double best_ms;            /* main-kernel time of the chosen configuration */
   double start_ms;           /* main-kernel time of the configuration tuning started from */
+  int32_t atan_form;         /* FP32 arctangent form (LK_OPT_ATAN) */
+  int32_t reserved;
 } lk_tuning;
 
 /* Choose the kernel configuration (work split and tile shapes) for a
  * workload: times the main direct-sum kernel of this exact call (eager, HIP
  * events, on `stream`) over a coordinate-descent search of segments per lane,
- * small-pair batch, LDS tile, A chunk and waves per CU, applies the fastest to
+ * arctangent form, small-pair batch, LDS tile, A chunk and waves per CU, applies the fastest to
  * the context (as if set with lk_set_option) and returns it in *out (host).
  * cache_path (host string, may be NULL): a text file of earlier results keyed
  * by GPU architecture, mode, dtype and the workload's size profile; a hit is

@@ -45,7 +45,8 @@ class Tuning(ctypes.Structure):
                 ("tile_a", ctypes.c_int32), ("chunk_a", ctypes.c_int32),
                 ("small_batch", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("evaluated", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("start_ms", ctypes.c_double)]
+                ("best_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("atan_form", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

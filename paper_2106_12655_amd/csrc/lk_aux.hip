@@ -1,7 +1,6 @@
 // lk_aux.hip -- everything around the direct-sum hot loop: input validation,
-// work planning, the device-side scan, conversion of the fixed-point sums to
-// outputs (round + flag + refit list), the potential link search (Alg. 2) and
-// the verification merge (Sec. 3.1, "Fast Verification").
+// work planning with its device-side schedule, the potential link search
+// (Alg. 2) and the verification merge (Sec. 3.1, "Fast Verification").
 //
 // All sizes that depend on the data (work item totals, the refit count) stay in
 // device memory, so every launch here has a host-known shape and the whole
@@ -15,10 +14,6 @@
 namespace lk {
 namespace {
 
-constexpr uint32_t kFlagRefit = 1u, kFlagAmbiguous = 2u, kFlagNonfinite = 4u, kFlagBadpair = 8u,
-                   kFlagBadloop = 16u;
-constexpr int32_t kIntInvalid = INT32_MIN;
-
 inline int blocks_for(int64_t n, int threads, int cap = 65535 * 8) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -27,14 +22,22 @@ inline int blocks_for(int64_t n, int threads, int cap = 65535 * 8) {
 }
 
 // ------------------------------------------------------------- validation
+// xi partial sums over a flat grid stride (one per block), the per-loop bits
+// that do not depend on xi (fewer than 3 vertices, non-finite coordinates) and
+// each loop's shortest squared segment (one wavefront per loop).  The zero-
+// length test of Alg. 3 (segment shorter than eps * xi) is applied by the plan,
+// which reduces the partials to xi itself.  Block 0 also zeroes the main
+// pass's schedule counts.
 template <typename Tin>
-__global__ __launch_bounds__(256) void xi_partial(const Tin* X, const int64_t* off, int32_t L,
-                                                  double* part) {
+__global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, int32_t L,
+                                              double* part, uint32_t* lf, double* minseg2,
+                                              int32_t* zero_counts) {
   __shared__ double red[256];
+  if (blockIdx.x == 0 && threadIdx.x < 2) zero_counts[threadIdx.x] = 0;
   const int64_t v0 = off[0], v1 = off[L];
-  const int64_t n = 3 * (v1 - v0);
+  const int64_t n3 = 3 * (v1 - v0);
   double s = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n3; k += (int64_t)gridDim.x * 256)
     s += fabs((double)X[3 * v0 + k]);
   red[threadIdx.x] = s;
   __syncthreads();
@@ -43,52 +46,32 @@ __global__ __launch_bounds__(256) void xi_partial(const Tin* X, const int64_t* o
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
 
-__global__ __launch_bounds__(256) void xi_final(const double* part, const int64_t* off, int32_t L,
-                                                double* xi, int32_t* zero_counts) {
-  __shared__ double red[256];
-  red[threadIdx.x] = part[threadIdx.x];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const int64_t nv = off[L] - off[0];
-    *xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
-    if (zero_counts) {
-      zero_counts[0] = 0;
-      zero_counts[1] = 0;
-    }
-  }
-}
-
-// One wavefront per loop: <3 vertices, non-finite coordinates and segments
-// shorter than eps * xi (the zero-length test of Alg. 3).
-template <typename Tin>
-__global__ __launch_bounds__(256) void loop_flags_k(const Tin* X, const int64_t* off, int32_t L,
-                                                    const double* xi, double eps, uint32_t* lf) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
-  const double lim = eps * (*xi);
-  const double lim2 = lim * lim;
   for (int64_t l = wave; l < L; l += nwaves) {
     const int64_t o = off[l], n = off[l + 1] - o;
     uint32_t f = (n < 3) ? kFlagBadloop : 0u;
-    for (int64_t s = lane; s < n; s += 64) {
-      const int64_t t = (s + 1 == n) ? 0 : s + 1;
-      const double x0 = (double)X[3 * (o + s)], y0 = (double)X[3 * (o + s) + 1],
-                   z0 = (double)X[3 * (o + s) + 2];
+    double mn = INFINITY;
+    for (int64_t q = lane; q < n; q += 64) {
+      const int64_t t = (q + 1 == n) ? 0 : q + 1;
+      const double x0 = (double)X[3 * (o + q)], y0 = (double)X[3 * (o + q) + 1],
+                   z0 = (double)X[3 * (o + q) + 2];
       const double x1 = (double)X[3 * (o + t)], y1 = (double)X[3 * (o + t) + 1],
                    z1 = (double)X[3 * (o + t) + 2];
       if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0)) f |= kFlagNonfinite | kFlagBadloop;
       const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
-      if (dx * dx + dy * dy + dz * dz < lim2) f |= kFlagBadloop;
+      mn = fmin(mn, dx * dx + dy * dy + dz * dz);
     }
-    for (int o2 = 32; o2 > 0; o2 >>= 1) f |= (uint32_t)__shfl_xor((int)f, o2);
-    if (lane == 0) lf[l] = f;
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      f |= (uint32_t)__shfl_xor((int)f, o2);
+      mn = fmin(mn, __shfl_xor(mn, o2));
+    }
+    if (lane == 0) {
+      lf[l] = f;
+      minseg2[l] = mn;
+    }
   }
 }
 
@@ -106,49 +89,6 @@ __device__ __forceinline__ int32_t wave_append(int32_t* count, bool pred) {
   base = __shfl(base, leader);
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
   return base + (int32_t)__popcll(m & below);
-}
-
-__global__ __launch_bounds__(256) void plan_k(PlanArgs A, int32_t L, const uint32_t* lf, Sched S,
-                                              int refit) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int64_t n = A.n_list;
-  if (A.n_list_dev) {
-    const int64_t nd = *A.n_list_dev;
-    n = nd < n ? nd : n;
-  }
-  if (q >= n) return;
-  const int32_t p = A.list ? A.list[q] : (int32_t)q;
-  const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
-  const bool valid = i >= 0 && j >= 0 && i < L && j < L && i != j;
-  int64_t items = 0;
-  WorkRec r{};
-  if (valid) {
-    r.oa = A.off[i];
-    r.ob = A.off[j];
-    const int64_t na = A.off[i + 1] - r.oa, nb = A.off[j + 1] - r.ob;
-    r.na = (int32_t)na;
-    r.nb = (int32_t)nb;
-    if (na >= 1 && nb >= 1) items = ((nb + A.bblock - 1) / A.bblock) * ((na + A.chunk - 1) / A.chunk);
-  }
-  // loops beyond 2^31 vertices or pairs beyond 2^31 work items are not handled
-  const bool too_big = valid && (A.off[i + 1] - A.off[i] > 0x7fffffffLL ||
-                                 A.off[j + 1] - A.off[j] > 0x7fffffffLL || items > 0x7fffffffLL);
-  if (too_big) items = 0;
-  if (refit)
-    A.flags[p] = (A.flags[p] & ~kFlagNonfinite) | (too_big ? kFlagNonfinite : 0u);
-  else
-    A.flags[p] = valid ? (lf[i] | lf[j] | (too_big ? kFlagBadloop | kFlagNonfinite : 0u))
-                       : kFlagBadpair;
-  A.acc[2 * (int64_t)p] = 0ull;
-  A.acc[2 * (int64_t)p + 1] = 0ull;
-  r.p = p;
-  r.items = (int32_t)items;
-  const bool small = items == 1 && r.na < kSmallA;
-  const bool big = items > 0 && !small;
-  const int32_t ps = wave_append(&S.counts[0], small);
-  const int32_t pb = wave_append(&S.counts[1], big);
-  if (small) S.small[ps] = r;
-  if (big) S.big_in[pb] = r;
 }
 
 // Exclusive scan of one value per thread over a 1024-thread workgroup
@@ -208,9 +148,9 @@ __device__ int64_t block_scan_array(const int64_t* src, int64_t n, int64_t* dst,
 
 __device__ __forceinline__ int cost_bucket(int32_t items) { return 31 - __clz(items); }
 
-// One workgroup: bucket the big pairs by log2(items), largest bucket first
-// (an LPT order up to a factor of two), then scan their items.
-__global__ __launch_bounds__(1024) void sched_k(Sched S, int32_t* zero_next) {
+// One workgroup (1024 threads): bucket the big pairs by log2(items), largest
+// bucket first (an LPT order up to a factor of two), then scan their items.
+__device__ void schedule(const Sched& S, int32_t* zero_next) {
   __shared__ int hist[32];
   __shared__ int cur[32];
   __shared__ int64_t wsum[16];
@@ -247,64 +187,124 @@ __global__ __launch_bounds__(1024) void sched_k(Sched S, int32_t* zero_next) {
   }
 }
 
-// General single-workgroup exclusive scan (pair search, verification).
-__global__ __launch_bounds__(1024) void scan_k(const int64_t* counts, int64_t n, int64_t* prefix) {
-  __shared__ int64_t wsum[16];
-  block_scan_array(counts, n, prefix, wsum);
-}
-
-__global__ __launch_bounds__(256) void finalize_k(PlanArgs A, double thr, double* lk_real,
-                                                  int32_t* lk_int, int32_t* refit_list,
-                                                  int32_t* refit_n, int refit_pass) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// One thread per list position (1024-thread workgroups: the last one to
+// finish also runs the schedule, which needs a full workgroup scan).
+__global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo li, Sched S,
+                                               int refit) {
+  // xi = mean |coordinate|: every block reduces the preparation kernel's
+  // partials in the same fixed order (cheaper than another launch)
+  __shared__ double red[1024];
+  double part = 0.0;
+  for (int k = threadIdx.x; k < li.n_part; k += 1024) part += li.part[k];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const int64_t nv = A.off[L] - A.off[0];
+  const double xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
   int64_t n = A.n_list;
   if (A.n_list_dev) {
     const int64_t nd = *A.n_list_dev;
     n = nd < n ? nd : n;
   }
-  if (q >= n) return;
-  const int32_t p = A.list ? A.list[q] : (int32_t)q;
-  uint32_t f = A.flags[p];
-  unsigned long long lo = A.acc[2 * (int64_t)p], hi = A.acc[2 * (int64_t)p + 1];
-  // 128-bit two's complement -> sign and magnitude -> double (one rounding of
-  // the fraction word, one of the sum)
+  // grid stride with the same trip count in every thread (the appends below
+  // are wavefront-collective)
+  for (int64_t base = (int64_t)blockIdx.x * 1024; base < A.n_list;
+       base += (int64_t)gridDim.x * 1024) {
+    const int64_t q = base + threadIdx.x;
+    bool small = false, big = false;
+    WorkRec r{};
+    if (q < n) {
+      const int32_t p = A.list ? A.list[q] : (int32_t)q;
+      const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
+      const bool valid = i >= 0 && j >= 0 && i < L && j < L && i != j;
+      int64_t items = 0;
+      if (valid) {
+        r.oa = A.off[i];
+        r.ob = A.off[j];
+        const int64_t na = A.off[i + 1] - r.oa, nb = A.off[j + 1] - r.ob;
+        r.na = (int32_t)na;
+        r.nb = (int32_t)nb;
+        if (na >= 1 && nb >= 1)
+          items = ((nb + A.bblock - 1) / A.bblock) * ((na + A.chunk - 1) / A.chunk);
+      }
+      // loops beyond 2^31 vertices or pairs beyond 2^31 work items are not handled
+      const bool too_big = valid && (A.off[i + 1] - A.off[i] > 0x7fffffffLL ||
+                                     A.off[j + 1] - A.off[j] > 0x7fffffffLL ||
+                                     items > 0x7fffffffLL);
+      if (too_big) items = 0;
+      uint32_t f;
+      if (refit) {
+        f = (A.out.flags[p] & ~kFlagNonfinite) | (too_big ? kFlagNonfinite : 0u);
+      } else if (valid) {
+        // Alg. 3's zero-length test: a segment shorter than eps * xi
+        const double lim = li.eps * xi;
+        const double lim2 = lim * lim;
+        const uint32_t fi = li.lf[i] | (li.minseg2[i] < lim2 ? kFlagBadloop : 0u);
+        const uint32_t fj = li.lf[j] | (li.minseg2[j] < lim2 ? kFlagBadloop : 0u);
+        f = fi | fj | (too_big ? kFlagBadloop | kFlagNonfinite : 0u);
+      } else {
+        f = kFlagBadpair;
+      }
+      A.acc[2 * (int64_t)p] = 0ull;
+      A.acc[2 * (int64_t)p + 1] = 0ull;
+      r.p = p;
+      r.items = (int32_t)items;
+      small = items == 1 && r.na < kSmallA;
+      big = items > 0 && !small;
+      if (!valid) {
+        A.out.flags[p] = f;
+        A.out.lk_real[p] = __builtin_nan("");
+        A.out.lk_int[p] = kIntInvalid;
+      } else if (items == 0) {
+        // nothing to sum (an empty loop, or beyond the supported sizes)
+        Outs o = A.out;
+        o.refit_list = nullptr;
+        finalize_pair(o, p, 0.0, f);
+      } else {
+        A.out.flags[p] = f;
+      }
+    }
+    const int32_t ps = wave_append(&S.counts[0], small);
+    const int32_t pb = wave_append(&S.counts[1], big);
+    if (small) S.small[ps] = r;
+    if (big) S.big_in[pb] = r;
+  }
+}
+
+// 128-bit two's complement -> sign and magnitude -> double (one rounding of
+// the fraction word, one of the sum).
+__device__ __forceinline__ double from_fixed(unsigned long long lo, unsigned long long hi) {
   const bool neg = (long long)hi < 0;
   if (neg) {
     lo = ~lo + 1ull;
     hi = ~hi + (lo == 0ull ? 1ull : 0ull);
   }
   const double mag = (double)hi + (double)lo * 5.421010862427522170e-20;  // 2^-64
-  const double v = neg ? -mag : mag;
-  bool requeue = false;
-  if (f & kFlagBadpair) {
-    lk_real[p] = __builtin_nan("");
-    lk_int[p] = kIntInvalid;
-  } else {
-    if (refit_pass) f |= kFlagRefit;
-    const bool bad = (f & kFlagNonfinite) || !isfinite(v) || fabs(v) > 2.0e9;
-    if (bad) {
-      f |= kFlagNonfinite;
-      lk_real[p] = __builtin_nan("");
-      lk_int[p] = kIntInvalid;
-      requeue = refit_list != nullptr;
-    } else {
-      const double r = round(v);  // half away from zero
-      const double frac = fabs(v - r);
-      lk_real[p] = v;
-      lk_int[p] = (int32_t)r;
-      if (frac > thr) {
-        if (refit_list)
-          requeue = true;
-        else
-          f |= kFlagAmbiguous;
-      }
-    }
-    A.flags[p] = f;
+  return neg ? -mag : mag;
+}
+
+__global__ __launch_bounds__(256) void finalize_split_k(Sched S, const unsigned long long* acc,
+                                                        Outs o) {
+  const int32_t nb = S.counts[1];
+  for (int32_t k = blockIdx.x * 256 + threadIdx.x; k < nb; k += gridDim.x * 256) {
+    const WorkRec r = S.big[k];
+    if (r.items < 2) continue;  // single-item pairs were finalised by their wave
+    const int32_t p = r.p;
+    finalize_pair(o, p, from_fixed(acc[2 * (int64_t)p], acc[2 * (int64_t)p + 1]), o.flags[p]);
   }
-  if (refit_list) {
-    const int32_t pos = wave_append(refit_n, requeue);
-    if (requeue) refit_list[pos] = p;
-  }
+}
+
+__global__ __launch_bounds__(1024) void sched_k(Sched S, int32_t* zero_next) {
+  schedule(S, zero_next);
+}
+
+// General single-workgroup exclusive scan (pair search, verification).
+__global__ __launch_bounds__(1024) void scan_k(const int64_t* counts, int64_t n, int64_t* prefix) {
+  __shared__ int64_t wsum[16];
+  block_scan_array(counts, n, prefix, wsum);
 }
 
 // ------------------------------------------------------ potential link search
@@ -461,26 +461,36 @@ __global__ __launch_bounds__(256) void verify_scatter_k(const int32_t* pr, const
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_loop_flags(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
-                             double* xi_partials, double* xi, uint32_t* lf, int32_t* zero_counts,
-                             hipStream_t s) {
-  const int lb = blocks_for((int64_t)n_loops * 64, 256, 8192);
-  if (in_f64) {
-    xi_partial<double><<<kXiBlocks, 256, 0, s>>>((const double*)xyz, off, n_loops, xi_partials);
-    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi, zero_counts);
-    loop_flags_k<double><<<lb, 256, 0, s>>>((const double*)xyz, off, n_loops, xi, DBL_EPSILON, lf);
-  } else {
-    xi_partial<float><<<kXiBlocks, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials);
-    xi_final<<<1, 256, 0, s>>>(xi_partials, off, n_loops, xi, zero_counts);
-    loop_flags_k<float><<<lb, 256, 0, s>>>((const float*)xyz, off, n_loops, xi,
-                                           (double)FLT_EPSILON, lf);
-  }
+int prep_blocks(int32_t n_loops) {
+  // one wavefront per loop up to kPrepMaxBlocks * 4 loops
+  int64_t g = ((int64_t)n_loops + 3) / 4;
+  if (g < kXiBlocks) g = kXiBlocks;
+  if (g > kPrepMaxBlocks) g = kPrepMaxBlocks;
+  return (int)g;
+}
+
+hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
+                       double* xi_partials, uint32_t* lf, double* minseg2, int32_t* zero_counts,
+                       hipStream_t s) {
+  const int g = prep_blocks(n_loops);
+  if (in_f64)
+    prep_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, xi_partials, lf, minseg2,
+                                     zero_counts);
+  else
+    prep_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials, lf, minseg2,
+                                    zero_counts);
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const uint32_t* lf, const Sched& sc,
+hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const LoopInfo& li, const Sched& sc,
                        bool refit, hipStream_t s) {
-  plan_k<<<blocks_for(a.n_list, 256), 256, 0, s>>>(a, n_loops, lf, sc, refit ? 1 : 0);
+  plan_k<<<blocks_for(a.n_list, 1024, 8192), 1024, 0, s>>>(a, n_loops, li, sc, refit ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_split(const Sched& sc, const unsigned long long* acc, const Outs& o,
+                                 int64_t n_pairs, hipStream_t s) {
+  finalize_split_k<<<blocks_for(n_pairs, 256, 1024), 256, 0, s>>>(sc, acc, o);
   return hipGetLastError();
 }
 
@@ -491,14 +501,6 @@ hipError_t launch_sched(const Sched& sc, int32_t* zero_next, hipStream_t s) {
 
 hipError_t launch_scan(const int64_t* counts, int64_t n, int64_t* prefix, hipStream_t s) {
   scan_k<<<1, 1024, 0, s>>>(counts, n, prefix);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize(const PlanArgs& a, double thr, double* lk_real, int32_t* lk_int,
-                           int32_t* refit_list, int32_t* refit_n, bool refit_pass,
-                           hipStream_t s) {
-  finalize_k<<<blocks_for(a.n_list, 256), 256, 0, s>>>(a, thr, lk_real, lk_int, refit_list,
-                                                       refit_n, refit_pass ? 1 : 0);
   return hipGetLastError();
 }
 

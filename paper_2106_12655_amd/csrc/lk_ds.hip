@@ -18,14 +18,24 @@
 //
 // Per term (Eq. 4, Sec. 2.1): a = l_j - k_i, b = l_j - k_{i+1},
 // c = l_{j+1} - k_{i+1}, d = l_{j+1} - k_i.  Walking j in order, a and b of
-// segment j+1 are d and c of segment j, so each step needs only two new
-// vertex-pair vectors, two square roots and four dot products.  The common
-// numerator of both arctangents is p = a . (s_j x s_i) (equal to a . (b x c)
-// and c . (d x a) in exact arithmetic, Sec. 3.4.2, but computed from the
-// short segment vectors, which keeps FP32 accurate for distant pairs).  The
-// two arctangents are merged into one: (d1 + i p)(d2 + i p) has the angle
-// atan2(p, d1) + atan2(p, d2), which stays inside (-pi, pi) because the
-// pair's parallelogram subtends less than a hemisphere, so
+// segment j+1 are d and c of segment j, so each step needs only the new
+// vertex-pair vectors v_r = l_{j+1} - k_r of the lane's vertices, their norms
+// and their dot products with the previous ones; the other dot products of
+// Eq. 4 follow from carried ones and the lane's segment vectors s_r:
+//   c . a = (d - s_r) . a = a . d - s_r . a      (s_r . a carried from the
+//                                                  previous step's s_r . d)
+//   d . c = d . (d - s_r) = |d|^2 - s_r . d
+// The common numerator of both arctangents is p = a . (s_j x s_r) (equal to
+// a . (b x c) and c . (d x a) in exact arithmetic, Sec. 3.4.2).  With the
+// lane's first vertex k_0 as a local origin, a = V_0 - delta_r where
+// V_0 = l_j - k_0 and delta_r = k_r - k_0, so
+//   p = s_r . (V_0 x s_j) - s_j . (s_r x delta_r)
+// with one cross product per step shared by the lane's R segments and a
+// per-lane constant s_r x delta_r; both pieces are built from short vectors,
+// which keeps FP32 accurate for distant pairs.  The two arctangents are merged
+// into one: (d1 + i p)(d2 + i p) has the angle atan2(p, d1) + atan2(p, d2),
+// which stays inside (-pi, pi) because the pair's parallelogram subtends less
+// than a hemisphere, so
 //   theta = atan2(p (d1 + d2), d1 d2 - p^2),  term = theta / (2 pi)
 // (the angle-addition idea of the appendix, Alg. 7, applied per term).
 #include "lk_internal.h"
@@ -51,16 +61,18 @@ __device__ __forceinline__ V3<T> cross(const V3<T>& a, const V3<T>& b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 
 // Own FP32 arctangent: octant reduction to t = min/max in [0, 1], then
 // atan(t) = t q(t^2) with q the Remez minimax polynomial of atan_poly.h.
 // (0, 0) gives NaN on purpose: it only arises for touching segments.
-__device__ __forceinline__ float atan2_minimax(float y, float x) {
+// atan2_reduced takes t = min(|x|, |y|) / max(|x|, |y|) already formed.
+__device__ __forceinline__ float atan2_reduced(float y, float x, float t) {
   const float ax = fabsf(x), ay = fabsf(y);
-  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-  const float t = mn * __builtin_amdgcn_rcpf(mx);
   const float s = t * t;
   float q = kAtanQ[LK_ATAN_DEG];
 #pragma unroll
@@ -69,6 +81,11 @@ __device__ __forceinline__ float atan2_minimax(float y, float x) {
   r = (ay > ax) ? (1.57079632679489662f - r) : r;
   r = (x < 0.0f) ? (3.14159265358979324f - r) : r;
   return copysignf(r, y);
+}
+
+__device__ __forceinline__ float atan2_minimax(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  return atan2_reduced(y, x, fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay)));
 }
 
 template <typename T, int AT>
@@ -89,6 +106,14 @@ template <>
 __device__ __forceinline__ double angle<double, 1>(double y, double x) {
   return atan2(y, x);
 }
+template <>
+__device__ __forceinline__ float angle<float, 2>(float y, float x) {
+  return atan2_minimax(y, x);
+}
+template <>
+__device__ __forceinline__ double angle<double, 2>(double y, double x) {
+  return atan2(y, x);
+}
 
 // LDS vertex record: 16 bytes for float (one ds_read_b128), 32 for double.
 template <typename T>
@@ -101,24 +126,28 @@ __device__ __forceinline__ V3<Tc> load_vertex(const Tin* X, int64_t v) {
   return {(Tc)X[3 * v], (Tc)X[3 * v + 1], (Tc)X[3 * v + 2]};
 }
 
-// The R consecutive segments of loop B owned by a lane: vertices k_0..k_R and
-// segment vectors s_r = k_{r+1} - k_r.  Segments past the end of the item are
-// evaluated on repeated vertices and masked out.
+// The R consecutive segments of loop B owned by a lane: vertices k_0..k_R,
+// segment vectors s_r = k_{r+1} - k_r and the constants s_r x (k_r - k_0) of
+// the numerator p.  Segments past the end of the item are evaluated on
+// repeated vertices and masked out.
 template <typename T, int R>
 struct Segs {
   V3<T> k[R + 1];
   V3<T> s[R];
+  V3<T> m[R];
   bool valid[R];
 };
 
 // Walk state at vertex l_j of loop A, for all R + 1 vertices of the lane:
-// V_r = l_j - k_r, N_r = |V_r|, E_r = N_r N_{r+1} + V_r . V_{r+1}.
+// V_r = l_j - k_r, N_r = |V_r|, E_r = N_r N_{r+1} + V_r . V_{r+1},
+// G_r = s_r . V_r.
 template <typename T, int R>
 struct Walk {
   V3<T> l;
   V3<T> V[R + 1];
   T N[R + 1];
   T E[R];
+  T G[R];
 };
 
 template <typename T, int R>
@@ -130,7 +159,10 @@ __device__ __forceinline__ void walk_init(Walk<T, R>& w, const V3<T>& l, const S
     w.N[r] = fsqrt(dot(w.V[r], w.V[r]));
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) w.E[r] = w.N[r] * w.N[r + 1] + dot(w.V[r], w.V[r + 1]);
+  for (int r = 0; r < R; ++r) {
+    w.E[r] = w.N[r] * w.N[r + 1] + dot(w.V[r], w.V[r + 1]);
+    w.G[r] = dot(g.s[r], w.V[r]);
+  }
 }
 
 // The Eq. 4 terms of segment (l_j, l_{j+1}) against the lane's R segments;
@@ -141,29 +173,60 @@ __device__ __forceinline__ void walk_init(Walk<T, R>& w, const V3<T>& l, const S
 template <typename T, int AT, int R>
 __device__ __forceinline__ T walk_step(Walk<T, R>& w, const V3<T>& l1, const Segs<T, R>& g) {
   V3<T> v[R + 1];
-  T n[R + 1], vert[R + 1];
+  T n2[R + 1], n[R + 1], vert[R + 1];
 #pragma unroll
   for (int r = 0; r <= R; ++r) {
     v[r] = l1 - g.k[r];
-    n[r] = fsqrt(dot(v[r], v[r]));
+    n2[r] = dot(v[r], v[r]);
+    n[r] = fsqrt(n2[r]);
     vert[r] = dot(w.V[r], v[r]);
   }
   const V3<T> sj = l1 - w.l;
-  T sum = 0;
+  const V3<T> M = cross(w.V[0], sj);
+  T X[R], Y[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const V3<T>& a = w.V[r];
-    const V3<T>& c = v[r + 1];
-    const V3<T>& d = v[r];
     const T na = w.N[r], nb = w.N[r + 1], nc = n[r + 1], nd = n[r];
-    const T p = dot(a, cross(sj, g.s[r]));
-    const T ca = dot(c, a);
-    const T f = nd * nc + dot(d, c);
+    const T gr = dot(g.s[r], v[r]);
+    // p = s_r . M - s_j . m_r as one fused chain (the subtraction folded into
+    // the first product's addend)
+    T p = dot(g.s[r], M);
+    if (r > 0) {
+      const V3<T>& m = g.m[r];
+      p = fmad(g.s[r].x, M.x, fmad(g.s[r].y, M.y, fmad(g.s[r].z, M.z, -dot(sj, m))));
+    }
+    const T ca = vert[r] - w.G[r];
+    const T f = nd * nc + (n2[r] - gr);
     const T d1 = nc * w.E[r] + vert[r + 1] * na + ca * nb;
     const T d2 = na * f + vert[r] * nc + ca * nd;
-    const T th = angle<T, AT>(p * (d1 + d2), d1 * d2 - p * p);
-    sum += g.valid[r] ? th : (T)0;
+    Y[r] = p * (d1 + d2);
+    X[r] = d1 * d2 - p * p;
     w.E[r] = f;
+    w.G[r] = gr;
+  }
+  T sum = 0;
+  if constexpr (AT == 0 && sizeof(T) == 4) {
+    // the R arctangents in phases (all reciprocals issued together, then the
+    // polynomials), which lets the transcendental unit run back to back
+    T mx[R], mn[R], inv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      mx[r] = fmaxf(fabsf(X[r]), fabsf(Y[r]));
+      mn[r] = fminf(fabsf(X[r]), fabsf(Y[r]));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) inv[r] = __builtin_amdgcn_rcpf(mx[r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T th = atan2_reduced(Y[r], X[r], mn[r] * inv[r]);
+      sum += g.valid[r] ? th : (T)0;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T th = angle<T, AT>(Y[r], X[r]);
+      sum += g.valid[r] ? th : (T)0;
+    }
   }
   w.l = l1;
 #pragma unroll
@@ -221,22 +284,29 @@ struct Layout {
   bool active;
 };
 
+// 32-bit arithmetic throughout: the plan guarantees fewer than 2^31 items per
+// pair and 2^31 vertices per loop, and js/je products stay below 2^30
+// (chunk <= 2^24, 64 groups).  `width`: lanes given to the item (a power of
+// two dividing 64; `lane` counts within them).
 template <int R>
-__device__ __forceinline__ Layout layout(const WorkRec& r, int64_t local, int chunk, int lane) {
-  constexpr int kB = kWave * R;
+__device__ __forceinline__ Layout layout(const WorkRec& r, int64_t local, int chunk, int lane,
+                                         unsigned width = kWave) {
+  constexpr unsigned kB = kWave * R;
   Layout L;
-  const int64_t nbb = (r.nb + kB - 1) / kB;
-  L.b0 = (local % nbb) * kB;
-  L.a0 = (local / nbb) * (int64_t)chunk;
+  const unsigned nbb = ((unsigned)r.nb + kB - 1) / kB;
+  const unsigned loc = (unsigned)local;
+  const unsigned bq = loc / nbb;
+  L.b0 = (int64_t)((loc - bq * nbb) * kB);
+  L.a0 = (int64_t)bq * chunk;
   L.nbh = (int)((r.nb - L.b0) < kB ? (r.nb - L.b0) : kB);
   L.nah = (int)((r.na - L.a0) < chunk ? (r.na - L.a0) : chunk);
-  const int slots = (L.nbh + R - 1) / R;
-  const int groups = kWave / slots;
-  L.bi = lane % slots;
-  const int g = lane / slots;
+  const unsigned slots = ((unsigned)L.nbh + R - 1) / R;
+  const unsigned groups = slots <= width ? width / slots : 1u;
+  const unsigned g = (unsigned)lane / slots;
+  L.bi = (int)((unsigned)lane - g * slots);
   L.active = g < groups;
-  L.js = (int)(((int64_t)L.nah * g) / groups);
-  L.je = (int)(((int64_t)L.nah * (g + 1)) / groups);
+  L.js = (int)(((unsigned)L.nah * g) / groups);
+  L.je = (int)(((unsigned)L.nah * (g + 1)) / groups);
   return L;
 }
 
@@ -263,6 +333,7 @@ __device__ __forceinline__ void make_segs(const V3<Tc>* k, const Layout& L, Segs
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     sg.s[r] = sg.k[r + 1] - sg.k[r];
+    sg.m[r] = cross(sg.s[r], sg.k[r] - sg.k[0]);
     sg.valid[r] = first + r < L.nbh;
   }
 }
@@ -276,46 +347,47 @@ __device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, i
     const Vtx<Tc> v0 = lds[jlo - t0];
     walk_init(wk, V3<Tc>{v0.x, v0.y, v0.z}, sg);
   }
-#pragma unroll 4
-  for (int j = jlo; j < jhi; ++j) {
+  // four steps are summed in the compute type before the FP64 lane sum
+  int j = jlo;
+  for (; j + 4 <= jhi; j += 4) {
+    Tc s4 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const Vtx<Tc> v1 = lds[j + q - t0 + 1];
+      s4 += walk_step<Tc, AT, R>(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg);
+    }
+    acc += (double)s4;
+  }
+  for (; j < jhi; ++j) {
     const Vtx<Tc> v1 = lds[j - t0 + 1];
     acc += (double)walk_step<Tc, AT, R>(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg);
   }
 }
 
-// Wave sum of the lanes' partials and its fixed-point addition to the pair.
-// `whole`: this item is the pair's only item, so the (zeroed) accumulator is
-// simply overwritten and no atomic round trip is needed.
+// Wave sum of the lanes' partials.  `whole`: this item is the pair's only one,
+// so its value is final and the pair is finalised at once (`fpre`: the pair's
+// flags as the plan left them, loaded when the item started so that finishing
+// does not wait on a load).  Otherwise the sum goes into the pair's fixed-point
+// accumulator, and the pair is finalised after this kernel, from the big list.
 __device__ __forceinline__ void finish_item(double acc, int32_t p, int lane, const DsArgs& A,
-                                            bool whole) {
+                                            bool whole, uint32_t fpre) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) {
-    const double v = acc * kInvTwoPi;
-    if (!(fabs(v) < 1.0e14)) {
-      atomicOr(&A.flags[p], 4u);  // NaN / Inf / absurd magnitude
-    } else if (whole) {
-      unsigned long long lo, hi;
-      to_fixed(v, lo, hi);
-      A.acc[2 * (int64_t)p] = lo;
-      A.acc[2 * (int64_t)p + 1] = hi;
-    } else {
-      fixed_add(&A.acc[2 * (int64_t)p], v);
-    }
-  }
+  if (lane != 0) return;
+  const double v = acc * kInvTwoPi;
+  const bool ok = fabs(v) < 1.0e14;  // false for NaN / Inf / absurd magnitude
+  if (whole)
+    finalize_pair(A.out, p, v, fpre | (ok ? 0u : kFlagNonfinite));
+  else if (ok)
+    fixed_add(&A.acc[2 * (int64_t)p], v);
+  else
+    atomicOr(&A.out.flags[p], kFlagNonfinite);
 }
 
-__device__ __forceinline__ WorkRec shfl_rec(const WorkRec& r, int src) {
-  WorkRec o;
-  o.oa = __shfl(r.oa, src);
-  o.ob = __shfl(r.ob, src);
-  o.na = __shfl(r.na, src);
-  o.nb = __shfl(r.nb, src);
-  o.p = __shfl(r.p, src);
-  o.items = 1;
-  return o;
-}
-
+// Every variant must fit in 256 registers per lane (two waves per SIMD); a
+// test checks the compiled register counts.  No occupancy attribute is set:
+// capping the compiler's register budget made it spread the transcendental
+// instructions through the loop, which measured slower.
 template <typename Tin, typename Tc, int AT, int R>
 __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -347,6 +419,7 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
           hi = mid;
       }
       const WorkRec r = A.s.big[lo];
+      const uint32_t fpre = r.items == 1 ? A.out.flags[r.p] : 0u;
       const Layout L = layout<R>(r, w - A.s.big_prefix[lo], A.chunk, lane);
       V3<Tc> kv[R + 1];
       load_b<Tin, Tc, R>(X, r, L, kv);
@@ -368,55 +441,92 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
         const int jhi = L.je < t0 + tl ? L.je : t0 + tl;
         if (L.active && jlo < jhi) walk_tile<Tc, AT, R>(lds, t0, jlo, jhi, L.js, wk, sg, acc);
       }
-      finish_item(acc, r.p, lane, A, r.items == 1);
+      finish_item(acc, r.p, lane, A, r.items == 1, fpre);
     } else {
       // a batch of small pairs (one item each, loop A of at most kSmallA - 1
-      // segments): records are read once per batch, and the next pair's
-      // vertices are loaded into registers while the current pair computes
+      // segments).  Pairs whose loop B has at most 64 segments run R at a
+      // time when R > 1, 64 / R lanes each (each lane walks more of loop A,
+      // and the per-pair setup, reduction and finalisation are shared); the
+      // others run one at a time on the whole wave.  Which way a pair runs
+      // depends only on the pair, so results are reproducible.  Records are
+      // re-read from the list where needed rather than held in registers
+      // across the walks.
       const int64_t m0 = (w - big_total) * (int64_t)A.batch;
       const int cnt = (int)((n_small - m0) < A.batch ? (n_small - m0) : A.batch);
-      WorkRec mine{};
-      if (lane < cnt) mine = A.s.small[m0 + lane];
-      WorkRec cur = shfl_rec(mine, 0);
-      Layout L = layout<R>(cur, 0, A.chunk, lane);
-      V3<Tc> kv[R + 1], a_lo, a_hi;
-      load_b<Tin, Tc, R>(X, cur, L, kv);
-      a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
-      a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
-      for (int m = 0; m < cnt; ++m) {
+      const WorkRec* recs = A.s.small + m0;
+      const int32_t nb_l = lane < cnt ? recs[lane].nb : 0;
+      const unsigned long long pmask = __ballot(R > 1 && lane < cnt && nb_l <= kWave);
+      unsigned long long smask = __ballot(lane < cnt) & ~pmask;
+      const int npk = __popcll(pmask);
+      if (npk > 0) {
+        constexpr int K = R, S = kWave / R;
+        const int seg = lane / S, sl = lane - seg * S;
+        Vtx<Tc>* myl = lds + seg * kSmallA;
+        for (int r0 = 0; r0 < npk; r0 += K) {
+          const bool has = r0 + seg < npk;
+          // batch position of the (r0 + seg)-th packed pair
+          unsigned long long mm = pmask;
+          for (int t = has ? r0 + seg : r0; t > 0; --t) mm &= mm - 1ull;
+          const WorkRec cur = recs[__ffsll((long long)mm) - 1];
+          const uint32_t fm = A.out.flags[cur.p];
+          __syncthreads();
+          if (has)
+            for (int v = sl; v <= cur.na; v += S) {
+              const V3<Tc> x = load_vertex<Tc>(X, cur.oa + (v < cur.na ? v : 0));
+              myl[v] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
+            }
+          const Layout L = layout<R>(cur, 0, A.chunk, sl, S);
+          V3<Tc> kv[R + 1];
+          load_b<Tin, Tc, R>(X, cur, L, kv);
+          Segs<Tc, R> sg;
+          make_segs<Tc, R>(kv, L, sg);
+          __syncthreads();
+          Walk<Tc, R> wk;
+          double acc = 0.0;
+          if (has && L.active && L.js < L.je) walk_tile<Tc, AT, R>(myl, 0, L.js, L.je, L.js, wk, sg, acc);
+#pragma unroll
+          for (int o = S / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+          if (has && sl == 0) {
+            const double v = acc * kInvTwoPi;
+            finalize_pair(A.out, cur.p, v, fm | (fabs(v) < 1.0e14 ? 0u : kFlagNonfinite));
+          }
+        }
+      }
+      while (smask) {
+        const int m = __ffsll((long long)smask) - 1;
+        smask &= smask - 1ull;
+        const WorkRec cur = recs[m];
+        const uint32_t fm = A.out.flags[cur.p];
+        const Layout L = layout<R>(cur, 0, A.chunk, lane);
+        V3<Tc> kv[R + 1];
+        load_b<Tin, Tc, R>(X, cur, L, kv);
+        const V3<Tc> a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
+        const V3<Tc> a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
         __syncthreads();
         if (lane <= cur.na) lds[lane] = Vtx<Tc>{a_lo.x, a_lo.y, a_lo.z, (Tc)0};
         if (lane + kWave <= cur.na) lds[lane + kWave] = Vtx<Tc>{a_hi.x, a_hi.y, a_hi.z, (Tc)0};
         Segs<Tc, R> sg;
         make_segs<Tc, R>(kv, L, sg);
-        const Layout Lc = L;
-        const int32_t pc = cur.p;
-        if (m + 1 < cnt) {
-          cur = shfl_rec(mine, m + 1);
-          L = layout<R>(cur, 0, A.chunk, lane);
-          load_b<Tin, Tc, R>(X, cur, L, kv);
-          a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
-          a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
-        }
         __syncthreads();
         Walk<Tc, R> wk;
         double acc = 0.0;
-        if (Lc.active && Lc.js < Lc.je) walk_tile<Tc, AT, R>(lds, 0, Lc.js, Lc.je, Lc.js, wk, sg, acc);
-        finish_item(acc, pc, lane, A, true);
+        if (L.active && L.js < L.je) walk_tile<Tc, AT, R>(lds, 0, L.js, L.je, L.js, wk, sg, acc);
+        finish_item(acc, cur.p, lane, A, true, fm);
       }
     }
   }
 }
 
-template <typename Tc>
+// A tile plus its closing vertex, or R small pairs' loops A side by side.
+template <typename Tc, int R>
 size_t lds_bytes(int tile) {
-  const int n = tile + 1 > kSmallA ? tile + 1 : kSmallA;
+  const int n = tile + 1 > R * kSmallA ? tile + 1 : R * kSmallA;
   return (size_t)n * sizeof(Vtx<Tc>);
 }
 
 template <typename Tin, typename Tc, int AT, int R>
 hipError_t launch_t(const DsArgs& a, int grid, hipStream_t s) {
-  const size_t shm = lds_bytes<Tc>(a.tile);
+  const size_t shm = lds_bytes<Tc, R>(a.tile);
   ds_persistent<Tin, Tc, AT, R><<<dim3(grid), dim3(kWave), shm, s>>>(a);
   return hipGetLastError();
 }
@@ -425,7 +535,7 @@ template <typename Tin, typename Tc, int AT, int R>
 int grid_t(int tile, int n_cu, int waves_per_cu) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT, R>, kWave,
-                                                   lds_bytes<Tc>(tile)) != hipSuccess ||
+                                                   lds_bytes<Tc, R>(tile)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (waves_per_cu > 0 && waves_per_cu < per_cu) per_cu = waves_per_cu;
@@ -452,6 +562,11 @@ Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
     if (segs >= 4) return in_f64 ? variant<double, float, 1, 4>() : variant<float, float, 1, 4>();
     if (segs >= 2) return in_f64 ? variant<double, float, 1, 2>() : variant<float, float, 1, 2>();
     return in_f64 ? variant<double, float, 1, 1>() : variant<float, float, 1, 1>();
+  }
+  if (atan_form == 2) {
+    if (segs >= 4) return in_f64 ? variant<double, float, 2, 4>() : variant<float, float, 2, 4>();
+    if (segs >= 2) return in_f64 ? variant<double, float, 2, 2>() : variant<float, float, 2, 2>();
+    return in_f64 ? variant<double, float, 2, 1>() : variant<float, float, 2, 1>();
   }
   if (segs >= 4) return in_f64 ? variant<double, float, 0, 4>() : variant<float, float, 0, 4>();
   if (segs >= 2) return in_f64 ? variant<double, float, 0, 2>() : variant<float, float, 0, 2>();

@@ -4,6 +4,7 @@
 // lk_runtime.hip holds the C ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace lk {
@@ -40,6 +41,28 @@ struct Sched {
   unsigned long long* counter;  // work counter
 };
 
+// Where a pass writes its per-pair results (finalisation happens in the
+// planning kernel for pairs without work, in the direct-sum kernel for pairs
+// of one work item and in a short kernel after it for pairs of several).
+struct Outs {
+  double* lk_real;             // [n_pairs]
+  int32_t* lk_int;             // [n_pairs]
+  uint32_t* flags;             // [n_pairs]
+  int32_t* refit_list;         // main MIXED pass: pairs queued for the FP64 refit (else NULL)
+  int32_t* refit_n;            // its length
+  double thr;                  // |v - round(v)| above this queues (main) or flags AMBIGUOUS
+  int32_t refit_pass;          // 1: the pass over the refit list (sets LK_FLAG_REFIT)
+};
+
+// Per-loop validation results of the preparation kernel.
+struct LoopInfo {
+  const uint32_t* lf;          // NONFINITE / BADLOOP bits known without xi [n_loops]
+  const double* minseg2;       // shortest squared segment length [n_loops]
+  const double* part;          // partial sums of |coordinate| [n_part]
+  int32_t n_part;
+  double eps;                  // machine epsilon of the input dtype
+};
+
 // Inputs of the planning step.
 struct PlanArgs {
   const int64_t* off;          // loop offsets [n_loops + 1]
@@ -48,9 +71,9 @@ struct PlanArgs {
   const int32_t* n_list_dev;   // optional: list length on the device (NULL = n_list)
   int64_t n_list;              // list length (upper bound when n_list_dev is set)
   unsigned long long* acc;     // per-pair 128-bit fixed-point sums [n_pairs][2]
-  uint32_t* flags;             // per-pair flags [n_pairs]
   int32_t chunk;               // vertices of loop A per work item
   int32_t bblock;              // segments of loop B per work item (64 x segments per lane)
+  Outs out;
 };
 
 // Inputs of one direct-sum pass.
@@ -58,11 +81,43 @@ struct DsArgs {
   const void* xyz;             // vertices, float or double, [V][3]
   Sched s;
   unsigned long long* acc;     // per-pair 128-bit fixed-point sums [n_pairs][2]
-  uint32_t* flags;             // per-pair flags [n_pairs]
   int32_t tile;                // LDS tile of loop A, vertices
   int32_t chunk;               // vertices of loop A per work item (multiple of tile)
   int32_t batch;               // small pairs per work index
+  Outs out;
 };
+
+constexpr uint32_t kFlagRefit = 1u, kFlagAmbiguous = 2u, kFlagNonfinite = 4u, kFlagBadpair = 8u,
+                   kFlagBadloop = 16u;
+constexpr int32_t kIntInvalid = INT32_MIN;
+
+// Rounds and flags one pair's value and writes its outputs (a6 of the path):
+// round half away from zero; a value farther than `thr` from its integer, or a
+// non-finite one, goes to the refit list in the main MIXED pass and is flagged
+// AMBIGUOUS (or NONFINITE) otherwise.  Called by one lane per pair.
+__device__ __forceinline__ void finalize_pair(const Outs& o, int32_t p, double v, uint32_t f) {
+  bool requeue = false;
+  if (o.refit_pass) f |= kFlagRefit;
+  const bool bad = (f & kFlagNonfinite) || !isfinite(v) || fabs(v) > 2.0e9;
+  if (bad) {
+    f |= kFlagNonfinite;
+    o.lk_real[p] = __builtin_nan("");
+    o.lk_int[p] = kIntInvalid;
+    requeue = o.refit_list != nullptr;
+  } else {
+    const double r = round(v);  // half away from zero
+    o.lk_real[p] = v;
+    o.lk_int[p] = (int32_t)r;
+    if (fabs(v - r) > o.thr) {
+      if (o.refit_list)
+        requeue = true;
+      else
+        f |= kFlagAmbiguous;
+    }
+  }
+  o.flags[p] = f;
+  if (requeue) o.refit_list[atomicAdd(o.refit_n, 1)] = p;
+}
 
 // --- lk_ds.hip
 // in_f64: input dtype; compute_f64: arithmetic (true = plain FP64 / refit);
@@ -77,33 +132,32 @@ int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int segs, int 
 int segs_supported(bool compute_f64, int segs);
 
 // --- lk_aux.hip
-constexpr int kXiBlocks = 256;
-// xi = mean |coordinate| over vertices [off[0], off[n_loops]); writes loop flags.
-// Also zeroes the given schedule counts (start of a call).
-hipError_t launch_loop_flags(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
-                             double* xi_partials /*[kXiBlocks]*/, double* xi,
-                             uint32_t* loop_flags, int32_t* zero_counts, hipStream_t s);
-
-// Per list position: validate the pair, merge loop flags, zero its accumulator,
-// count its work items and append its record to the small or big list.
+constexpr int kXiBlocks = 256;        // least workgroups of the preparation kernel
+constexpr int kPrepMaxBlocks = 4096;  // most workgroups (xi partials buffer size)
+// Workgroups of the preparation kernel for n_loops loops (= xi partials).
+int prep_blocks(int32_t n_loops);
+// xi partial sums (one per workgroup) and, one wavefront per loop, the loop's
+// NONFINITE / <3-vertex bits and shortest squared segment; zeroes the main
+// pass's two schedule counts.
+hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
+                       double* xi_partials /*[prep_blocks]*/, uint32_t* lf, double* minseg2,
+                       int32_t* zero_counts, hipStream_t s);
+// Per list position: validate the pair, apply the zero-length test (xi from
+// the partials), zero its accumulator, count its work items and append its
+// record to the small or big list; pairs without work are finalised here.
 // refit = true: REFIT-pass semantics (keeps flags, clears NONFINITE).
-hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const uint32_t* loop_flags,
-                       const Sched& s, bool refit, hipStream_t s_);
+hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const LoopInfo& li, const Sched& s,
+                       bool refit, hipStream_t st);
+// After the direct-sum kernel: finalise the pairs of the big list that were
+// split over several work items (128-bit fixed point -> FP64, round, flag).
+hipError_t launch_finalize_split(const Sched& s, const unsigned long long* acc, const Outs& o,
+                                 int64_t n_pairs, hipStream_t st);
 // Sort the big list (largest first), scan its items, set big_total, zero the
 // work counter and (optionally) three int32 of the next pass: its two
 // schedule counts and the refit count that follows them in memory.
 hipError_t launch_sched(const Sched& s, int32_t* zero_counts_next, hipStream_t st);
-
-// Convert sums to outputs.  refit_list/refit_n: if non-NULL (main MIXED pass),
-// pairs with |frac| > thr or a non-finite value are appended.  refit_pass: the
-// list being finalised is the refit list (sets LK_FLAG_REFIT).
-hipError_t launch_finalize(const PlanArgs& a, double thr, double* lk_real, int32_t* lk_int,
-                           int32_t* refit_list, int32_t* refit_n, bool refit_pass,
-                           hipStream_t s);
-
 // Exclusive scan of counts[0..n) into prefix[0..n] (single workgroup).
 hipError_t launch_scan(const int64_t* counts, int64_t n, int64_t* prefix, hipStream_t s);
-
 // Potential link search.
 hipError_t launch_boxes(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                         double* boxes /*[n_loops][6]*/, hipStream_t s);

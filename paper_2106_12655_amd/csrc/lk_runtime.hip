@@ -2,9 +2,12 @@
 // argument checking, the kernel sequence of each call and its HIP-graph cache.
 //
 // lk_direct_sum enqueues, on the caller's stream:
-//   loop validation (xi, per-loop flags) -> plan (items per pair) -> scan ->
-//   persistent direct-sum kernel -> finalize (round, flag, refit list)
-//   [MIXED only: plan(refit list) -> scan -> FP64 direct-sum kernel -> finalize]
+//   preparation (xi partials, per-loop validity) -> plan (items per pair) ->
+//   schedule (LPT order, scan) -> persistent direct-sum kernel, which also
+//   rounds, flags and queues refits for pairs of one work item -> the same for
+//   pairs split over several items
+//   [MIXED only: plan -> schedule -> FP64 direct-sum -> split pairs, on the
+//   refit list]
 // Every launch has a host-known shape; data-dependent counts live in device
 // memory.  The first call with a given argument set is captured into a HIP
 // graph (when the stream allows capture) and replayed by later identical calls.
@@ -48,7 +51,7 @@ struct lk_ctx {
   int opt_tile = 0, opt_chunk = 0, opt_waves = 0, opt_atan = 0, opt_segs = 0, opt_segs64 = 0;
   int opt_batch = 0;
   // workspace
-  DevBuf loop_flags, xi, recs, big_prefix, meta, acc, flags, refit_list;
+  DevBuf loop_flags, minseg2, xi, recs, big_prefix, meta, acc, flags, refit_list;
   DevBuf boxes, vcounts, vprefix;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
   // graphs
@@ -101,6 +104,7 @@ lk_status ensure(lk_ctx* ctx, DevBuf& b, size_t bytes) {
     b.p = nullptr;
     return ctx->fail(LK_ENOMEM, "hipMalloc(%zu) failed", want);
   }
+
   b.bytes = want;
   ctx->ws_epoch++;
   return LK_OK;
@@ -156,10 +160,26 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   const bool timed = ev != nullptr;
   using namespace lk;
   uint32_t* lf = (uint32_t*)ctx->loop_flags.p;
-  double* xi = (double*)ctx->xi.p;  // [kXiBlocks] partials followed by xi
+  double* xi = (double*)ctx->xi.p;  // [kPrepMaxBlocks] partial sums of |coordinate|
   int32_t* rlist = (int32_t*)ctx->refit_list.p;
   int32_t* rn = meta_at<int32_t>(ctx, kMetaRefitN);
   unsigned long long* acc = (unsigned long long*)ctx->acc.p;
+
+  LoopInfo li;
+  li.lf = lf;
+  li.minseg2 = (const double*)ctx->minseg2.p;
+  li.part = xi;
+  li.n_part = prep_blocks(n_loops);
+  li.eps = P.in_f64 ? 2.220446049250313080847e-16 : 1.1920928955078125e-07;
+
+  Outs out{};
+  out.lk_real = lk_real;
+  out.lk_int = lk_int;
+  out.flags = flags;
+  out.refit_list = P.mixed ? rlist : nullptr;
+  out.refit_n = P.mixed ? rn : nullptr;
+  out.thr = ctx->refit_thr;
+  out.refit_pass = 0;
 
   PlanArgs M{};
   M.off = off;
@@ -168,43 +188,49 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   M.n_list_dev = nullptr;
   M.n_list = n_pairs;
   M.acc = acc;
-  M.flags = flags;
   M.chunk = P.chunk;
   M.bblock = lk::kWave * (P.mixed ? P.segs : P.segs64);
+  M.out = out;
   DsArgs A{};
   A.xyz = xyz;
   A.s = make_sched(ctx, n_pairs, false);
   A.acc = acc;
-  A.flags = flags;
   A.tile = P.tile;
   A.chunk = P.chunk;
   A.batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
+  A.out = out;
 
-  LK_HIP(launch_loop_flags(xyz, P.in_f64, off, n_loops, xi, xi + kXiBlocks, lf, A.s.counts, s));
-  LK_HIP(launch_plan(M, n_loops, lf, A.s, false, s));
+  LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
+                     s));
+  LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
   LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
   if (timed) LK_HIP(hipEventRecord(ev[0], s));
   LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
                            P.mixed ? P.grid : P.grid64, s));
   if (timed) LK_HIP(hipEventRecord(ev[1], s));
-  LK_HIP(launch_finalize(M, ctx->refit_thr, lk_real, lk_int, P.mixed ? rlist : nullptr,
-                         P.mixed ? rn : nullptr, false, s));
+  LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
   if (P.mixed) {
+    Outs ro = out;
+    ro.refit_list = nullptr;
+    ro.refit_n = nullptr;
+    ro.refit_pass = 1;
     PlanArgs R = M;
     R.list = rlist;
     R.n_list_dev = rn;
     R.chunk = default_chunk(true);
     R.bblock = lk::kWave * P.segs64;
+    R.out = ro;
     DsArgs B = A;
     B.s = make_sched(ctx, n_pairs, true);
     B.tile = default_tile(true);
     B.chunk = default_chunk(true);
-    LK_HIP(launch_plan(R, n_loops, lf, B.s, true, s));
+    B.out = ro;
+    LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
     LK_HIP(launch_sched(B.s, nullptr, s));
     if (timed) LK_HIP(hipEventRecord(ev[2], s));
     LK_HIP(launch_direct_sum(B, P.in_f64, true, 0, P.segs64, P.grid_refit, s));
     if (timed) LK_HIP(hipEventRecord(ev[3], s));
-    LK_HIP(launch_finalize(R, ctx->refit_thr, lk_real, lk_int, nullptr, nullptr, true, s));
+    LK_HIP(launch_finalize_split(B.s, acc, ro, n_pairs, s));
   }
   return LK_OK;
 }
@@ -233,7 +259,8 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, bool mixed) {
 lk_status ensure_workspace(lk_ctx* ctx, int32_t n_loops, int64_t n_pairs) {
   lk_status st;
   if ((st = ensure(ctx, ctx->loop_flags, 4 * (size_t)n_loops)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kXiBlocks + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->minseg2, 8 * (size_t)n_loops)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->xi, 8 * (size_t)(lk::kPrepMaxBlocks + 1))) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->recs, 3 * sizeof(lk::WorkRec) * (size_t)n_pairs)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->big_prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->meta, kMetaBytes)) != LK_OK) return st;
@@ -282,9 +309,9 @@ void lk_destroy(lk_ctx* ctx) {
   hipDeviceSynchronize();
   for (auto& kv : ctx->graphs)
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-  DevBuf* bufs[] = {&ctx->loop_flags, &ctx->xi,    &ctx->recs,       &ctx->big_prefix,
-                    &ctx->meta,       &ctx->acc,   &ctx->flags,      &ctx->refit_list,
-                    &ctx->boxes,      &ctx->vcounts, &ctx->vprefix};
+  DevBuf* bufs[] = {&ctx->loop_flags, &ctx->minseg2, &ctx->xi,      &ctx->recs,
+                    &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
+                    &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -333,7 +360,7 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       ctx->opt_waves = (int)v;
       break;
     case LK_OPT_ATAN:
-      if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "atan form must be 0 or 1");
+      if (v < 0 || v > 2) return ctx->fail(LK_EINVAL, "atan form must be 0, 1 or 2");
       ctx->opt_atan = (int)v;
       break;
     case LK_OPT_SEGS_PER_LANE:
@@ -625,6 +652,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     ctx->opt_chunk = t.chunk_a;
     ctx->opt_batch = t.small_batch;
     ctx->opt_waves = t.waves_per_cu;
+    ctx->opt_atan = t.atan_form;
     for (auto& kv : ctx->graphs)
       if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
     ctx->graphs.clear();
@@ -638,8 +666,8 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
       std::string k;
       lk_tuning t{};
       if (ls >> k >> t.segs_per_lane >> t.segs_per_lane_f64 >> t.tile_a >> t.chunk_a >>
-          t.small_batch >> t.waves_per_cu >> t.best_ms >> t.start_ms) {
-        if (k == key) {
+          t.small_batch >> t.waves_per_cu >> t.best_ms >> t.start_ms >> t.atan_form) {
+        if (k == key && t.atan_form >= 0 && t.atan_form <= 2) {
           t.from_cache = 1;
           apply(t);
           *out = t;
@@ -671,6 +699,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   cur.chunk_a = ctx->opt_chunk ? ctx->opt_chunk : default_chunk(!mixed);
   cur.small_batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
   cur.waves_per_cu = ctx->opt_waves;
+  cur.atan_form = ctx->opt_atan;
   int evaluated = 0;
   auto measure = [&](const lk_tuning& t, double* ms) -> lk_status {
     apply(t);
@@ -714,6 +743,11 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     return LK_OK;
   };
   if (mixed) {
+    // segments per lane and the arctangent's instruction order interact (the
+    // compiler schedules each variant differently): sweep one, the other, and
+    // the first again
+    if ((st = sweep(&lk_tuning::segs_per_lane, {1, 2, 4})) != LK_OK) return st;
+    if ((st = sweep(&lk_tuning::atan_form, {0, 2})) != LK_OK) return st;
     if ((st = sweep(&lk_tuning::segs_per_lane, {1, 2, 4})) != LK_OK) return st;
   } else {
     if ((st = sweep(&lk_tuning::segs_per_lane_f64, {1, 2})) != LK_OK) return st;
@@ -745,7 +779,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     std::ofstream o(cache_path, std::ios::app);
     o << key << " " << cur.segs_per_lane << " " << cur.segs_per_lane_f64 << " " << cur.tile_a
       << " " << cur.chunk_a << " " << cur.small_batch << " " << cur.waves_per_cu << " "
-      << cur.best_ms << " " << cur.start_ms << "\n";
+      << cur.best_ms << " " << cur.start_ms << " " << cur.atan_form << "\n";
   }
   *out = cur;
   return LK_OK;

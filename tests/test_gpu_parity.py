@@ -305,4 +305,41 @@ def test_autotune_picks_a_valid_configuration(ctx, tmp_path):
     assert np.abs(real.cpu().numpy() - oreal).max() < MIXED_TOL
     t2 = lk_mod.Context(0).autotune(xyz, off, pr, "mixed", cache_path=cache)
     assert t2["from_cache"] == 1 and t2["segs_per_lane"] == t1["segs_per_lane"]
+    assert t2["atan_form"] == t1["atan_form"]
+    tctx.close()
+
+
+def test_arctangent_forms_and_lane_blocking():
+    # the two orders of the own minimax arctangent compute the same operations:
+    # bitwise equal results for every segments-per-lane variant; HIP's atan2f
+    # agrees within the mixed tolerance
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    from paper_2106_12655_amd import _lib
+    rng = np.random.default_rng(11)
+    parts = [I.chainmail(7, rows=8, cols=8)]
+    loops = [_smooth_loop(rng, n, rng.uniform(-0.4, 0.4, 3)) for n in (300, 700, 1500)]
+    xyz = np.vstack([parts[0].xyz.astype(np.float64) + 50.0] + loops).astype(np.float32)
+    sizes = list(parts[0].sizes) + [len(q) for q in loops]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ls = I.LoopSet(xyz=xyz, offsets=off, exp_pairs=np.zeros((0, 2), np.int32),
+                   exp_lk=np.zeros(0, np.int32), name="forms")
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    tctx = lk_mod.Context(0)
+    xyz_d, off_d = _dev(ls)
+    pr = torch.from_numpy(pairs).cuda()
+    for segs in (1, 2, 4):
+        got = {}
+        for form in (0, 2, 1):
+            tctx.set_option(_lib.OPT_SEGS_PER_LANE, segs)
+            tctx.set_option(_lib.OPT_ATAN, form)
+            real, lk, flags = tctx.direct_sum(xyz_d, off_d, pr, "mixed")
+            torch.cuda.synchronize()
+            got[form] = real.cpu().numpy()
+            assert np.array_equal(lk.cpu().numpy(), olk), (segs, form)
+            assert np.abs(got[form] - oreal).max() < TANGLE_TOL, (segs, form)
+        print("segs %d: form 0 vs 2 max |diff| %.3e, atan2f vs oracle %.3e" % (
+            segs, np.abs(got[0] - got[2]).max(), np.abs(got[1] - oreal).max()), flush=True)
+        assert np.array_equal(got[0], got[2]), segs
     tctx.close()
