@@ -68,10 +68,12 @@ enum {
   LK_FLAG_AMBIGUOUS = 2u, /* |value - round(value)| > threshold in FP64 too */
   LK_FLAG_NONFINITE = 4u, /* NaN/Inf in the sum (degenerate or intersecting input) */
   LK_FLAG_BADPAIR = 8u,   /* i == j or an index outside [0, n_loops) */
-  LK_FLAG_BADLOOP = 16u   /* a loop has < 3 vertices, a non-finite coordinate, or a
+  LK_FLAG_BADLOOP = 16u,  /* a loop has < 3 vertices, a non-finite coordinate, or a
                              segment shorter than eps * xi (Alg. 3 zero-length test,
                              xi = mean |coordinate| over the call's vertices,
                              eps = machine epsilon of the input dtype) */
+  LK_FLAG_SKIPPED = 32u   /* lk_direct_sum_check with early exit stopped before this
+                             pair's sum was complete (no value, LK_INT_INVALID) */
 };
 
 /* Integer reported for pairs whose value is not finite or whose indices are bad. */
@@ -115,6 +117,25 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
 lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* loop_offsets,
                         int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
                         double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream);
+
+/* Direct sum fused with the certificate check (Sec. 3.1, "Fast
+ * Verification", and its early-exit strategy): as lk_direct_sum, and each
+ * pair's final integer is compared with expected[p] (int32 [n_pairs], device)
+ * as soon as it is known.  A pair is a mismatch when its integer differs or
+ * when it cannot be certified (LK_FLAG_NONFINITE, AMBIGUOUS, BADPAIR or
+ * BADLOOP).  *n_mismatch (int64, device) receives the count; nothing is
+ * copied to the host, so the call is asynchronous and graph-capturable.
+ * early_exit != 0: once a mismatch is found, the kernels stop taking new
+ * work.  Pairs whose sum was not completed then carry LK_FLAG_SKIPPED,
+ * LK_INT_INVALID and a NaN real, and the count covers the pairs compared
+ * before the stop (at least 1).  For the simulation use of Sec. 3.1, pass the
+ * union of the current candidate pairs and the expected non-zero pairs, with
+ * expected 0 for pairs that are new. */
+lk_status lk_direct_sum_check(lk_ctx* ctx, const void* xyz, int dtype,
+                              const int64_t* loop_offsets, int32_t n_loops, const int32_t* pairs,
+                              int64_t n_pairs, const int32_t* expected, int early_exit, int mode,
+                              double* lk_real, int32_t* lk_int, uint32_t* flags,
+                              int64_t* n_mismatch /* device */, void* stream);
 
 /* --------------------------------------------------------------- verify */
 /* Compare the current sparse linking matrix (pairs, lk)[n] with the expected

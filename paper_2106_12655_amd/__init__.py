@@ -7,8 +7,9 @@ a built library or a GPU every call raises.
 
 Functions follow the paper's pipeline (Qu & James 2021, Alg. 1):
 ``build_pairs`` (potential link search, Alg. 2), ``direct_sum`` (stage 3 by
-direct summation of Eq. 4, Alg. 5) and ``verify`` (the before/after comparison
-with optional early exit, Sec. 3.1).
+direct summation of Eq. 4, Alg. 5), ``direct_sum_check`` (the same fused with
+the certificate comparison and its early exit, Sec. 3.1) and ``verify`` (the
+before/after comparison of two sparse matrices, Sec. 3.1).
 """
 from __future__ import annotations
 
@@ -16,10 +17,11 @@ import ctypes
 
 from . import _lib
 from ._lib import (FLAG_AMBIGUOUS, FLAG_BADLOOP, FLAG_BADPAIR, FLAG_NONFINITE, FLAG_REFIT,
-                   INT_INVALID, LkError)
+                   FLAG_SKIPPED, INT_INVALID, LkError)
 
-__all__ = ["Context", "build_pairs", "direct_sum", "verify", "LkError", "FLAG_REFIT",
-           "FLAG_AMBIGUOUS", "FLAG_NONFINITE", "FLAG_BADPAIR", "FLAG_BADLOOP", "INT_INVALID"]
+__all__ = ["Context", "build_pairs", "direct_sum", "direct_sum_check", "verify", "LkError",
+           "FLAG_REFIT", "FLAG_AMBIGUOUS", "FLAG_NONFINITE", "FLAG_BADPAIR", "FLAG_BADLOOP",
+           "FLAG_SKIPPED", "INT_INVALID"]
 
 
 def _torch():
@@ -141,6 +143,35 @@ class Context:
                                            _ptr(lk), _ptr(flags), _stream(self.device)))
         return real, lk, flags
 
+    def direct_sum_check(self, xyz, offsets, pairs, expected, early_exit: bool = False,
+                         mode: str = "mixed", out=None):
+        """Eq. 4 summed per pair with the fused certificate check
+        (lk_direct_sum_check): each pair's integer is compared with
+        ``expected`` (int32 [P]) as soon as it is final.  Returns
+        ``(lk_real, lk_int, flags, n_mismatch)``, all on the device
+        (``n_mismatch``: int64 [1]).  With ``early_exit`` the kernels stop
+        after the first mismatch; unfinished pairs carry FLAG_SKIPPED."""
+        torch = _torch()
+        self._dev(xyz, None, "xyz")
+        self._dev(offsets, torch.int64, "offsets")
+        self._dev(pairs, torch.int32, "pairs")
+        self._dev(expected, torch.int32, "expected")
+        P = pairs.shape[0] if pairs.dim() == 2 else 0
+        if expected.numel() != P:
+            raise ValueError("expected must have one entry per pair")
+        if out is None:
+            out = (torch.empty(P, dtype=torch.float64, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device),
+                   torch.empty(1, dtype=torch.int64, device=xyz.device))
+        real, lk, flags, nm = out
+        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        self._check(self.lib.lk_direct_sum_check(
+            self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), offsets.numel() - 1, _ptr(pairs), P,
+            _ptr(expected), 1 if early_exit else 0, m, _ptr(real), _ptr(lk), _ptr(flags), _ptr(nm),
+            _stream(self.device)))
+        return real, lk, flags, nm
+
     def autotune(self, xyz, offsets, pairs, mode: str = "mixed", cache_path: str | None = None,
                  out=None) -> dict:
         """Time kernel configurations on this call and keep the fastest
@@ -196,6 +227,11 @@ def build_pairs(xyz, offsets, capacity=None):
 
 def direct_sum(xyz, offsets, pairs, mode="mixed", out=None):
     return context(xyz.device.index or 0).direct_sum(xyz, offsets, pairs, mode, out)
+
+
+def direct_sum_check(xyz, offsets, pairs, expected, early_exit=False, mode="mixed", out=None):
+    return context(xyz.device.index or 0).direct_sum_check(xyz, offsets, pairs, expected,
+                                                           early_exit, mode, out)
 
 
 def verify(pairs, lk, exp_pairs, exp_lk, early_exit=False, cap=1024):

@@ -31,9 +31,15 @@ inline int blocks_for(int64_t n, int threads, int cap = 65535 * 8) {
 template <typename Tin>
 __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, int32_t L,
                                               double* part, uint32_t* lf, double* minseg2,
-                                              int32_t* zero_counts) {
+                                              int32_t* zero_counts,
+                                              unsigned long long* zero_mismatch,
+                                              int32_t* zero_stop) {
   __shared__ double red[256];
   if (blockIdx.x == 0 && threadIdx.x < 2) zero_counts[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && zero_mismatch) {
+    *zero_mismatch = 0ull;
+    *zero_stop = 0;
+  }
   const int64_t v0 = off[0], v1 = off[L];
   const int64_t n3 = 3 * (v1 - v0);
   double s = 0.0;
@@ -258,12 +264,19 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
         A.out.flags[p] = f;
         A.out.lk_real[p] = __builtin_nan("");
         A.out.lk_int[p] = kIntInvalid;
+        check_pair(A.out, p, kIntInvalid, f);
       } else if (items == 0) {
         // nothing to sum (an empty loop, or beyond the supported sizes)
         Outs o = A.out;
         o.refit_list = nullptr;
         finalize_pair(o, p, 0.0, f);
       } else {
+        if (A.out.expected && !refit) {
+          // a fused check marks every pair SKIPPED until it is finalised
+          f |= kFlagSkipped;
+          A.out.lk_real[p] = __builtin_nan("");
+          A.out.lk_int[p] = kIntInvalid;
+        }
         A.out.flags[p] = f;
       }
     }
@@ -288,6 +301,7 @@ __device__ __forceinline__ double from_fixed(unsigned long long lo, unsigned lon
 
 __global__ __launch_bounds__(256) void finalize_split_k(Sched S, const unsigned long long* acc,
                                                         Outs o) {
+  if (o.stop && *o.stop) return;  // a fused check stopped early: sums may be partial
   const int32_t nb = S.counts[1];
   for (int32_t k = blockIdx.x * 256 + threadIdx.x; k < nb; k += gridDim.x * 256) {
     const WorkRec r = S.big[k];
@@ -471,14 +485,14 @@ int prep_blocks(int32_t n_loops) {
 
 hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                        double* xi_partials, uint32_t* lf, double* minseg2, int32_t* zero_counts,
-                       hipStream_t s) {
+                       unsigned long long* zero_mismatch, int32_t* zero_stop, hipStream_t s) {
   const int g = prep_blocks(n_loops);
   if (in_f64)
     prep_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, xi_partials, lf, minseg2,
-                                     zero_counts);
+                                     zero_counts, zero_mismatch, zero_stop);
   else
     prep_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials, lf, minseg2,
-                                    zero_counts);
+                                    zero_counts, zero_mismatch, zero_stop);
   return hipGetLastError();
 }
 
@@ -496,6 +510,13 @@ hipError_t launch_finalize_split(const Sched& sc, const unsigned long long* acc,
 
 hipError_t launch_sched(const Sched& sc, int32_t* zero_next, hipStream_t s) {
   sched_k<<<1, 1024, 0, s>>>(sc, zero_next);
+  return hipGetLastError();
+}
+
+__global__ void zero_i64_k(int64_t* p) { *p = 0; }
+
+hipError_t launch_zero_i64(int64_t* p, hipStream_t s) {
+  zero_i64_k<<<1, 1, 0, s>>>(p);
   return hipGetLastError();
 }
 

@@ -65,7 +65,23 @@ __device__ __forceinline__ float fmad(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// FP64 square root from the hardware reciprocal-square-root estimate and two
+// Goldschmidt iterations (s -> sqrt(x), h -> 1 / (2 sqrt(x))), then one
+// Newton correction on the residual x - s^2.  No range scaling: arguments
+// are squared distances of geometry, far from the FP64 limits; x = 0 gives
+// NaN, which only happens for coincident vertices (a degenerate pair, flagged).
+__device__ __forceinline__ double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  return fma(fma(-s, s, x), h, s);
+}
 
 // Own FP32 arctangent: octant reduction to t = min/max in [0, 1], then
 // atan(t) = t q(t^2) with q the Remez minimax polynomial of atan_poly.h.
@@ -88,6 +104,28 @@ __device__ __forceinline__ float atan2_minimax(float y, float x) {
   return atan2_reduced(y, x, fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay)));
 }
 
+// Own FP64 arctangent: the same octant reduction, t = min/max from the
+// hardware reciprocal estimate with two Newton steps and a residual
+// correction (no IEEE division sequence), and the degree-19 polynomial of
+// atan_poly.h (relative error 2.5e-16 in FP64 Horner form).
+__device__ __forceinline__ double atan2_f64(double y, double x) {
+  const double ax = fabs(x), ay = fabs(y);
+  const double mx = fmax(ax, ay), mn = fmin(ax, ay);
+  double r = __builtin_amdgcn_rcp(mx);
+  r = fma(r, fma(-mx, r, 1.0), r);
+  r = fma(r, fma(-mx, r, 1.0), r);
+  const double q = mn * r;
+  const double t = fma(fma(-mx, q, mn), r, q);
+  const double s = t * t;
+  double p = kAtanQ64[LK_ATAN_DEG64];
+#pragma unroll
+  for (int k = LK_ATAN_DEG64 - 1; k >= 0; --k) p = fma(p, s, kAtanQ64[k]);
+  double a = t * p;
+  a = (ay > ax) ? (1.57079632679489661923 - a) : a;
+  a = (x < 0.0) ? (3.14159265358979323846 - a) : a;
+  return copysign(a, y);
+}
+
 template <typename T, int AT>
 __device__ __forceinline__ T angle(T y, T x);
 template <>
@@ -100,7 +138,7 @@ __device__ __forceinline__ float angle<float, 1>(float y, float x) {
 }
 template <>
 __device__ __forceinline__ double angle<double, 0>(double y, double x) {
-  return atan2(y, x);
+  return atan2_f64(y, x);
 }
 template <>
 __device__ __forceinline__ double angle<double, 1>(double y, double x) {
@@ -400,13 +438,22 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   const int64_t total = big_total + (n_small + A.batch - 1) / A.batch;
 
   // the next work index is fetched one item ahead so the atomic's latency
-  // overlaps the current item's arithmetic
+  // overlaps the current item's arithmetic; a fused check's stop flag is read
+  // with it (device-scope load, so another wave's store is seen)
   unsigned long long wnext = 0;
-  if (lane == 0) wnext = atomicAdd(A.s.counter, 1ull);
+  int stopnext = 0;
+  if (lane == 0) {
+    wnext = atomicAdd(A.s.counter, 1ull);
+    if (A.out.stop) stopnext = __hip_atomic_load(A.out.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (;;) {
     const int64_t w = (int64_t)__shfl(wnext, 0);
-    if (w >= total) break;
-    if (lane == 0) wnext = atomicAdd(A.s.counter, 1ull);
+    if (w >= total || __shfl(stopnext, 0)) break;
+    if (lane == 0) {
+      wnext = atomicAdd(A.s.counter, 1ull);
+      if (A.out.stop)
+        stopnext = __hip_atomic_load(A.out.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 
     if (w < big_total) {
       // one item of a big pair: position with big_prefix[pos] <= w < big_prefix[pos + 1]

@@ -52,6 +52,13 @@ struct Outs {
   int32_t* refit_n;            // its length
   double thr;                  // |v - round(v)| above this queues (main) or flags AMBIGUOUS
   int32_t refit_pass;          // 1: the pass over the refit list (sets LK_FLAG_REFIT)
+  // fused check (NULL expected: none): final integers are compared with
+  // expected[p]; mismatches are counted, and with early_exit the first one
+  // sets *stop, which the kernels poll before taking new work
+  const int32_t* expected;
+  unsigned long long* n_mismatch;
+  int32_t* stop;
+  int32_t early_exit;
 };
 
 // Per-loop validation results of the preparation kernel.
@@ -88,7 +95,17 @@ struct DsArgs {
 };
 
 constexpr uint32_t kFlagRefit = 1u, kFlagAmbiguous = 2u, kFlagNonfinite = 4u, kFlagBadpair = 8u,
-                   kFlagBadloop = 16u;
+                   kFlagBadloop = 16u, kFlagSkipped = 32u;
+constexpr uint32_t kFlagUncertified = kFlagNonfinite | kFlagAmbiguous | kFlagBadpair | kFlagBadloop;
+
+// Fused check of one final pair (see Outs).
+__device__ __forceinline__ void check_pair(const Outs& o, int32_t p, int32_t value, uint32_t f) {
+  if (!o.expected) return;
+  if ((f & kFlagUncertified) || value != o.expected[p]) {
+    atomicAdd(o.n_mismatch, 1ull);
+    if (o.early_exit) atomicExch(o.stop, 1);
+  }
+}
 constexpr int32_t kIntInvalid = INT32_MIN;
 
 // Rounds and flags one pair's value and writes its outputs (a6 of the path):
@@ -97,17 +114,20 @@ constexpr int32_t kIntInvalid = INT32_MIN;
 // AMBIGUOUS (or NONFINITE) otherwise.  Called by one lane per pair.
 __device__ __forceinline__ void finalize_pair(const Outs& o, int32_t p, double v, uint32_t f) {
   bool requeue = false;
+  f &= ~kFlagSkipped;
   if (o.refit_pass) f |= kFlagRefit;
+  double real;
+  int32_t ival;
   const bool bad = (f & kFlagNonfinite) || !isfinite(v) || fabs(v) > 2.0e9;
   if (bad) {
     f |= kFlagNonfinite;
-    o.lk_real[p] = __builtin_nan("");
-    o.lk_int[p] = kIntInvalid;
+    real = __builtin_nan("");
+    ival = kIntInvalid;
     requeue = o.refit_list != nullptr;
   } else {
     const double r = round(v);  // half away from zero
-    o.lk_real[p] = v;
-    o.lk_int[p] = (int32_t)r;
+    real = v;
+    ival = (int32_t)r;
     if (fabs(v - r) > o.thr) {
       if (o.refit_list)
         requeue = true;
@@ -115,8 +135,20 @@ __device__ __forceinline__ void finalize_pair(const Outs& o, int32_t p, double v
         f |= kFlagAmbiguous;
     }
   }
+  if (requeue && o.expected) {
+    // a fused check leaves the pair undecided (SKIPPED, no value) until the
+    // FP64 refit finalises it
+    real = __builtin_nan("");
+    ival = kIntInvalid;
+    f |= kFlagSkipped;
+  }
+  o.lk_real[p] = real;
+  o.lk_int[p] = ival;
   o.flags[p] = f;
-  if (requeue) o.refit_list[atomicAdd(o.refit_n, 1)] = p;
+  if (requeue)
+    o.refit_list[atomicAdd(o.refit_n, 1)] = p;
+  else
+    check_pair(o, p, ival, f);
 }
 
 // --- lk_ds.hip
@@ -138,10 +170,12 @@ constexpr int kPrepMaxBlocks = 4096;  // most workgroups (xi partials buffer siz
 int prep_blocks(int32_t n_loops);
 // xi partial sums (one per workgroup) and, one wavefront per loop, the loop's
 // NONFINITE / <3-vertex bits and shortest squared segment; zeroes the main
-// pass's two schedule counts.
+// pass's two schedule counts and (when given) the fused check's mismatch
+// count and stop flag.
 hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                        double* xi_partials /*[prep_blocks]*/, uint32_t* lf, double* minseg2,
-                       int32_t* zero_counts, hipStream_t s);
+                       int32_t* zero_counts, unsigned long long* zero_mismatch,
+                       int32_t* zero_stop, hipStream_t s);
 // Per list position: validate the pair, apply the zero-length test (xi from
 // the partials), zero its accumulator, count its work items and append its
 // record to the small or big list; pairs without work are finalised here.
@@ -156,6 +190,8 @@ hipError_t launch_finalize_split(const Sched& s, const unsigned long long* acc, 
 // work counter and (optionally) three int32 of the next pass: its two
 // schedule counts and the refit count that follows them in memory.
 hipError_t launch_sched(const Sched& s, int32_t* zero_counts_next, hipStream_t st);
+// *p = 0 with a kernel (safe inside a captured sequence).
+hipError_t launch_zero_i64(int64_t* p, hipStream_t s);
 // Exclusive scan of counts[0..n) into prefix[0..n] (single workgroup).
 hipError_t launch_scan(const int64_t* counts, int64_t n, int64_t* prefix, hipStream_t s);
 // Potential link search.

@@ -36,7 +36,8 @@ struct DevBuf {
 };
 
 using GraphKey = std::tuple<const void*, int, const void*, int32_t, const void*, int64_t, int,
-                            void*, void*, void*, int, int, int, int, int64_t>;
+                            void*, void*, void*, int, int, int, int, int64_t, const void*, void*,
+                            int>;
 
 }  // namespace
 
@@ -132,7 +133,16 @@ constexpr size_t kMetaBigTotalMain = 24; // int64
 constexpr size_t kMetaBigTotalRefit = 32;
 constexpr size_t kMetaCounterMain = 40;  // uint64 work counters
 constexpr size_t kMetaCounterRefit = 48;
+constexpr size_t kMetaStop = 56;         // int32: fused check's stop flag
 constexpr size_t kMetaBytes = 64;
+
+// Fused certificate check of a call (lk_direct_sum_check); empty for
+// lk_direct_sum.
+struct Check {
+  const int32_t* expected = nullptr;
+  int early_exit = 0;
+  int64_t* n_mismatch = nullptr;
+};
 
 template <typename T>
 T* meta_at(lk_ctx* ctx, size_t off) {
@@ -156,7 +166,7 @@ lk::Sched make_sched(lk_ctx* ctx, int64_t n_pairs, bool refit) {
 lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const int64_t* off,
                              int32_t n_loops, const int32_t* pairs, int64_t n_pairs,
                              double* lk_real, int32_t* lk_int, uint32_t* flags, hipStream_t s,
-                             hipEvent_t* ev /* 4 events or NULL */) {
+                             hipEvent_t* ev /* 4 events or NULL */, const Check& ck = Check()) {
   const bool timed = ev != nullptr;
   using namespace lk;
   uint32_t* lf = (uint32_t*)ctx->loop_flags.p;
@@ -180,6 +190,10 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   out.refit_n = P.mixed ? rn : nullptr;
   out.thr = ctx->refit_thr;
   out.refit_pass = 0;
+  out.expected = ck.expected;
+  out.n_mismatch = ck.expected ? (unsigned long long*)ck.n_mismatch : nullptr;
+  out.stop = ck.expected ? meta_at<int32_t>(ctx, kMetaStop) : nullptr;
+  out.early_exit = ck.expected ? ck.early_exit : 0;
 
   PlanArgs M{};
   M.off = off;
@@ -201,7 +215,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   A.out = out;
 
   LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
-                     s));
+                     out.n_mismatch, out.stop, s));
   LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
   LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
   if (timed) LK_HIP(hipEventRecord(ev[0], s));
@@ -387,9 +401,12 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
   return LK_OK;
 }
 
-lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
-                        int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
-                        double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream) {
+namespace {
+
+lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                          int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                          double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream,
+                          const Check& ck) {
   if (!ctx) return LK_EINVAL;
   ctx->err.clear();
   if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
@@ -403,7 +420,10 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   if (st != LK_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   ctx->stats = lk_stats{};
-  if (n_pairs == 0) return LK_OK;
+  if (n_pairs == 0) {
+    if (ck.n_mismatch) LK_HIP(lk::launch_zero_i64(ck.n_mismatch, s));
+    return LK_OK;
+  }
 
   const bool in_f64 = dtype == LK_F64;
   const bool mixed = mode == LK_MIXED;
@@ -436,7 +456,7 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
       ev = &ctx->ring[4 * (size_t)(ctx->ring_pos % slots)];
     }
     st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
-                            ev);
+                            ev, ck);
     if (timed && st == LK_OK) {
       const int slots = (int)(ctx->ring.size() / 4);
       ctx->ring_pos = (ctx->ring_pos + 1) % slots;
@@ -448,7 +468,7 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   GraphKey key{xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int, flags,
                P.tile, P.chunk, P.grid,
                ctx->opt_batch * 1024 + P.atan_form * 16 + P.segs * 4 + P.segs64,
-               (int64_t)(ctx->refit_thr * 1e9)};
+               (int64_t)(ctx->refit_thr * 1e9), ck.expected, ck.n_mismatch, ck.early_exit};
   auto it = ctx->graphs.find(key);
   if (it != ctx->graphs.end() && it->second.epoch == ctx->ws_epoch && it->second.exec) {
     LK_HIP(hipGraphLaunch(it->second.exec, s));
@@ -461,7 +481,7 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   }
   LK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
-                          nullptr);
+                          nullptr, ck);
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
   if (st != LK_OK) {
@@ -482,6 +502,33 @@ lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* 
   ctx->graphs[key] = {ex, ctx->ws_epoch};
   LK_HIP(hipGraphLaunch(ex, s));
   return LK_OK;
+}
+
+}  // namespace
+
+lk_status lk_direct_sum(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                        int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                        double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream) {
+  return direct_sum_call(ctx, xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int,
+                         flags, stream, Check());
+}
+
+lk_status lk_direct_sum_check(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                              int32_t n_loops, const int32_t* pairs, int64_t n_pairs,
+                              const int32_t* expected, int early_exit, int mode, double* lk_real,
+                              int32_t* lk_int, uint32_t* flags, int64_t* n_mismatch,
+                              void* stream) {
+  if (!ctx) return LK_EINVAL;
+  if (!n_mismatch || (n_pairs > 0 && !expected)) {
+    ctx->err.clear();
+    return ctx->fail(LK_EINVAL, "null expected or n_mismatch");
+  }
+  Check ck;
+  ck.expected = expected;
+  ck.early_exit = early_exit ? 1 : 0;
+  ck.n_mismatch = n_mismatch;
+  return direct_sum_call(ctx, xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int,
+                         flags, stream, ck);
 }
 
 lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
