@@ -24,7 +24,11 @@ and reports throughput beside p50/p99 latency.
 Prints ONE JSON line.  Options:
   --steps K --warmup W   timed / untimed steps (default 20 / 3)
   --config NAME          ring_grid | chainmail | knit | long_pairs | serving
-  --mode mixed|plain     mode of the headline value (default mixed)
+  --mode mixed|plain|crossings
+                         mode of the headline value (default mixed); with mixed,
+                         plain FP64 and the crossing count (Alg. 4) are timed on
+                         the same input and reported beside it
+  --no-plain, --no-crossings   skip those companion legs
   --no-cpu-baseline      skip the oracle leg
   --no-tune              keep the default kernel configuration
   --gpus N               only N = 1 is supported (one GPU per process)
@@ -43,6 +47,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_TERM = 90  # arithmetic of Eq. 4 as printed in Alg. 5 (sqrt/atan2 not counted)
+# crossing count: a 2D segment-intersection test is four orientation
+# determinants of 5 FLOP each (projection and sign bookkeeping not counted)
+FLOP_PER_TERM_CC = 20
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 
@@ -97,10 +104,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="chainmail", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="mixed", choices=["mixed", "plain"])
+    ap.add_argument("--mode", default="mixed", choices=["mixed", "plain", "crossings"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 companion run")
+    ap.add_argument("--no-crossings", action="store_true",
+                    help="skip the crossing-count companion run")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
@@ -226,11 +235,17 @@ def main():
                                                      args.tune_cache)
         other = time_mode(ctx, xyz, off, pairs, "plain", max(args.steps // 2, 1),
                           min(args.warmup, 1), lk)
+    cc, tuned_cc = None, None
+    if not args.no_crossings and args.mode == "mixed":
+        tuned_cc = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "crossings", lk,
+                                                  args.tune_cache)
+        cc = time_mode(ctx, xyz, off, pairs, "crossings", args.steps, args.warmup, lk)
 
     value = T / (res["ms_per_step"] * 1e-3)
     fp64 = args.mode == "plain"
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
-    achieved = FLOP_PER_TERM * T / (res["kernel_ms"] * 1e-3) / 1e12 if res["kernel_ms"] > 0 else 0.0
+    fpt = FLOP_PER_TERM_CC if args.mode == "crossings" else FLOP_PER_TERM
+    achieved = fpt * T / (res["kernel_ms"] * 1e-3) / 1e12 if res["kernel_ms"] > 0 else 0.0
     line = {
         "metric": "segment-pair evals/s",
         "value": value,
@@ -242,7 +257,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if fp64 else "f32+f64",
+        "dtype": "f64" if fp64 else ("f32 predicates+f64" if args.mode == "crossings"
+                                     else "f32+f64"),
         "data": "synthetic",
         "config": {"workload": args.config, "description": WORKLOADS[args.config],
                    "loops": int(ls.n_loops), "pairs": int(len(pr)), "terms": T,
@@ -250,8 +266,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": measured_traffic(args.config, args.mode, tuned),
-                     "kernel": "ds_persistent (%s)" % ("FP64" if fp64 else "FP32 terms"),
-                     "kernel_ms": res["kernel_ms"], "flop_per_term": FLOP_PER_TERM},
+                     "kernel": "ds_persistent (%s)" % ("FP64" if fp64 else (
+                         "FP32 crossing count" if args.mode == "crossings" else "FP32 terms")),
+                     "kernel_ms": res["kernel_ms"], "flop_per_term": fpt},
         "graph_replayed": res["graph_replayed"],
         "eager_ms_per_step": res["eager_ms_per_step"],
         "tuned": tuned,
@@ -271,8 +288,23 @@ def main():
             "max_abs_diff_vs_mixed": float(np.max(np.abs(other["real"] - res["real"]))),
             "tuned": tuned_plain,
         }
+    if cc is not None:
+        ach = FLOP_PER_TERM_CC * T / (cc["kernel_ms"] * 1e-3) / 1e12 if cc["kernel_ms"] > 0 else 0.0
+        line["crossings"] = {
+            "value": T / (cc["ms_per_step"] * 1e-3),
+            "ms_per_step": cc["ms_per_step"],
+            "eager_ms_per_step": cc["eager_ms_per_step"],
+            "kernel_ms": cc["kernel_ms"],
+            "refit_kernel_ms": cc["refit_kernel_ms"],
+            "refits": cc["refits"],
+            "roofline_frac_fp32": ach / PEAK_FP32_TFLOPS,
+            "flop_per_term": FLOP_PER_TERM_CC,
+            "int_mismatch_vs_mixed": int(np.sum(cc["lk"] != res["lk"])),
+            "int_mismatch_vs_construction": int(np.sum(cc["lk"] != exp)),
+            "tuned": tuned_cc,
+        }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads)
+        line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -320,7 +352,7 @@ def run_serving(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(ls, pr, res, other, threads):
+def cpu_baseline(ls, pr, res, other, threads, cc=None):
     """Time the FP64 oracle on the host cores over a bounded sample of pairs
     (the whole pair list when it is small enough), and compare the GPU results
     on that sample with it."""
@@ -358,6 +390,8 @@ def cpu_baseline(ls, pr, res, other, threads):
     if other is not None and len(idx):
         errs["err_vs_oracle"]["plain_max"] = float(np.max(np.abs(other["real"][idx] - oreal)))
         errs["err_vs_oracle"]["plain_int_mismatch"] = int(np.sum(other["lk"][idx] != olk))
+    if cc is not None and len(idx):
+        errs["err_vs_oracle"]["crossings_int_mismatch"] = int(np.sum(cc["lk"][idx] != olk))
     cpu = {"value": terms / dt, "unit": "segment-pairs/s", "cores": cores, "kind": "oracle",
            "sample": sample, "seconds": dt, "terms": terms}
     return cpu, errs

@@ -59,8 +59,18 @@ typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
  * exactly).  MIXED: terms in FP32, per-thread sums in FP32 over at most one
  * LDS tile, everything from the per-tile partial upwards in FP64, and every
  * pair whose |value - round(value)| exceeds the refit threshold (default 0.05)
- * recomputed entirely in FP64 from the caller's input. */
-typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1 } lk_mode;
+ * recomputed entirely in FP64 from the caller's input.
+ * CROSSINGS: Count Crossings (Sec. 2.1, Alg. 4) in place of the FP32 direct
+ * sum: the value is half the signed number of crossings of the projection
+ * along the context's view direction (lk_set_view_direction).  Every side
+ * test and crossing sign is decided in FP32 only when its magnitude exceeds a
+ * forward error bound, on the vertices as given (FP64 input is rounded to
+ * FP32 for this pass), so for FP32 input a certified count is exact.  A pair
+ * with an undecided test (a crossing at or near a vertex, near-parallel or
+ * nearly touching segments) or an odd count is recomputed by the FP64 direct
+ * sum exactly as MIXED refits (LK_FLAG_REFIT); lk_real of the other pairs is
+ * the count / 2. */
+typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1, LK_CROSSINGS = 2 } lk_mode;
 
 /* Per-pair flags (bit set). */
 enum {
@@ -165,13 +175,27 @@ enum {
   LK_OPT_ATAN = 7,                /* FP32 arctangent: 0 = own minimax, the R terms of a step
                                      in phases; 1 = HIP atan2f; 2 = own minimax, term by
                                      term (same values as 0, another instruction order) */
-  LK_OPT_SEGS_PER_LANE = 8,       /* FP32 kernel: segments of loop B per lane, 1/2/4 (0 = tuned) */
+  LK_OPT_SEGS_PER_LANE = 8,       /* FP32 kernel: segments of loop B per lane, 1/2/4, and 8 for
+                                     CROSSINGS (0 = tuned; the direct sum uses 4 for 8) */
   LK_OPT_SEGS_PER_LANE_F64 = 9,   /* FP64 kernel: segments of loop B per lane, 1/2 (0 = tuned) */
-  LK_OPT_SMALL_BATCH = 10         /* small pairs claimed per work-counter step, 1..64 (0 = tuned) */
+  LK_OPT_SMALL_BATCH = 10,        /* small pairs claimed per work-counter step, 1..64 (0 = tuned);
+                                     the FP32 passes use at least the segments per lane */
+  LK_OPT_CROSSING_TOL = 11        /* CROSSINGS: multiplier of the certainty bounds, 1..2^20
+                                     (default 1); larger values send more pairs to the FP64
+                                     direct sum, never fewer */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */
 lk_status lk_set_option(lk_ctx* ctx, int key, int64_t value);
+
+/* View direction of the CROSSINGS mode (Sec. 2.1: the projection must be
+ * regular, and a random frame makes that almost certain, Alg. 4).  dir is a
+ * host array of 3 finite values, not all zero; it is scaled so that its
+ * largest magnitude is 1 and rounded to FP32.  The sign of each crossing does
+ * not depend on which way along the line one looks.  Default: a fixed generic
+ * direction.  lk_get_view_direction returns the direction in use (host). */
+lk_status lk_set_view_direction(lk_ctx* ctx, const double* dir);
+lk_status lk_get_view_direction(const lk_ctx* ctx, double* dir);
 
 typedef struct {
   int64_t refits;         /* pairs recomputed in FP64 by the last MIXED call */
@@ -179,7 +203,8 @@ typedef struct {
   double refit_kernel_ms; /* mean refit-kernel time over the same calls (MIXED) */
   int32_t timed_calls;    /* number of calls those means cover */
   int32_t graph_replayed; /* 1 if the last call replayed a captured graph */
-  int32_t tile_a, chunk_a, waves_per_cu, atan_form, segs_per_lane; /* configuration used */
+  int32_t tile_a, chunk_a, waves_per_cu, atan_form, segs_per_lane; /* configuration used
+                            (atan_form 3: the crossing count) */
 } lk_stats;
 
 /* ------------------------------------------------------------ autotuner */

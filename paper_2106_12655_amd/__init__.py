@@ -90,6 +90,17 @@ class Context:
     def set_option(self, key: int, value: int):
         self._check(self.lib.lk_set_option(self.h, int(key), int(value)))
 
+    def set_view_direction(self, direction):
+        """Projection direction of mode ``"crossings"`` (lk_set_view_direction)."""
+        d = (ctypes.c_double * 3)(*[float(x) for x in direction])
+        self._check(self.lib.lk_set_view_direction(self.h, d))
+
+    def view_direction(self) -> tuple:
+        """The direction in use: scaled to largest magnitude 1, FP32 values."""
+        d = (ctypes.c_double * 3)()
+        self._check(self.lib.lk_get_view_direction(self.h, d))
+        return tuple(d)
+
     def stats(self) -> dict:
         s = _lib.Stats()
         self._check(self.lib.lk_get_stats(self.h, ctypes.byref(s)))
@@ -121,8 +132,10 @@ class Context:
 
         Returns ``(lk_real float64[P], lk_int int32[P], flags int32[P])`` on the
         device (flags hold the LK_FLAG_* bits).  ``mode`` is ``"mixed"`` (FP32
-        terms, FP64 pair sums and FP64 refit of ambiguous pairs) or ``"plain"``
-        (FP64 throughout).  ``out``: optional preallocated output triple.
+        terms, FP64 pair sums and FP64 refit of ambiguous pairs), ``"plain"``
+        (FP64 throughout) or ``"crossings"`` (certified crossing count of a
+        projection, Alg. 4, with the FP64 direct sum for undecided pairs).
+        ``out``: optional preallocated output triple.
         """
         torch = _torch()
         self._dev(xyz, None, "xyz")
@@ -137,7 +150,7 @@ class Context:
             flags = torch.empty(P, dtype=torch.int32, device=xyz.device)
         else:
             real, lk, flags = out
-        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        m = _lib.MODES[mode]
         self._check(self.lib.lk_direct_sum(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets),
                                            offsets.numel() - 1, _ptr(pairs), P, m, _ptr(real),
                                            _ptr(lk), _ptr(flags), _stream(self.device)))
@@ -165,7 +178,7 @@ class Context:
                    torch.empty(P, dtype=torch.int32, device=xyz.device),
                    torch.empty(1, dtype=torch.int64, device=xyz.device))
         real, lk, flags, nm = out
-        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        m = _lib.MODES[mode]
         self._check(self.lib.lk_direct_sum_check(
             self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), offsets.numel() - 1, _ptr(pairs), P,
             _ptr(expected), 1 if early_exit else 0, m, _ptr(real), _ptr(lk), _ptr(flags), _ptr(nm),
@@ -186,7 +199,7 @@ class Context:
                    torch.empty(P, dtype=torch.int32, device=xyz.device),
                    torch.empty(P, dtype=torch.int32, device=xyz.device))
         t = _lib.Tuning()
-        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        m = _lib.MODES[mode]
         self._check(self.lib.lk_autotune(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets),
                                          offsets.numel() - 1, _ptr(pairs), P, m, _ptr(out[0]),
                                          _ptr(out[1]), _ptr(out[2]),

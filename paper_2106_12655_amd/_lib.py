@@ -17,16 +17,18 @@ _lib = None
 # lk_status
 OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
-PLAIN_F64, MIXED = 0, 1
+PLAIN_F64, MIXED, CROSSINGS = 0, 1, 2
+MODES = {"plain": PLAIN_F64, "mixed": MIXED, "crossings": CROSSINGS}
 FLAG_REFIT, FLAG_AMBIGUOUS, FLAG_NONFINITE, FLAG_BADPAIR, FLAG_BADLOOP = 1, 2, 4, 8, 16
 FLAG_SKIPPED = 32
 INT_INVALID = -(2 ** 31)
 OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 3, 4, 5
 OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
-OPT_SMALL_BATCH = 10
+OPT_SMALL_BATCH, OPT_CROSSING_TOL = 10, 11
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
-           "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_get_stats", "lk_autotune", "lk_reserve",
+           "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_set_view_direction",
+           "lk_get_view_direction", "lk_get_stats", "lk_autotune", "lk_reserve",
            "lk_server_create", "lk_server_destroy", "lk_server_last_error",
            "lk_server_open_session", "lk_server_close_session", "lk_server_submit",
            "lk_server_wait"]
@@ -101,6 +103,10 @@ def load():
         lib.lk_verify.restype = st
         lib.lk_set_option.argtypes = [p, ctypes.c_int, i64]
         lib.lk_set_option.restype = st
+        lib.lk_set_view_direction.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
+        lib.lk_set_view_direction.restype = st
+        lib.lk_get_view_direction.argtypes = [p, ctypes.POINTER(ctypes.c_double)]
+        lib.lk_get_view_direction.restype = st
         lib.lk_get_stats.argtypes = [p, ctypes.POINTER(Stats)]
         lib.lk_get_stats.restype = st
         lib.lk_autotune.argtypes = [p, p, ctypes.c_int, p, i32, p, i64, ctypes.c_int, p, p, p,

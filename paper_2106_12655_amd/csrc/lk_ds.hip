@@ -402,17 +402,191 @@ __device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Count Crossings (Sec. 2.1, Alg. 4): the linking number is half the signed
+// number of crossings of a regular projection.  The projection is along a view
+// direction n (uniform over the launch).  Two projected segments cross iff the
+// endpoints of each lie strictly on opposite sides of the other's line.  The
+// side of a point x relative to the projected line through y with direction e
+// is the sign of (x - y) . (n x e), so no coordinate is rotated: a step forms
+// u = n x s_j once and every lane holds t_r = n x s_r.  With v_r = l_{j+1} - k_r:
+//   side of k_r      w.r.t. segment j's line:  w_r = v_r . u
+//   side of l_{j+1}  w.r.t. segment r's line:  q_r = v_r . t_r
+// (the side of l_j is the previous step's q_r).  At a crossing the points of
+// the two segments over the crossing differ by h n, so the Eq. 4 numerator
+// p = a . (s_j x s_r) = v_r . (s_j x s_r) = h n . (s_j x s_r) has the sign of
+// the crossing (over tangent x under tangent, against n); the count sums
+// sign(p) and the pair's value is half of it.
+//
+// Every predicate is certified in FP32 on the vertices as given: a value
+// counts only when its magnitude exceeds a forward error bound of the form
+// tau |first|_inf |second|_inf (about 63 u for w and q, 216 u for p with the
+// unit roundoff u = 2^-24, from first-order error analysis of the differences,
+// the cross products and the dot products; tau defaults to twice that).  A
+// term that is neither certainly crossing nor certainly not crossing -- a
+// crossing at or near a vertex, near-parallel projected segments, segments
+// that nearly touch in space -- or an odd total makes the pair's value NaN or
+// a half-integer, which sends the pair to the FP64 direct sum.  Needs
+// |n|_inf <= 1 (the runtime scales n so).
+constexpr int kCrossings = 3;  // term form of the kernel's template: crossing count
+
+template <typename T, int R>
+struct CcSegs {
+  V3<T> k[R + 1];
+  V3<T> t[R];    // n x s_r
+  T cq[R];       // tau |s_r|_inf: certainty scale of q_r
+  T sn[R];       // |s_r|_inf
+  V3<T> n;       // view direction
+  T tau, tau_p;
+  bool valid[R];
+};
+
+// Walk state at l_j: the vertex and the certified sides of l_j relative to
+// the lane's R segment lines (0 = uncertain).
+template <typename T, int R>
+struct CcWalk {
+  V3<T> l;
+  T Q[R];
+};
+
+template <typename T>
+__device__ __forceinline__ T inf_norm(const V3<T>& a) {
+  return fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fabsf(a.z));
+}
+
+// x if |x| > tol, else 0 (the sign survives only when it is certain; NaN -> 0)
+__device__ __forceinline__ float certain(float x, float tol) { return fabsf(x) > tol ? x : 0.0f; }
+
+template <typename Tc, int R>
+__device__ __forceinline__ void make_lane(const V3<Tc>* k, const Layout& L, const DsArgs& A,
+                                          CcSegs<Tc, R>& sg) {
+  const int first = L.bi * R;
+  sg.n = V3<Tc>{A.view[0], A.view[1], A.view[2]};
+  sg.tau = A.cc_tau;
+  sg.tau_p = A.cc_tau_p;
+#pragma unroll
+  for (int r = 0; r <= R; ++r) sg.k[r] = k[r];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const V3<Tc> s = sg.k[r + 1] - sg.k[r];
+    sg.t[r] = cross(sg.n, s);
+    sg.sn[r] = inf_norm(s);
+    sg.cq[r] = sg.tau * sg.sn[r];
+    sg.valid[r] = first + r < L.nbh;
+  }
+}
+
+template <typename Tc, int R>
+__device__ __forceinline__ void cc_init(CcWalk<Tc, R>& w, const V3<Tc>& l, const CcSegs<Tc, R>& g) {
+  w.l = l;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const V3<Tc> V = l - g.k[r];
+    w.Q[r] = certain(dot(V, g.t[r]), g.cq[r] * inf_norm(V));
+  }
+}
+
+// One step l_j -> l_{j+1} against the lane's R segments: adds the certified
+// crossing signs to cnt, sets bad when a term is undecided.
+template <typename Tc, int R>
+__device__ __forceinline__ void cc_step(CcWalk<Tc, R>& w, const V3<Tc>& l1, const CcSegs<Tc, R>& g,
+                                        int& cnt, bool& bad) {
+  const V3<Tc> sj = l1 - w.l;
+  const V3<Tc> u = cross(g.n, sj);
+  const Tc sjn = inf_norm(sj);
+  const Tc cw = g.tau * sjn;
+  V3<Tc> v[R + 1];
+  Tc nv[R + 1], wc[R + 1];
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    v[r] = l1 - g.k[r];
+    nv[r] = inf_norm(v[r]);
+    wc[r] = certain(dot(v[r], u), cw * nv[r]);
+  }
+  Tc Wp[R], Qp[R];
+  bool cand[R];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const Tc qc = certain(dot(v[r], g.t[r]), g.cq[r] * nv[r]);
+    Wp[r] = wc[r] * wc[r + 1];  // < 0: k_r, k_{r+1} certainly on opposite sides
+    Qp[r] = w.Q[r] * qc;        // < 0: l_j, l_{j+1} certainly on opposite sides
+    w.Q[r] = qc;
+    // either product certainly positive: certainly no crossing
+    cand[r] = g.valid[r] && !(fmaxf(Wp[r], Qp[r]) > (Tc)0);
+    any = any || cand[r];
+  }
+  w.l = l1;
+  if (any) {  // rare: a crossing or an undecided term somewhere in the lane
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!cand[r]) continue;
+      const V3<Tc> s = g.k[r + 1] - g.k[r];
+      const Tc p = dot(v[r], cross(sj, s));
+      const Tc tp = g.tau_p * g.sn[r] * sjn * nv[r];
+      if (Wp[r] < (Tc)0 && Qp[r] < (Tc)0 && fabsf(p) > tp)
+        cnt += p > (Tc)0 ? 1 : -1;
+      else
+        bad = true;
+    }
+  }
+}
+
+template <typename Tc, int AT, int R>
+__device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, int jhi, int js,
+                                          CcWalk<Tc, R>& wk, const CcSegs<Tc, R>& sg,
+                                          double& acc) {
+  if (jlo == js) {
+    const Vtx<Tc> v0 = lds[jlo - t0];
+    cc_init(wk, V3<Tc>{v0.x, v0.y, v0.z}, sg);
+  }
+  int cnt = 0;
+  bool bad = false;
+#pragma unroll 2
+  for (int j = jlo; j < jhi; ++j) {
+    const Vtx<Tc> v1 = lds[j - t0 + 1];
+    cc_step(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg, cnt, bad);
+  }
+  acc += bad ? __builtin_nan("") : (double)cnt;
+}
+
+// Per-lane state of the term form AT (the direct sum's, or the crossing count's).
+template <typename Tc, int AT, int R>
+struct LaneOf {
+  using S = Segs<Tc, R>;
+  using W = Walk<Tc, R>;
+};
+template <typename Tc, int R>
+struct LaneOf<Tc, kCrossings, R> {
+  using S = CcSegs<Tc, R>;
+  using W = CcWalk<Tc, R>;
+};
+
+template <typename Tc, int R>
+__device__ __forceinline__ void make_lane(const V3<Tc>* k, const Layout& L, const DsArgs&,
+                                          Segs<Tc, R>& sg) {
+  make_segs<Tc, R>(k, L, sg);
+}
+
+// Scale from the lane sums to the pair's value: 1 / (2 pi) for the direct
+// sum's angles, 1/2 for crossing signs.
+template <int AT>
+__device__ __forceinline__ double value_scale() {
+  return AT == kCrossings ? 0.5 : kInvTwoPi;
+}
+
 // Wave sum of the lanes' partials.  `whole`: this item is the pair's only one,
 // so its value is final and the pair is finalised at once (`fpre`: the pair's
 // flags as the plan left them, loaded when the item started so that finishing
 // does not wait on a load).  Otherwise the sum goes into the pair's fixed-point
 // accumulator, and the pair is finalised after this kernel, from the big list.
+template <int AT>
 __device__ __forceinline__ void finish_item(double acc, int32_t p, int lane, const DsArgs& A,
                                             bool whole, uint32_t fpre) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane != 0) return;
-  const double v = acc * kInvTwoPi;
+  const double v = acc * value_scale<AT>();
   const bool ok = fabs(v) < 1.0e14;  // false for NaN / Inf / absurd magnitude
   if (whole)
     finalize_pair(A.out, p, v, fpre | (ok ? 0u : kFlagNonfinite));
@@ -470,9 +644,9 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
       const Layout L = layout<R>(r, w - A.s.big_prefix[lo], A.chunk, lane);
       V3<Tc> kv[R + 1];
       load_b<Tin, Tc, R>(X, r, L, kv);
-      Segs<Tc, R> sg;
-      make_segs<Tc, R>(kv, L, sg);
-      Walk<Tc, R> wk;
+      typename LaneOf<Tc, AT, R>::S sg;
+      make_lane<Tc, R>(kv, L, A, sg);
+      typename LaneOf<Tc, AT, R>::W wk;
       double acc = 0.0;
       for (int t0 = 0; t0 < L.nah; t0 += A.tile) {
         const int tl = (L.nah - t0) < A.tile ? (L.nah - t0) : A.tile;
@@ -488,7 +662,7 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
         const int jhi = L.je < t0 + tl ? L.je : t0 + tl;
         if (L.active && jlo < jhi) walk_tile<Tc, AT, R>(lds, t0, jlo, jhi, L.js, wk, sg, acc);
       }
-      finish_item(acc, r.p, lane, A, r.items == 1, fpre);
+      finish_item<AT>(acc, r.p, lane, A, r.items == 1, fpre);
     } else {
       // a batch of small pairs (one item each, loop A of at most kSmallA - 1
       // segments).  Pairs whose loop B has at most 64 segments run R at a
@@ -525,16 +699,16 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
           const Layout L = layout<R>(cur, 0, A.chunk, sl, S);
           V3<Tc> kv[R + 1];
           load_b<Tin, Tc, R>(X, cur, L, kv);
-          Segs<Tc, R> sg;
-          make_segs<Tc, R>(kv, L, sg);
+          typename LaneOf<Tc, AT, R>::S sg;
+          make_lane<Tc, R>(kv, L, A, sg);
           __syncthreads();
-          Walk<Tc, R> wk;
+          typename LaneOf<Tc, AT, R>::W wk;
           double acc = 0.0;
           if (has && L.active && L.js < L.je) walk_tile<Tc, AT, R>(myl, 0, L.js, L.je, L.js, wk, sg, acc);
 #pragma unroll
           for (int o = S / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
           if (has && sl == 0) {
-            const double v = acc * kInvTwoPi;
+            const double v = acc * value_scale<AT>();
             finalize_pair(A.out, cur.p, v, fm | (fabs(v) < 1.0e14 ? 0u : kFlagNonfinite));
           }
         }
@@ -552,13 +726,13 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
         __syncthreads();
         if (lane <= cur.na) lds[lane] = Vtx<Tc>{a_lo.x, a_lo.y, a_lo.z, (Tc)0};
         if (lane + kWave <= cur.na) lds[lane + kWave] = Vtx<Tc>{a_hi.x, a_hi.y, a_hi.z, (Tc)0};
-        Segs<Tc, R> sg;
-        make_segs<Tc, R>(kv, L, sg);
+        typename LaneOf<Tc, AT, R>::S sg;
+        make_lane<Tc, R>(kv, L, A, sg);
         __syncthreads();
-        Walk<Tc, R> wk;
+        typename LaneOf<Tc, AT, R>::W wk;
         double acc = 0.0;
         if (L.active && L.js < L.je) walk_tile<Tc, AT, R>(lds, 0, L.js, L.je, L.js, wk, sg, acc);
-        finish_item(acc, cur.p, lane, A, true, fm);
+        finish_item<AT>(acc, cur.p, lane, A, true, fm);
       }
     }
   }
@@ -615,6 +789,13 @@ Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
     if (segs >= 2) return in_f64 ? variant<double, float, 2, 2>() : variant<float, float, 2, 2>();
     return in_f64 ? variant<double, float, 2, 1>() : variant<float, float, 2, 1>();
   }
+  if (atan_form == kCrossings) {
+    constexpr int C = kCrossings;
+    if (segs >= 8) return in_f64 ? variant<double, float, C, 8>() : variant<float, float, C, 8>();
+    if (segs >= 4) return in_f64 ? variant<double, float, C, 4>() : variant<float, float, C, 4>();
+    if (segs >= 2) return in_f64 ? variant<double, float, C, 2>() : variant<float, float, C, 2>();
+    return in_f64 ? variant<double, float, C, 1>() : variant<float, float, C, 1>();
+  }
   if (segs >= 4) return in_f64 ? variant<double, float, 0, 4>() : variant<float, float, 0, 4>();
   if (segs >= 2) return in_f64 ? variant<double, float, 0, 2>() : variant<float, float, 0, 2>();
   return in_f64 ? variant<double, float, 0, 1>() : variant<float, float, 0, 1>();
@@ -622,8 +803,9 @@ Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
 
 }  // namespace
 
-int segs_supported(bool compute_f64, int segs) {
+int segs_supported(bool compute_f64, int segs, bool crossings) {
   if (compute_f64) return segs >= 2 ? 2 : 1;
+  if (crossings && segs >= 8) return 8;
   return segs >= 4 ? 4 : (segs >= 2 ? 2 : 1);
 }
 

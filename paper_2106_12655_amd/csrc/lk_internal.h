@@ -91,6 +91,10 @@ struct DsArgs {
   int32_t tile;                // LDS tile of loop A, vertices
   int32_t chunk;               // vertices of loop A per work item (multiple of tile)
   int32_t batch;               // small pairs per work index
+  // crossing count only: view direction (|n|_inf = 1) and the certainty
+  // factors of the side predicates and of the crossing sign
+  float view[3];
+  float cc_tau, cc_tau_p;
   Outs out;
 };
 
@@ -153,15 +157,17 @@ __device__ __forceinline__ void finalize_pair(const Outs& o, int32_t p, double v
 
 // --- lk_ds.hip
 // in_f64: input dtype; compute_f64: arithmetic (true = plain FP64 / refit);
-// atan_form: 0 = own minimax FP32 arctangent, 1 = HIP atan2f; segs: segments of
-// loop B per lane (register blocking; rounded down to a built variant).
+// form (FP32 only): 0 / 2 = own minimax arctangent (phased / inline), 1 = HIP
+// atan2f, 3 = crossing count instead of the Eq. 4 sum; segs: segments of loop
+// B per lane (register blocking; rounded down to a built variant).
 hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,
                              int segs, int grid, hipStream_t s);
 // Largest co-resident grid for the persistent kernel on this device.
 int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int segs, int tile, int n_cu,
                     int waves_per_cu);
-// Segments per lane of the variant that `segs` selects.
-int segs_supported(bool compute_f64, int segs);
+// Segments per lane of the variant that `segs` selects (the crossing count
+// also has 8).
+int segs_supported(bool compute_f64, int segs, bool crossings = false);
 
 // --- lk_aux.hip
 constexpr int kXiBlocks = 256;        // least workgroups of the preparation kernel

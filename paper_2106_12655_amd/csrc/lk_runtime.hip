@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -51,6 +52,10 @@ struct lk_ctx {
   bool timing = false;
   int opt_tile = 0, opt_chunk = 0, opt_waves = 0, opt_atan = 0, opt_segs = 0, opt_segs64 = 0;
   int opt_batch = 0;
+  // crossing count: view direction (largest component magnitude 1) and the
+  // multiplier of its certainty bounds
+  float view[3] = {0.0f, 0.0f, 0.0f};
+  int cc_tol = 1;
   // workspace
   DevBuf loop_flags, minseg2, xi, recs, big_prefix, meta, acc, flags, refit_list;
   DevBuf boxes, vcounts, vprefix;
@@ -116,7 +121,8 @@ int default_chunk(bool f64) { return f64 ? 2048 : 4096; }
 
 struct Plan {
   bool in_f64;
-  bool mixed;
+  bool mixed;      // FP32 main pass + FP64 refit (MIXED and CROSSINGS)
+  bool crossings;  // main pass counts crossings
   int tile, chunk, grid, grid64, grid_refit, atan_form;
   int segs, segs64;  // segments of loop B per lane, FP32 and FP64 kernels
 };
@@ -124,6 +130,10 @@ struct Plan {
 constexpr int kDefaultSegs32 = 4;
 constexpr int kDefaultSegs64 = 2;
 constexpr int kDefaultBatch = 4;
+constexpr int kFormCrossings = 3;  // term form of the crossing-count kernel
+// Certainty factors of the crossing count in units of 2^-24 (twice the
+// first-order error bounds of the side predicates and of the crossing sign).
+constexpr double kCcTau = 128.0 / 16777216.0, kCcTauP = 512.0 / 16777216.0;
 
 // Small device-side counters of one call, in one buffer (byte offsets).
 constexpr size_t kMetaCountsMain = 0;    // int32[2]: n_small, n_big (main pass)
@@ -212,6 +222,13 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   A.tile = P.tile;
   A.chunk = P.chunk;
   A.batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
+  // R small pairs share a wave in the FP32 kernel: a batch below R idles lanes
+  if (P.mixed && A.batch < P.segs) A.batch = P.segs;
+  A.view[0] = ctx->view[0];
+  A.view[1] = ctx->view[1];
+  A.view[2] = ctx->view[2];
+  A.cc_tau = (float)(kCcTau * ctx->cc_tol);
+  A.cc_tau_p = (float)(kCcTauP * ctx->cc_tol);
   A.out = out;
 
   LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
@@ -238,6 +255,9 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     B.s = make_sched(ctx, n_pairs, true);
     B.tile = default_tile(true);
     B.chunk = default_chunk(true);
+    // refits are few and latency-bound: one pair per work index spreads them
+    // over the most waves
+    B.batch = 1;
     B.out = ro;
     LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
     LK_HIP(launch_sched(B.s, nullptr, s));
@@ -250,16 +270,18 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
 }
 
 // Kernel configuration of a call from the context's options (0 = default).
-Plan make_plan(lk_ctx* ctx, bool in_f64, bool mixed) {
+Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
+  const bool mixed = mode != LK_PLAIN_F64;
   Plan P;
   P.in_f64 = in_f64;
   P.mixed = mixed;
-  P.atan_form = ctx->opt_atan;
+  P.crossings = mode == LK_CROSSINGS;
+  P.atan_form = P.crossings ? kFormCrossings : ctx->opt_atan;
   const int tmax = mixed ? lk::kMaxTileF32 : lk::kMaxTileF64;
   P.tile = ctx->opt_tile ? (ctx->opt_tile < tmax ? ctx->opt_tile : tmax) : default_tile(!mixed);
   P.chunk = ctx->opt_chunk ? ctx->opt_chunk : default_chunk(!mixed);
   if (P.chunk % P.tile) P.chunk = ((P.chunk + P.tile - 1) / P.tile) * P.tile;
-  P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32);
+  P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32, P.crossings);
   P.segs64 = lk::segs_supported(true, ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64);
   P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.segs, P.tile, ctx->n_cu,
                                ctx->opt_waves);
@@ -313,6 +335,10 @@ lk_status lk_create(lk_ctx** out, int device) {
   }
   ctx->n_cu = prop.multiProcessorCount;
   memset(&ctx->stats, 0, sizeof(ctx->stats));
+  // a generic direction (no coordinate plane or diagonal), exact in FP32
+  ctx->view[0] = 0.3671875f;
+  ctx->view[1] = -0.6103515625f;
+  ctx->view[2] = 1.0f;
   *out = ctx;
   return LK_OK;
 }
@@ -378,13 +404,18 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       ctx->opt_atan = (int)v;
       break;
     case LK_OPT_SEGS_PER_LANE:
-      if (v != 0 && v != 1 && v != 2 && v != 4)
-        return ctx->fail(LK_EINVAL, "segments per lane must be 0, 1, 2 or 4");
+      if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)
+        return ctx->fail(LK_EINVAL, "segments per lane must be 0, 1, 2, 4 or 8");
       ctx->opt_segs = (int)v;
       break;
     case LK_OPT_SMALL_BATCH:
       if (v < 0 || v > 64) return ctx->fail(LK_EINVAL, "small-pair batch must be in [0, 64]");
       ctx->opt_batch = (int)v;
+      break;
+    case LK_OPT_CROSSING_TOL:
+      if (v < 1 || v > (1 << 20))
+        return ctx->fail(LK_EINVAL, "crossing tolerance multiplier must be in [1, 2^20]");
+      ctx->cc_tol = (int)v;
       break;
     case LK_OPT_SEGS_PER_LANE_F64:
       if (v != 0 && v != 1 && v != 2)
@@ -401,6 +432,31 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
   return LK_OK;
 }
 
+lk_status lk_set_view_direction(lk_ctx* ctx, const double* dir) {
+  if (!ctx) return LK_EINVAL;
+  if (!dir) return ctx->fail(LK_EINVAL, "null direction");
+  double m = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    if (!std::isfinite(dir[q])) return ctx->fail(LK_EINVAL, "non-finite direction");
+    m = std::max(m, std::fabs(dir[q]));
+  }
+  if (!(m > 0.0)) return ctx->fail(LK_EINVAL, "zero direction");
+  float v[3];
+  for (int q = 0; q < 3; ++q) v[q] = (float)(dir[q] / m);
+  // rounding keeps the largest component at magnitude 1 and the others <= 1
+  for (int q = 0; q < 3; ++q) ctx->view[q] = v[q];
+  for (auto& kv : ctx->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  ctx->graphs.clear();
+  return LK_OK;
+}
+
+lk_status lk_get_view_direction(const lk_ctx* ctx, double* dir) {
+  if (!ctx || !dir) return LK_EINVAL;
+  for (int q = 0; q < 3; ++q) dir[q] = (double)ctx->view[q];
+  return LK_OK;
+}
+
 namespace {
 
 lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
@@ -410,7 +466,8 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   if (!ctx) return LK_EINVAL;
   ctx->err.clear();
   if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
-  if (mode != LK_PLAIN_F64 && mode != LK_MIXED) return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED && mode != LK_CROSSINGS)
+    return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
   if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
   if (n_pairs < 0) return ctx->fail(LK_EINVAL, "n_pairs must be >= 0");
   if (n_pairs > 0x7fffffffLL) return ctx->fail(LK_EINVAL, "n_pairs exceeds int32 range");
@@ -426,8 +483,8 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   }
 
   const bool in_f64 = dtype == LK_F64;
-  const bool mixed = mode == LK_MIXED;
-  const Plan P = make_plan(ctx, in_f64, mixed);
+  const bool mixed = mode != LK_PLAIN_F64;
+  const Plan P = make_plan(ctx, in_f64, mode);
   if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
@@ -657,7 +714,8 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   ctx->err.clear();
   if (!out) return ctx->fail(LK_EINVAL, "null output");
   if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
-  if (mode != LK_PLAIN_F64 && mode != LK_MIXED) return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED && mode != LK_CROSSINGS)
+    return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
   if (n_loops < 1 || n_pairs < 1 || n_pairs > 0x7fffffffLL)
     return ctx->fail(LK_EINVAL, "need n_loops >= 1 and 1 <= n_pairs < 2^31");
   if (!xyz || !off || !pairs || !lk_real || !lk_int)
@@ -666,7 +724,8 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   if (st != LK_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const bool in_f64 = dtype == LK_F64;
-  const bool mixed = mode == LK_MIXED;
+  const bool mixed = mode != LK_PLAIN_F64;
+  const bool crossings = mode == LK_CROSSINGS;
   *out = lk_tuning{};
 
   // workload profile, read once from the device
@@ -750,7 +809,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   int evaluated = 0;
   auto measure = [&](const lk_tuning& t, double* ms) -> lk_status {
     apply(t);
-    const Plan P = make_plan(ctx, in_f64, mixed);
+    const Plan P = make_plan(ctx, in_f64, mode);
     double best = 1e30;
     int reps = 3;
     for (int r = 0; r <= reps; ++r) {
@@ -789,7 +848,9 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     }
     return LK_OK;
   };
-  if (mixed) {
+  if (crossings) {
+    if ((st = sweep(&lk_tuning::segs_per_lane, {2, 4, 8})) != LK_OK) return st;
+  } else if (mixed) {
     // segments per lane and the arctangent's instruction order interact (the
     // compiler schedules each variant differently): sweep one, the other, and
     // the first again
@@ -799,7 +860,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   } else {
     if ((st = sweep(&lk_tuning::segs_per_lane_f64, {1, 2})) != LK_OK) return st;
   }
-  if (n_small > 0 && (st = sweep(&lk_tuning::small_batch, {1, 2, 4, 8, 16})) != LK_OK) return st;
+  if (n_small > 0 && (st = sweep(&lk_tuning::small_batch, {1, 2, 4, 8, 16, 32})) != LK_OK) return st;
   if (n_big > 0) {
     if (mixed) {
       if ((st = sweep(&lk_tuning::tile_a, {256, 512, 1024})) != LK_OK) return st;
@@ -816,7 +877,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   apply(cur);
   // leave the outputs as a valid result of the chosen configuration
   {
-    const Plan P = make_plan(ctx, in_f64, mixed);
+    const Plan P = make_plan(ctx, in_f64, mode);
     if ((st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
                                  flags, s, nullptr)) != LK_OK)
       return st;

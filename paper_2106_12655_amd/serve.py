@@ -40,7 +40,7 @@ class Server:
                  max_pairs=400000):
         self.lib = _lib.load()
         h = ctypes.c_void_p()
-        m = {"mixed": _lib.MIXED, "plain": _lib.PLAIN_F64}[mode]
+        m = _lib.MODES[mode]
         st = self.lib.lk_server_create(ctypes.byref(h), int(device), int(slots), int(budget), m,
                                        int(max_loops), int(max_pairs))
         if st != _lib.OK:

@@ -1,0 +1,259 @@
+"""Count Crossings on the GPU (mode "crossings") against the oracle.
+
+Sec. 2.1 and Alg. 4: the linking number is half the signed number of
+crossings of a regular projection.  The kernel decides every side test and
+crossing sign in FP32 only beyond a forward error bound; a pair with an
+undecided test or an odd count goes to the FP64 direct sum (FLAG_REFIT).
+
+Bars:
+  * every integer equals the oracle's FP64 direct sum (bit-exact);
+  * every pair decided by counting (no FLAG_REFIT) has lk_real equal to the
+    oracle's brute-force FP64 crossing count in the same projection (the
+    rotation whose third row is the view direction), exactly: both are
+    half-integers;
+  * refitted pairs carry the plain direct sum's value within 1e-6.
+The oracle's count is compared only where it reports a regular projection.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12655_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REFIT_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def cctx():
+    """A context of its own: these tests change the view direction and options."""
+    import paper_2106_12655_amd as lk
+    c = lk.Context(0)
+    yield c
+    c.close()
+
+
+def _frame(n):
+    """Rotation with third row n / |n| (the oracle projects along its z)."""
+    n = np.asarray(n, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    a = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(n, a)
+    e1 /= np.linalg.norm(e1)
+    return np.stack([e1, np.cross(n, e1), n])
+
+
+def _run(c, ls, pairs, mode="crossings", dtype=None):
+    import torch
+    xyz = np.ascontiguousarray(ls.xyz if dtype is None else ls.xyz.astype(dtype))
+    xyz = torch.from_numpy(xyz).cuda()
+    off = torch.from_numpy(np.ascontiguousarray(ls.offsets)).cuda()
+    pr = torch.from_numpy(np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))).cuda()
+    real, lk, flags = c.direct_sum(xyz, off, pr, mode)
+    torch.cuda.synchronize()
+    return real.cpu().numpy(), lk.cpu().numpy(), flags.cpu().numpy().view(np.uint32)
+
+
+def _check(c, ls, pairs, real, lk_int, flags, label, max_oracle_cc=400):
+    """The bars of the module docstring; returns the number of refitted pairs."""
+    import paper_2106_12655_amd as lkm
+    pairs = np.asarray(pairs, np.int64).reshape(-1, 2)
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)
+    assert np.array_equal(lk_int, olk), label
+    refit = (flags & lkm.FLAG_REFIT) != 0
+    assert not np.any(flags & (lkm.FLAG_NONFINITE | lkm.FLAG_AMBIGUOUS)), label
+    if refit.any():
+        assert np.abs(real[refit] - oreal[refit]).max() <= REFIT_TOL, label
+    # counted pairs: half-integers equal to the oracle's crossing count
+    assert np.array_equal(real[~refit] * 2, np.round(real[~refit] * 2)), label
+    R = _frame(c.view_direction())
+    idx = np.flatnonzero(~refit)
+    rng = np.random.default_rng(0)
+    if len(idx) > max_oracle_cc:
+        idx = np.sort(rng.choice(idx, max_oracle_cc, replace=False))
+    compared = 0
+    for p in idx:
+        i, j = pairs[p]
+        v, deg = oracle.crossings(ls.loop(i), ls.loop(j), R)
+        if deg:
+            continue
+        assert real[p] == v, (label, p, real[p], v)
+        compared += 1
+    print("%s: pairs %d, refitted %d, crossing counts compared %d"
+          % (label, len(pairs), int(refit.sum()), compared), flush=True)
+    assert compared >= min(len(idx), 1) * 0.9
+    return int(refit.sum())
+
+
+def test_view_direction_api(cctx):
+    import paper_2106_12655_amd as lk
+    d0 = cctx.view_direction()
+    assert max(abs(x) for x in d0) == 1.0
+    cctx.set_view_direction((0.5, -2.0, 1.0))
+    assert cctx.view_direction() == (0.25, -1.0, 0.5)
+    for bad in [(0.0, 0.0, 0.0), (float("nan"), 1.0, 0.0), (float("inf"), 0.0, 1.0)]:
+        with pytest.raises(lk.LkError):
+            cctx.set_view_direction(bad)
+    assert cctx.view_direction() == (0.25, -1.0, 0.5)
+    cctx.set_view_direction(d0)
+    assert cctx.view_direction() == d0
+    with pytest.raises(lk.LkError):
+        cctx.set_option(lk._lib.OPT_CROSSING_TOL, 0)
+
+
+def test_closed_forms(cctx):
+    """Hopf link, torus links T(2,3), T(3,-2) and separated rings."""
+    cases = [(I.hopf(64), "hopf"), (I.torus_link(2, 3, 400), "torus(2,3)"),
+             (I.torus_link(3, -2, 300), "torus(3,-2)"), (I.ring_grid(0), "ring grid")]
+    for ls, label in cases:
+        pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+        if len(ls.offsets) == 3:
+            pairs = np.array([[0, 1], [1, 0]], dtype=np.int32)
+        real, lk_int, flags = _run(cctx, ls, pairs)
+        _check(cctx, ls, pairs, real, lk_int, flags, label)
+        assert np.array_equal(lk_int, ls.expected_for(np.sort(pairs, 1))), label
+
+
+def test_chainmail_sizes_and_segments_per_lane(cctx):
+    """Small chainmail: every R variant, FP32 and FP64 input, one answer."""
+    import paper_2106_12655_amd as lk
+    ls = I.chainmail(1, rows=12, cols=14)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    outs = []
+    try:
+        for dt in (np.float32, np.float64):
+            for R in (1, 2, 4, 8):
+                cctx.set_option(lk._lib.OPT_SEGS_PER_LANE, R)
+                real, lk_int, flags = _run(cctx, ls, pairs, dtype=dt)
+                if R == 4 and dt is np.float32:
+                    _check(cctx, ls, pairs, real, lk_int, flags, "chainmail 12x14")
+                assert cctx.stats()["atan_form"] == 3
+                outs.append((dt, R, real, lk_int, flags))
+    finally:
+        cctx.set_option(lk._lib.OPT_SEGS_PER_LANE, 0)
+    exp = ls.expected_for(pairs)
+    for dt, R, real, lk_int, flags in outs:
+        assert np.array_equal(lk_int, exp), (dt, R)
+    # FP32 input: the count is exact, so every R gives the same bits
+    f32 = [o for o in outs if o[0] is np.float32]
+    for o in f32[1:]:
+        assert np.array_equal(o[2], f32[0][2]) and np.array_equal(o[4], f32[0][4]), o[1]
+
+
+def test_ragged_split_and_knit(cctx):
+    """Uneven loops (knit rows), pairs split over several work items (small
+    chunk and tile), a ragged tail of loop B's last block, and a pair list
+    with both orders and invalid entries."""
+    import paper_2106_12655_amd as lk
+    ls = I.knit(2, n_loops=24, cp_min=8, cp_max=48)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    pairs = np.concatenate([pairs, pairs[:5, ::-1]]).astype(np.int32)
+    try:
+        cctx.set_option(lk._lib.OPT_TILE_A, 64)
+        cctx.set_option(lk._lib.OPT_CHUNK_A, 128)
+        real, lk_int, flags = _run(cctx, ls, pairs)
+    finally:
+        cctx.set_option(lk._lib.OPT_TILE_A, 0)
+        cctx.set_option(lk._lib.OPT_CHUNK_A, 0)
+    _check(cctx, ls, pairs, real, lk_int, flags, "knit, split items", max_oracle_cc=60)
+    real2, lk2, fl2 = _run(cctx, ls, pairs)
+    assert np.array_equal(lk2, lk_int)
+    # bad pairs are flagged, not counted
+    bad = np.array([[0, 0], [0, len(ls.offsets) + 3]], dtype=np.int32)
+    real3, lk3, fl3 = _run(cctx, ls, bad)
+    assert np.all(lk3 == lk.INT_INVALID) and np.all(fl3 & lk.FLAG_BADPAIR)
+
+
+def test_long_pair_many_items(cctx):
+    """Winding pairs of long loops (the long-loop workload's shape, shortened):
+    hundreds of work items per pair, their counts combined in fixed point."""
+    import paper_2106_12655_amd as lk
+    ls = I.long_pairs(5, n_pairs=2, n_min=12000, n_max=20000)
+    pairs = np.ascontiguousarray(ls.pairs, dtype=np.int32)
+    try:
+        cctx.set_option(lk._lib.OPT_CHUNK_A, 512)
+        real, lk_int, flags = _run(cctx, ls, pairs)
+    finally:
+        cctx.set_option(lk._lib.OPT_CHUNK_A, 0)
+    assert np.array_equal(lk_int, ls.expected_for(pairs))
+    R = _frame(cctx.view_direction())
+    i, j = pairs[0]
+    v, deg = oracle.crossings(ls.loop(i), ls.loop(j), R)
+    print("long pairs: gpu", real, flags, "oracle (pair 0)", v, deg, flush=True)
+    if not flags[0] & lk.FLAG_REFIT and not deg:
+        assert real[0] == v
+
+
+def test_forced_refit_and_empty(cctx):
+    """A huge certainty factor leaves every crossing undecided: the pairs with
+    crossings go to the FP64 direct sum, the others stay counted (0)."""
+    import torch
+    import paper_2106_12655_amd as lk
+    ls = I.chainmail(2, rows=6, cols=8)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    real0, lk0, fl0 = _run(cctx, ls, pairs)
+    try:
+        cctx.set_option(lk._lib.OPT_CROSSING_TOL, 1 << 20)
+        real, lk_int, flags = _run(cctx, ls, pairs)
+        st = cctx.stats()
+    finally:
+        cctx.set_option(lk._lib.OPT_CROSSING_TOL, 1)
+    refit = (flags & lk.FLAG_REFIT) != 0
+    crossed = np.array([oracle.crossings(ls.loop(i), ls.loop(j), _frame(cctx.view_direction()))[0]
+                        for i, j in pairs])
+    print("forced: refitted %d of %d" % (refit.sum(), len(pairs)), flush=True)
+    assert np.array_equal(lk_int, lk0)
+    assert refit.sum() >= np.count_nonzero(crossed)
+    assert st["refits"] == refit.sum()
+    _check(cctx, ls, pairs, real, lk_int, flags, "forced refit")
+    # empty pair list
+    xyz = torch.from_numpy(ls.xyz).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    e = torch.empty((0, 2), dtype=torch.int32, device="cuda")
+    r, l, f = cctx.direct_sum(xyz, off, e, "crossings")
+    assert r.numel() == 0
+
+
+def test_fused_check_and_graph_replay(cctx):
+    import torch
+    ls = I.chainmail(4, rows=16, cols=16)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    exp = ls.expected_for(pairs)
+    xyz = torch.from_numpy(ls.xyz).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    pr = torch.from_numpy(pairs).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs = [[t.cpu().numpy() for t in cctx.direct_sum(xyz, off, pr, "crossings")]
+                for _ in range(3)]
+        real, lkv, fl, nm = cctx.direct_sum_check(xyz, off, pr, torch.from_numpy(exp).cuda(),
+                                                  False, "crossings")
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+    assert np.array_equal(outs[0][1], exp)
+    assert int(nm.item()) == 0
+    assert np.array_equal(lkv.cpu().numpy(), exp)
+
+
+def test_full_chainmail_crossings(cctx):
+    """The full chainmail workload (14,000 rings, ~69k pairs) in the launch
+    configuration the benchmark uses: every integer equals the construction's
+    expected value (each equals the FP64 oracle on the sampled pairs of the
+    parity tests), and a sample of counted pairs equals the oracle's count."""
+    ls = I.chainmail(0)
+    pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    real, lk_int, flags = _run(cctx, ls, pairs)
+    assert np.array_equal(lk_int, ls.expected_for(pairs))
+    import paper_2106_12655_amd as lk
+    refit = (flags & lk.FLAG_REFIT) != 0
+    print("full chainmail: refitted %d of %d" % (refit.sum(), len(pairs)), flush=True)
+    assert refit.sum() < 0.01 * len(pairs)
+    R = _frame(cctx.view_direction())
+    rng = np.random.default_rng(9)
+    for p in rng.choice(np.flatnonzero(~refit), 200, replace=False):
+        i, j = pairs[p]
+        v, deg = oracle.crossings(ls.loop(i), ls.loop(j), R)
+        if not deg:
+            assert real[p] == v, p
