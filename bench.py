@@ -178,6 +178,7 @@ def time_mode(ctx, xyz, off, pairs, mode, steps, warmup, lkmod):
         "kernel_ms": st["kernel_ms"],
         "refit_kernel_ms": st["refit_kernel_ms"],
         "refits": int(np.sum(flags.view(np.uint32) & 1)),
+        "refits_direct_sum": int(st.get("refits_direct_sum", 0)),
         "real": real,
         "lk": lk,
         "flags": flags.view(np.uint32),
@@ -240,6 +241,13 @@ def main():
         tuned_cc = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "crossings", lk,
                                                   args.tune_cache)
         cc = time_mode(ctx, xyz, off, pairs, "crossings", args.steps, args.warmup, lk)
+        if T <= 1e12:
+            # the same count with culling off: every segment pair is tested, so
+            # the kernel time prices the per-term work against the roofline
+            ctx.set_option(lk._lib.OPT_CROSSING_CULL, 0)
+            cc["exhaustive"] = time_mode(ctx, xyz, off, pairs, "crossings",
+                                         max(min(args.steps, 5), 1), min(args.warmup, 1), lk)
+            ctx.set_option(lk._lib.OPT_CROSSING_CULL, 1)
 
     value = T / (res["ms_per_step"] * 1e-3)
     fp64 = args.mode == "plain"
@@ -289,7 +297,8 @@ def main():
             "tuned": tuned_plain,
         }
     if cc is not None:
-        ach = FLOP_PER_TERM_CC * T / (cc["kernel_ms"] * 1e-3) / 1e12 if cc["kernel_ms"] > 0 else 0.0
+        # value: segment pairs covered per second (culling skips most of them);
+        # the roofline fraction comes from the exhaustive run, which tests all
         line["crossings"] = {
             "value": T / (cc["ms_per_step"] * 1e-3),
             "ms_per_step": cc["ms_per_step"],
@@ -297,12 +306,22 @@ def main():
             "kernel_ms": cc["kernel_ms"],
             "refit_kernel_ms": cc["refit_kernel_ms"],
             "refits": cc["refits"],
-            "roofline_frac_fp32": ach / PEAK_FP32_TFLOPS,
-            "flop_per_term": FLOP_PER_TERM_CC,
+            "refits_direct_sum": cc["refits_direct_sum"],
             "int_mismatch_vs_mixed": int(np.sum(cc["lk"] != res["lk"])),
             "int_mismatch_vs_construction": int(np.sum(cc["lk"] != exp)),
             "tuned": tuned_cc,
         }
+        ex = cc.get("exhaustive")
+        if ex is not None:
+            ach = FLOP_PER_TERM_CC * T / (ex["kernel_ms"] * 1e-3) / 1e12 if ex["kernel_ms"] > 0 else 0.0
+            line["crossings"]["exhaustive"] = {
+                "value": T / (ex["ms_per_step"] * 1e-3),
+                "ms_per_step": ex["ms_per_step"],
+                "kernel_ms": ex["kernel_ms"],
+                "roofline_frac_fp32": ach / PEAK_FP32_TFLOPS,
+                "flop_per_term": FLOP_PER_TERM_CC,
+                "int_mismatch_vs_culled": int(np.sum(ex["lk"] != cc["lk"])),
+            }
     if not args.no_cpu_baseline:
         line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)

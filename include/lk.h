@@ -67,9 +67,14 @@ typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
  * forward error bound, on the vertices as given (FP64 input is rounded to
  * FP32 for this pass), so for FP32 input a certified count is exact.  A pair
  * with an undecided test (a crossing at or near a vertex, near-parallel or
- * nearly touching segments) or an odd count is recomputed by the FP64 direct
- * sum exactly as MIXED refits (LK_FLAG_REFIT); lk_real of the other pairs is
- * the count / 2. */
+ * nearly touching segments) or an odd count is counted again in FP64 (the
+ * same predicates with bounds at the FP64 unit roundoff), and a pair still
+ * undecided there goes to the FP64 direct sum; both set LK_FLAG_REFIT.
+ * lk_real is the count / 2 for every counted pair.  As Alg. 4 bounds its search with a BVH, the count skips
+ * blocks of 64 consecutive vertices (and of 4096) whose projected boxes are
+ * disjoint from the other loop's block (LK_OPT_CROSSING_CULL).  To size those
+ * boxes the first CROSSINGS call with a given offsets array reads its
+ * vertex count from the device, which synchronises the stream once. */
 typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1, LK_CROSSINGS = 2 } lk_mode;
 
 /* Per-pair flags (bit set). */
@@ -180,9 +185,12 @@ enum {
   LK_OPT_SEGS_PER_LANE_F64 = 9,   /* FP64 kernel: segments of loop B per lane, 1/2 (0 = tuned) */
   LK_OPT_SMALL_BATCH = 10,        /* small pairs claimed per work-counter step, 1..64 (0 = tuned);
                                      the FP32 passes use at least the segments per lane */
-  LK_OPT_CROSSING_TOL = 11        /* CROSSINGS: multiplier of the certainty bounds, 1..2^20
+  LK_OPT_CROSSING_TOL = 11,       /* CROSSINGS: multiplier of the certainty bounds, 1..2^20
                                      (default 1); larger values send more pairs to the FP64
                                      direct sum, never fewer */
+  LK_OPT_CROSSING_CULL = 12       /* CROSSINGS: 1 = skip vertex blocks and pairs whose projected
+                                     boxes are disjoint (default), 0 = test every segment pair;
+                                     the results are the same */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */
@@ -198,13 +206,15 @@ lk_status lk_set_view_direction(lk_ctx* ctx, const double* dir);
 lk_status lk_get_view_direction(const lk_ctx* ctx, double* dir);
 
 typedef struct {
-  int64_t refits;         /* pairs recomputed in FP64 by the last MIXED call */
+  int64_t refits;         /* pairs recomputed in FP64 by the last MIXED or CROSSINGS call */
   double kernel_ms;       /* mean main-kernel time over the timed calls in the ring */
   double refit_kernel_ms; /* mean refit-kernel time over the same calls (MIXED) */
   int32_t timed_calls;    /* number of calls those means cover */
   int32_t graph_replayed; /* 1 if the last call replayed a captured graph */
   int32_t tile_a, chunk_a, waves_per_cu, atan_form, segs_per_lane; /* configuration used
                             (atan_form 3: the crossing count) */
+  int64_t refits_direct_sum; /* CROSSINGS: pairs the FP64 crossing count could not decide
+                                either, computed by the FP64 direct sum */
 } lk_stats;
 
 /* ------------------------------------------------------------ autotuner */

@@ -24,7 +24,7 @@ FLAG_SKIPPED = 32
 INT_INVALID = -(2 ** 31)
 OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 3, 4, 5
 OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
-OPT_SMALL_BATCH, OPT_CROSSING_TOL = 10, 11
+OPT_SMALL_BATCH, OPT_CROSSING_TOL, OPT_CROSSING_CULL = 10, 11, 12
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
            "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_set_view_direction",
@@ -40,7 +40,8 @@ class Stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("refit_kernel_ms", ctypes.c_double),
                 ("timed_calls", ctypes.c_int32), ("graph_replayed", ctypes.c_int32), ("tile_a", ctypes.c_int32),
                 ("chunk_a", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32)]
+                ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32),
+                ("refits_direct_sum", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):

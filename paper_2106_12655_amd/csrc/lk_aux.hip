@@ -81,6 +81,81 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
   }
 }
 
+// ------------------------------------------------- crossing-count boxes
+// One 256-thread workgroup per superblock slot: the loop that owns the slot
+// comes from a binary search over the slot bases, each wave boxes every
+// fourth block of the superblock, and the workgroup joins the block boxes
+// into the superblock box.  Coordinates are FP32 on the vertices as the
+// crossing kernel sees them (FP64 input rounded first).  Each box is widened
+// by 8 u (u = 2^-24) times the largest |x|_1 of its vertices, which covers the
+// rounding of the two projections and the FP32 directions' deviation from
+// exact orthogonality to the view direction.
+__device__ __forceinline__ float4 box_join(const float4& a, const float4& b) {
+  return float4{fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w)};
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* off, int32_t L,
+                                                  CcProj pr, float4* blk, int64_t n_blk,
+                                                  float4* sup, int64_t n_slots) {
+  __shared__ float4 part[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t o0 = off[0];
+  for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+    // largest loop i with (off[i] - off[0]) / kCcSuper + i <= slot
+    int32_t lo = 0, hi = L;
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if ((off[mid] - o0) / kCcSuper + mid <= slot)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int64_t oi = off[lo], n = off[lo + 1] - oi;
+    const int64_t s = slot - ((oi - o0) / kCcSuper + lo);
+    const int64_t nblk = (n + kCcBlock - 1) / kCcBlock;
+    const bool used = s * (kCcSuper / kCcBlock) < nblk;  // uniform over the workgroup
+    if (!used) continue;
+    const int64_t bbase = (oi - o0) / kCcBlock + lo;
+    float4 acc = float4{INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int64_t k = s * (kCcSuper / kCcBlock) + wave; k < nblk && k < (s + 1) * (kCcSuper / kCcBlock);
+         k += 4) {
+      const int64_t v0 = k * kCcBlock;
+      const int64_t m = (n - v0) < kCcBlock ? (n - v0) : kCcBlock;
+      float a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY, mag = 0.0f;
+      for (int t = lane; t <= m; t += 64) {  // m + 1 vertices: the last closes the block
+        int64_t v = v0 + t;
+        if (v >= n) v -= n;
+        const float x = (float)X[3 * (oi + v)], y = (float)X[3 * (oi + v) + 1],
+                    z = (float)X[3 * (oi + v) + 2];
+        const float a = fmaf(x, pr.e1[0], fmaf(y, pr.e1[1], z * pr.e1[2]));
+        const float b = fmaf(x, pr.e2[0], fmaf(y, pr.e2[1], z * pr.e2[2]));
+        a0 = fminf(a0, a);
+        a1 = fmaxf(a1, a);
+        b0 = fminf(b0, b);
+        b1 = fmaxf(b1, b);
+        mag = fmaxf(mag, fabsf(x) + fabsf(y) + fabsf(z));
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        a0 = fminf(a0, __shfl_xor(a0, o));
+        a1 = fmaxf(a1, __shfl_xor(a1, o));
+        b0 = fminf(b0, __shfl_xor(b0, o));
+        b1 = fmaxf(b1, __shfl_xor(b1, o));
+        mag = fmaxf(mag, __shfl_xor(mag, o));
+      }
+      const float pad = 4.76837158203125e-7f * mag;  // 8 * 2^-24
+      const float4 box = float4{a0 - pad, a1 + pad, b0 - pad, b1 + pad};
+      if (lane == 0 && bbase + k < n_blk) blk[bbase + k] = box;
+      acc = box_join(acc, box);
+    }
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      sup[slot] = box_join(box_join(part[0], part[1]), box_join(part[2], part[3]));
+    __syncthreads();
+  }
+}
+
 // --------------------------------------------------------------- planning
 // Append to a device list from a wavefront: one atomic per wave, then each
 // lane with `pred` gets base + (number of lower lanes with pred).  All active
@@ -241,6 +316,14 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
                                      A.off[j + 1] - A.off[j] > 0x7fffffffLL ||
                                      items > 0x7fffffffLL);
       if (too_big) items = 0;
+      // crossing count: two loops of one superblock each whose projected
+      // boxes are disjoint have no crossing, so the pair is 0 without work
+      if (A.cc_sup && valid && !too_big && items > 0 && r.na <= kCcSuper && r.nb <= kCcSuper) {
+        const int64_t o0 = A.off[0];
+        const int64_t si = (r.oa - o0) / kCcSuper + i, sj = (r.ob - o0) / kCcSuper + j;
+        if (si < A.cc_nsup && sj < A.cc_nsup && boxes_disjoint(A.cc_sup[si], A.cc_sup[sj]))
+          items = 0;
+      }
       uint32_t f;
       if (refit) {
         f = (A.out.flags[p] & ~kFlagNonfinite) | (too_big ? kFlagNonfinite : 0u);
@@ -493,6 +576,17 @@ hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t
   else
     prep_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials, lf, minseg2,
                                     zero_counts, zero_mismatch, zero_stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_cc_boxes(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
+                           const CcProj& pr, float4* blk, int64_t n_blk, float4* sup,
+                           int64_t n_sup, hipStream_t s) {
+  const int g = blocks_for(n_sup, 1, 65536);
+  if (in_f64)
+    cc_boxes_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, pr, blk, n_blk, sup, n_sup);
+  else
+    cc_boxes_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, pr, blk, n_blk, sup, n_sup);
   return hipGetLastError();
 }
 

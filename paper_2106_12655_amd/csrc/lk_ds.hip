@@ -423,10 +423,14 @@ __device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, i
 // tau |first|_inf |second|_inf (about 63 u for w and q, 216 u for p with the
 // unit roundoff u = 2^-24, from first-order error analysis of the differences,
 // the cross products and the dot products; tau defaults to twice that).  A
-// term that is neither certainly crossing nor certainly not crossing -- a
-// crossing at or near a vertex, near-parallel projected segments, segments
-// that nearly touch in space -- or an odd total makes the pair's value NaN or
-// a half-integer, which sends the pair to the FP64 direct sum.  Needs
+// term that is neither certainly crossing nor certainly not crossing, or an
+// odd total, makes the pair's value NaN or a half-integer, and the pair is
+// counted again by this kernel in FP64 (Tc = double, bounds at u = 2^-53):
+// the depth separation of two segments enters |v| but not the side values,
+// so at shallow crossings of curves far apart in depth the FP32 bound is
+// loose while FP64 decides.  Only a pair that FP64 cannot decide either -- a
+// crossing within about 1e-16 of a vertex, overlapping projected segments,
+// segments that touch in space -- goes to the FP64 direct sum.  Needs
 // |n|_inf <= 1 (the runtime scales n so).
 constexpr int kCrossings = 3;  // term form of the kernel's template: crossing count
 
@@ -451,19 +455,22 @@ struct CcWalk {
 
 template <typename T>
 __device__ __forceinline__ T inf_norm(const V3<T>& a) {
-  return fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fabsf(a.z));
+  return fmax(fmax(fabs(a.x), fabs(a.y)), fabs(a.z));
 }
 
 // x if |x| > tol, else 0 (the sign survives only when it is certain; NaN -> 0)
-__device__ __forceinline__ float certain(float x, float tol) { return fabsf(x) > tol ? x : 0.0f; }
+template <typename T>
+__device__ __forceinline__ T certain(T x, T tol) {
+  return fabs(x) > tol ? x : (T)0;
+}
 
 template <typename Tc, int R>
 __device__ __forceinline__ void make_lane(const V3<Tc>* k, const Layout& L, const DsArgs& A,
                                           CcSegs<Tc, R>& sg) {
   const int first = L.bi * R;
   sg.n = V3<Tc>{A.view[0], A.view[1], A.view[2]};
-  sg.tau = A.cc_tau;
-  sg.tau_p = A.cc_tau_p;
+  sg.tau = (Tc)A.cc_tau;
+  sg.tau_p = (Tc)A.cc_tau_p;
 #pragma unroll
   for (int r = 0; r <= R; ++r) sg.k[r] = k[r];
 #pragma unroll
@@ -513,7 +520,7 @@ __device__ __forceinline__ void cc_step(CcWalk<Tc, R>& w, const V3<Tc>& l1, cons
     Qp[r] = w.Q[r] * qc;        // < 0: l_j, l_{j+1} certainly on opposite sides
     w.Q[r] = qc;
     // either product certainly positive: certainly no crossing
-    cand[r] = g.valid[r] && !(fmaxf(Wp[r], Qp[r]) > (Tc)0);
+    cand[r] = g.valid[r] && !(fmax(Wp[r], Qp[r]) > (Tc)0);
     any = any || cand[r];
   }
   w.l = l1;
@@ -524,10 +531,11 @@ __device__ __forceinline__ void cc_step(CcWalk<Tc, R>& w, const V3<Tc>& l1, cons
       const V3<Tc> s = g.k[r + 1] - g.k[r];
       const Tc p = dot(v[r], cross(sj, s));
       const Tc tp = g.tau_p * g.sn[r] * sjn * nv[r];
-      if (Wp[r] < (Tc)0 && Qp[r] < (Tc)0 && fabsf(p) > tp)
+      if (Wp[r] < (Tc)0 && Qp[r] < (Tc)0 && fabs(p) > tp) {
         cnt += p > (Tc)0 ? 1 : -1;
-      else
+      } else {
         bad = true;
+      }
     }
   }
 }
@@ -548,6 +556,58 @@ __device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, i
     cc_step(wk, V3<Tc>{v1.x, v1.y, v1.z}, sg, cnt, bad);
   }
   acc += bad ? __builtin_nan("") : (double)cnt;
+}
+
+// One work item of the crossing count with culling: the item's B block (R
+// blocks of 64 segments) has a projected box; loop A's superblocks and then
+// blocks whose boxes are disjoint from it are skipped, and every other block
+// is staged (65 vertices) and walked from a fresh start.  The box tests are
+// uniform over the wave.
+template <typename Tin, typename Tc, int R>
+__device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X, Vtx<Tc>* lds,
+                                               const WorkRec& r, const Layout& L, int lane,
+                                               CcWalk<Tc, R>& wk, const CcSegs<Tc, R>& sg,
+                                               double& acc) {
+  const int32_t ia = A.pairs[2 * (int64_t)r.p], ib = A.pairs[2 * (int64_t)r.p + 1];
+  const int64_t o0 = A.off[0];
+  const int64_t bslot = (r.ob - o0) / kCcBlock + ib + L.b0 / kCcBlock;
+  float4 bb = float4{INFINITY, -INFINITY, INFINITY, -INFINITY};
+  bool bok = true;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    if (L.b0 + (int64_t)c * kCcBlock < r.nb) {
+      if (bslot + c < A.cc_nblk) {
+        const float4 q = A.cc_blk[bslot + c];
+        bb = float4{fminf(bb.x, q.x), fmaxf(bb.y, q.y), fminf(bb.z, q.z), fmaxf(bb.w, q.w)};
+      } else {
+        bok = false;
+      }
+    }
+  }
+  if (!bok) bb = float4{-INFINITY, INFINITY, -INFINITY, INFINITY};  // no box: cull nothing
+  const int64_t ablk = (r.oa - o0) / kCcBlock + ia;
+  const int64_t asup = (r.oa - o0) / kCcSuper + ia;
+  const int a0 = (int)L.a0, a_end = (int)L.a0 + L.nah;
+  const int lo_l = a0 + L.js, hi_l = a0 + L.je;  // this lane's segments of A
+  for (int sp = a0 / kCcSuper; sp * kCcSuper < a_end; ++sp) {
+    if (asup + sp < A.cc_nsup && boxes_disjoint(A.cc_sup[asup + sp], bb)) continue;
+    const int k0 = max(sp * (kCcSuper / kCcBlock), a0 / kCcBlock);
+    const int k1 = min((sp + 1) * (kCcSuper / kCcBlock), (a_end + kCcBlock - 1) / kCcBlock);
+    for (int k = k0; k < k1; ++k) {
+      if (ablk + k < A.cc_nblk && boxes_disjoint(A.cc_blk[ablk + k], bb)) continue;
+      const int v0 = k * kCcBlock;
+      __syncthreads();
+      for (int t = lane; t <= kCcBlock; t += kWave) {
+        const int idx = (v0 + t) % r.na;  // the block's vertices, cyclic
+        const V3<Tc> x = load_vertex<Tc>(X, r.oa + idx);
+        lds[t] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
+      }
+      __syncthreads();
+      const int jlo = max(v0, lo_l), jhi = min(v0 + kCcBlock, hi_l);
+      if (L.active && jlo < jhi)
+        walk_tile<Tc, kCrossings, R>(lds, v0, jlo, jhi, jlo, wk, sg, acc);
+    }
+  }
 }
 
 // Per-lane state of the term form AT (the direct sum's, or the crossing count's).
@@ -648,6 +708,14 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
       make_lane<Tc, R>(kv, L, A, sg);
       typename LaneOf<Tc, AT, R>::W wk;
       double acc = 0.0;
+      bool culled = false;
+      if constexpr (AT == kCrossings) {
+        if (A.cc_blk) {
+          cc_item_culled<Tin, Tc, R>(A, X, lds, r, L, lane, wk, sg, acc);
+          culled = true;
+        }
+      }
+      if (!culled)
       for (int t0 = 0; t0 < L.nah; t0 += A.tile) {
         const int tl = (L.nah - t0) < A.tile ? (L.nah - t0) : A.tile;
         __syncthreads();
@@ -775,6 +843,11 @@ constexpr Variant variant() {
 }
 
 Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
+  if (compute_f64 && atan_form == kCrossings) {
+    constexpr int C = kCrossings;
+    if (segs >= 2) return in_f64 ? variant<double, double, C, 2>() : variant<float, double, C, 2>();
+    return in_f64 ? variant<double, double, C, 1>() : variant<float, double, C, 1>();
+  }
   if (compute_f64) {
     if (segs >= 2) return in_f64 ? variant<double, double, 0, 2>() : variant<float, double, 0, 2>();
     return in_f64 ? variant<double, double, 0, 1>() : variant<float, double, 0, 1>();

@@ -61,6 +61,24 @@ struct Outs {
   int32_t early_exit;
 };
 
+// Culling of the crossing count (Alg. 4 bounds its search with a BVH over
+// projected segments; here the hierarchy is implicit in the vertex order).
+// Loop i's vertex block k holds vertices kCcBlock k .. kCcBlock k + m
+// (m = min(kCcBlock, n - kCcBlock k), cyclic: the last vertex closes the
+// block's last segment); its projected box sits at slot
+// (off[i] - off[0]) / kCcBlock + i + k.  Superblock s covers blocks
+// kCcSuper / kCcBlock s .. + (kCcSuper / kCcBlock - 1) at slot
+// (off[i] - off[0]) / kCcSuper + i + s.  A box is {min, max} of x . e1 then
+// {min, max} of x . e2, e1 and e2 spanning the plane orthogonal to the view
+// direction; two disjoint boxes hold no crossing.
+constexpr int kCcBlock = 64;
+constexpr int kCcSuper = 64 * 64;
+
+__device__ __forceinline__ bool boxes_disjoint(const float4& a, const float4& b) {
+  // NaN compares false: such boxes never cull
+  return a.y < b.x || b.y < a.x || a.w < b.z || b.w < a.z;
+}
+
 // Per-loop validation results of the preparation kernel.
 struct LoopInfo {
   const uint32_t* lf;          // NONFINITE / BADLOOP bits known without xi [n_loops]
@@ -80,6 +98,8 @@ struct PlanArgs {
   unsigned long long* acc;     // per-pair 128-bit fixed-point sums [n_pairs][2]
   int32_t chunk;               // vertices of loop A per work item
   int32_t bblock;              // segments of loop B per work item (64 x segments per lane)
+  const float4* cc_sup;        // crossing count: superblock boxes (NULL: no pair culling)
+  int64_t cc_nsup;             // their slots (a slot beyond never culls)
   Outs out;
 };
 
@@ -95,6 +115,11 @@ struct DsArgs {
   // factors of the side predicates and of the crossing sign
   float view[3];
   float cc_tau, cc_tau_p;
+  const float4* cc_blk;        // block and superblock boxes (NULL: no culling)
+  const float4* cc_sup;
+  int64_t cc_nblk, cc_nsup;    // their slots (a slot beyond never culls)
+  const int32_t* pairs;        // the call's pair list (loop indices for the box slots)
+  const int64_t* off;          // loop offsets (off[0] anchors the box slots)
   Outs out;
 };
 
@@ -178,6 +203,14 @@ int prep_blocks(int32_t n_loops);
 // NONFINITE / <3-vertex bits and shortest squared segment; zeroes the main
 // pass's two schedule counts and (when given) the fused check's mismatch
 // count and stop flag.
+// Crossing count: block and superblock boxes of every loop (see kCcBlock)
+// for the slots below n_blk / n_sup (the rest are not written).
+struct CcProj {
+  float e1[3], e2[3];  // directions spanning the plane orthogonal to the view
+};
+hipError_t launch_cc_boxes(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
+                           const CcProj& pr, float4* blk, int64_t n_blk, float4* sup,
+                           int64_t n_sup, hipStream_t s);
 hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                        double* xi_partials /*[prep_blocks]*/, uint32_t* lf, double* minseg2,
                        int32_t* zero_counts, unsigned long long* zero_mismatch,

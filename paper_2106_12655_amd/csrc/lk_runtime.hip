@@ -56,9 +56,16 @@ struct lk_ctx {
   // multiplier of its certainty bounds
   float view[3] = {0.0f, 0.0f, 0.0f};
   int cc_tol = 1;
+  bool cc_cull = true;
+  // vertex count of the last offsets array seen in CROSSINGS mode (sizes the
+  // culling boxes; read from the device once per offsets pointer and length)
+  const void* cc_off_key = nullptr;
+  int32_t cc_loops_key = -1;
+  int64_t cc_vertices = 0;
   // workspace
   DevBuf loop_flags, minseg2, xi, recs, big_prefix, meta, acc, flags, refit_list;
   DevBuf boxes, vcounts, vprefix;
+  DevBuf cc_blk, cc_sup;  // crossing count: projected block and superblock boxes
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
   // graphs
   struct Cached {
@@ -73,6 +80,7 @@ struct lk_ctx {
   lk_stats stats;
   hipStream_t last_stream = nullptr;
   bool last_mixed = false;
+  bool last_crossings = false;
   bool last_timed = false;
 
   lk_status fail(lk_status st, const char* fmt, ...) {
@@ -125,6 +133,7 @@ struct Plan {
   bool crossings;  // main pass counts crossings
   int tile, chunk, grid, grid64, grid_refit, atan_form;
   int segs, segs64;  // segments of loop B per lane, FP32 and FP64 kernels
+  int grid_cc64;     // CROSSINGS: grid of the FP64 crossing count
 };
 
 constexpr int kDefaultSegs32 = 4;
@@ -134,6 +143,7 @@ constexpr int kFormCrossings = 3;  // term form of the crossing-count kernel
 // Certainty factors of the crossing count in units of 2^-24 (twice the
 // first-order error bounds of the side predicates and of the crossing sign).
 constexpr double kCcTau = 128.0 / 16777216.0, kCcTauP = 512.0 / 16777216.0;
+constexpr double kCcTau64 = kCcTau / 536870912.0, kCcTauP64 = kCcTauP / 536870912.0;  // 2^-29
 
 // Small device-side counters of one call, in one buffer (byte offsets).
 constexpr size_t kMetaCountsMain = 0;    // int32[2]: n_small, n_big (main pass)
@@ -144,7 +154,13 @@ constexpr size_t kMetaBigTotalRefit = 32;
 constexpr size_t kMetaCounterMain = 40;  // uint64 work counters
 constexpr size_t kMetaCounterRefit = 48;
 constexpr size_t kMetaStop = 56;         // int32: fused check's stop flag
-constexpr size_t kMetaBytes = 64;
+// CROSSINGS: the FP64 crossing count refits first and queues what it cannot
+// decide for the FP64 direct sum (a second refit pass)
+constexpr size_t kMetaCountsRefit2 = 64; // int32[2]
+constexpr size_t kMetaRefitN2 = 72;      // int32 (follows the above)
+constexpr size_t kMetaBigTotalRefit2 = 80;
+constexpr size_t kMetaCounterRefit2 = 88;
+constexpr size_t kMetaBytes = 96;
 
 // Fused certificate check of a call (lk_direct_sum_check); empty for
 // lk_direct_sum.
@@ -159,17 +175,45 @@ T* meta_at(lk_ctx* ctx, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ctx->meta.p) + off);
 }
 
-lk::Sched make_sched(lk_ctx* ctx, int64_t n_pairs, bool refit) {
+// pass: 0 main, 1 refit, 2 second refit (CROSSINGS)
+lk::Sched make_sched(lk_ctx* ctx, int64_t n_pairs, int pass) {
   lk::Sched S;
   lk::WorkRec* recs = (lk::WorkRec*)ctx->recs.p;
   S.small = recs;
   S.big_in = recs + n_pairs;
   S.big = recs + 2 * n_pairs;
   S.big_prefix = (int64_t*)ctx->big_prefix.p;
-  S.counts = meta_at<int32_t>(ctx, refit ? kMetaCountsRefit : kMetaCountsMain);
-  S.big_total = meta_at<int64_t>(ctx, refit ? kMetaBigTotalRefit : kMetaBigTotalMain);
-  S.counter = meta_at<unsigned long long>(ctx, refit ? kMetaCounterRefit : kMetaCounterMain);
+  const size_t counts[3] = {kMetaCountsMain, kMetaCountsRefit, kMetaCountsRefit2};
+  const size_t totals[3] = {kMetaBigTotalMain, kMetaBigTotalRefit, kMetaBigTotalRefit2};
+  const size_t counters[3] = {kMetaCounterMain, kMetaCounterRefit, kMetaCounterRefit2};
+  S.counts = meta_at<int32_t>(ctx, counts[pass]);
+  S.big_total = meta_at<int64_t>(ctx, totals[pass]);
+  S.counter = meta_at<unsigned long long>(ctx, counters[pass]);
   return S;
+}
+
+// Two directions spanning the plane orthogonal to the view direction.
+lk::CcProj cc_projection(const float* view) {
+  double n[3] = {view[0], view[1], view[2]};
+  const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (double& c : n) c /= nn;
+  // the coordinate axis least aligned with n
+  int ax = 0;
+  for (int q = 1; q < 3; ++q)
+    if (std::fabs(n[q]) < std::fabs(n[ax])) ax = q;
+  double a[3] = {0.0, 0.0, 0.0};
+  a[ax] = 1.0;
+  double e1[3] = {n[1] * a[2] - n[2] * a[1], n[2] * a[0] - n[0] * a[2], n[0] * a[1] - n[1] * a[0]};
+  const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (double& c : e1) c /= l1;
+  const double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2],
+                        n[0] * e1[1] - n[1] * e1[0]};
+  lk::CcProj P;
+  for (int q = 0; q < 3; ++q) {
+    P.e1[q] = (float)e1[q];
+    P.e2[q] = (float)e2[q];
+  }
+  return P;
 }
 
 // Enqueue the whole direct-sum sequence (no graph logic here).
@@ -214,10 +258,13 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   M.acc = acc;
   M.chunk = P.chunk;
   M.bblock = lk::kWave * (P.mixed ? P.segs : P.segs64);
+  const bool cull = P.crossings && ctx->cc_cull;
+  M.cc_sup = cull ? (const float4*)ctx->cc_sup.p : nullptr;
+  M.cc_nsup = cull ? (int64_t)(ctx->cc_sup.bytes / 16) : 0;
   M.out = out;
   DsArgs A{};
   A.xyz = xyz;
-  A.s = make_sched(ctx, n_pairs, false);
+  A.s = make_sched(ctx, n_pairs, 0);
   A.acc = acc;
   A.tile = P.tile;
   A.chunk = P.chunk;
@@ -229,10 +276,20 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   A.view[2] = ctx->view[2];
   A.cc_tau = (float)(kCcTau * ctx->cc_tol);
   A.cc_tau_p = (float)(kCcTauP * ctx->cc_tol);
+  A.cc_blk = cull ? (const float4*)ctx->cc_blk.p : nullptr;
+  A.cc_sup = cull ? (const float4*)ctx->cc_sup.p : nullptr;
+  A.cc_nblk = cull ? (int64_t)(ctx->cc_blk.bytes / 16) : 0;
+  A.cc_nsup = cull ? (int64_t)(ctx->cc_sup.bytes / 16) : 0;
+  A.pairs = pairs;
+  A.off = off;
   A.out = out;
 
   LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
                      out.n_mismatch, out.stop, s));
+  if (cull)
+    LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
+                           (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
+                           s));
   LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
   LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
   if (timed) LK_HIP(hipEventRecord(ev[0], s));
@@ -241,30 +298,61 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   if (timed) LK_HIP(hipEventRecord(ev[1], s));
   LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
   if (P.mixed) {
+    // refit: the FP64 direct sum (MIXED), or the FP64 crossing count
+    // (CROSSINGS), which queues what it cannot decide for the FP64 direct sum
+    int32_t* rlist2 = rlist + n_pairs;
+    int32_t* rn2 = meta_at<int32_t>(ctx, kMetaRefitN2);
     Outs ro = out;
-    ro.refit_list = nullptr;
-    ro.refit_n = nullptr;
+    ro.refit_list = P.crossings ? rlist2 : nullptr;
+    ro.refit_n = P.crossings ? rn2 : nullptr;
     ro.refit_pass = 1;
     PlanArgs R = M;
     R.list = rlist;
     R.n_list_dev = rn;
-    R.chunk = default_chunk(true);
+    R.chunk = P.crossings ? P.chunk : default_chunk(true);
     R.bblock = lk::kWave * P.segs64;
+    R.cc_sup = nullptr;
     R.out = ro;
     DsArgs B = A;
-    B.s = make_sched(ctx, n_pairs, true);
+    if (!P.crossings) B.cc_blk = B.cc_sup = nullptr;
+    B.cc_tau = (float)(kCcTau64 * ctx->cc_tol);
+    B.cc_tau_p = (float)(kCcTauP64 * ctx->cc_tol);
+    B.s = make_sched(ctx, n_pairs, 1);
     B.tile = default_tile(true);
-    B.chunk = default_chunk(true);
+    B.chunk = R.chunk;
     // refits are few and latency-bound: one pair per work index spreads them
     // over the most waves
     B.batch = 1;
     B.out = ro;
     LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
-    LK_HIP(launch_sched(B.s, nullptr, s));
+    LK_HIP(launch_sched(B.s, P.crossings ? meta_at<int32_t>(ctx, kMetaCountsRefit2) : nullptr, s));
     if (timed) LK_HIP(hipEventRecord(ev[2], s));
-    LK_HIP(launch_direct_sum(B, P.in_f64, true, 0, P.segs64, P.grid_refit, s));
+    // the FP64 crossing count gets the whole grid: its pairs are the ones
+    // with shallow crossings, often the largest
+    LK_HIP(launch_direct_sum(B, P.in_f64, true, P.crossings ? kFormCrossings : 0, P.segs64,
+                             P.crossings ? P.grid_cc64 : P.grid_refit, s));
     if (timed) LK_HIP(hipEventRecord(ev[3], s));
     LK_HIP(launch_finalize_split(B.s, acc, ro, n_pairs, s));
+    if (P.crossings) {
+      Outs r2 = out;
+      r2.refit_list = nullptr;
+      r2.refit_n = nullptr;
+      r2.refit_pass = 1;
+      PlanArgs R2 = R;
+      R2.list = rlist2;
+      R2.n_list_dev = rn2;
+      R2.chunk = default_chunk(true);
+      R2.out = r2;
+      DsArgs B2 = B;
+      B2.cc_blk = B2.cc_sup = nullptr;
+      B2.s = make_sched(ctx, n_pairs, 2);
+      B2.chunk = R2.chunk;
+      B2.out = r2;
+      LK_HIP(launch_plan(R2, n_loops, li, B2.s, true, s));
+      LK_HIP(launch_sched(B2.s, nullptr, s));
+      LK_HIP(launch_direct_sum(B2, P.in_f64, true, 0, P.segs64, P.grid_refit, s));
+      LK_HIP(launch_finalize_split(B2.s, acc, r2, n_pairs, s));
+    }
   }
   return LK_OK;
 }
@@ -289,6 +377,9 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
                                  ctx->n_cu, ctx->opt_waves);
   // refits are rare: a small persistent grid keeps the empty refit pass cheap
   P.grid_refit = 2 * ctx->n_cu < P.grid64 ? 2 * ctx->n_cu : P.grid64;
+  P.grid_cc64 = P.crossings ? lk::direct_sum_grid(in_f64, true, kFormCrossings, P.segs64,
+                                                  default_tile(true), ctx->n_cu, 0)
+                            : 0;
   return P;
 }
 
@@ -301,8 +392,31 @@ lk_status ensure_workspace(lk_ctx* ctx, int32_t n_loops, int64_t n_pairs) {
   if ((st = ensure(ctx, ctx->big_prefix, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->meta, kMetaBytes)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->acc, 16 * (size_t)n_pairs)) != LK_OK) return st;
-  if ((st = ensure(ctx, ctx->refit_list, 4 * (size_t)n_pairs)) != LK_OK) return st;
+  // two refit lists: the second is the CROSSINGS mode's FP64 direct-sum pass
+  if ((st = ensure(ctx, ctx->refit_list, 8 * (size_t)n_pairs)) != LK_OK) return st;
   return LK_OK;
+}
+
+// Crossing count: size the culling boxes for the call's vertex count, which
+// is read from the device (one synchronisation) the first time an offsets
+// array is seen.  Inside a stream capture nothing is read and the boxes keep
+// their size; the kernels never cull through a slot beyond it.
+lk_status cc_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream_t s,
+                     bool can_sync) {
+  if (can_sync && (ctx->cc_off_key != off || ctx->cc_loops_key != n_loops)) {
+    int64_t ends[2] = {0, 0};
+    LK_HIP(hipMemcpyAsync(&ends[0], off, 8, hipMemcpyDeviceToHost, s));
+    LK_HIP(hipMemcpyAsync(&ends[1], off + n_loops, 8, hipMemcpyDeviceToHost, s));
+    LK_HIP(hipStreamSynchronize(s));
+    ctx->cc_off_key = off;
+    ctx->cc_loops_key = n_loops;
+    ctx->cc_vertices = ends[1] - ends[0] > 0 ? ends[1] - ends[0] : 0;
+  }
+  const int64_t v = ctx->cc_off_key == off && ctx->cc_loops_key == n_loops ? ctx->cc_vertices : 0;
+  lk_status st;
+  if ((st = ensure(ctx, ctx->cc_blk, 16 * (size_t)(v / lk::kCcBlock + n_loops + 1))) != LK_OK)
+    return st;
+  return ensure(ctx, ctx->cc_sup, 16 * (size_t)(v / lk::kCcSuper + n_loops + 1));
 }
 
 bool check_dtype(int d) { return d == LK_F32 || d == LK_F64; }
@@ -351,7 +465,8 @@ void lk_destroy(lk_ctx* ctx) {
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   DevBuf* bufs[] = {&ctx->loop_flags, &ctx->minseg2, &ctx->xi,      &ctx->recs,
                     &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
-                    &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix};
+                    &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix,
+                    &ctx->cc_blk,     &ctx->cc_sup};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -416,6 +531,10 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       if (v < 1 || v > (1 << 20))
         return ctx->fail(LK_EINVAL, "crossing tolerance multiplier must be in [1, 2^20]");
       ctx->cc_tol = (int)v;
+      break;
+    case LK_OPT_CROSSING_CULL:
+      if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "crossing culling must be 0 or 1");
+      ctx->cc_cull = v != 0;
       break;
     case LK_OPT_SEGS_PER_LANE_F64:
       if (v != 0 && v != 1 && v != 2)
@@ -486,6 +605,12 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   const bool mixed = mode != LK_PLAIN_F64;
   const Plan P = make_plan(ctx, in_f64, mode);
   if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
+  if (P.crossings) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    if ((st = cc_prepare(ctx, off, n_loops, s, cs == hipStreamCaptureStatusNone)) != LK_OK)
+      return st;
+  }
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
     flags = (uint32_t*)ctx->flags.p;
@@ -498,6 +623,7 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   ctx->stats.segs_per_lane = mixed ? P.segs : P.segs64;
   ctx->last_stream = s;
   ctx->last_mixed = mixed;
+  ctx->last_crossings = P.crossings;
   ctx->last_timed = false;
 
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -594,9 +720,12 @@ lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
   if (st != LK_OK) return st;
   if (ctx->last_mixed && ctx->meta.p) {
     LK_HIP(hipStreamSynchronize(ctx->last_stream));
-    int32_t rn = 0;
+    int32_t rn = 0, rn2 = 0;
     LK_HIP(hipMemcpy(&rn, meta_at<int32_t>(ctx, kMetaRefitN), 4, hipMemcpyDeviceToHost));
+    if (ctx->last_crossings)
+      LK_HIP(hipMemcpy(&rn2, meta_at<int32_t>(ctx, kMetaRefitN2), 4, hipMemcpyDeviceToHost));
     ctx->stats.refits = rn;
+    ctx->stats.refits_direct_sum = rn2;
   }
   if (ctx->timing && ctx->ring_count > 0) {
     LK_HIP(hipStreamSynchronize(ctx->last_stream));
@@ -784,6 +913,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   }
 
   if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
+  if (crossings && (st = cc_prepare(ctx, off, n_loops, s, true)) != LK_OK) return st;
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;
     flags = (uint32_t*)ctx->flags.p;
@@ -867,7 +997,13 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     } else {
       if ((st = sweep(&lk_tuning::tile_a, {128, 256, 512})) != LK_OK) return st;
     }
-    if ((st = sweep(&lk_tuning::chunk_a, {1024, 2048, 4096, 8192, 16384})) != LK_OK) return st;
+    if (crossings) {
+      // culling makes an item's cost its overlapping blocks, not its size
+      if ((st = sweep(&lk_tuning::chunk_a, {4096, 16384, 65536, 262144, 1048576})) != LK_OK)
+        return st;
+    } else if ((st = sweep(&lk_tuning::chunk_a, {1024, 2048, 4096, 8192, 16384})) != LK_OK) {
+      return st;
+    }
   }
   if ((st = sweep(&lk_tuning::waves_per_cu, {0, 8, 12})) != LK_OK) return st;
 

@@ -257,3 +257,49 @@ def test_full_chainmail_crossings(cctx):
         v, deg = oracle.crossings(ls.loop(i), ls.loop(j), R)
         if not deg:
             assert real[p] == v, p
+
+
+def _threaded_triangle(n_ring: int):
+    """A ring of n_ring segments and a 3-vertex loop linked through it, plus a
+    second long ring far away in projection (culled everywhere)."""
+    from paper_2106_12655_amd.inputs import _pack
+    t = 2 * np.pi * np.arange(n_ring) / n_ring
+    ring = np.stack([np.cos(t), np.sin(t), 0.01 * np.sin(7 * t)], 1)
+    tri = np.array([[0.6, 0.01, -0.5], [1.4, -0.02, -0.45], [1.05, 0.0, 0.7]])
+    far = ring + np.array([40.0, -35.0, 3.0])
+    return _pack([ring, tri, far], np.float32, {}, "threaded", 0)
+
+
+def test_culling_matches_brute_force(cctx):
+    """Block culling on and off give the same bits: uneven knit rows with
+    small tiles and chunks that do not align with the 64- and 4096-vertex
+    blocks, long winding pairs (several superblocks per loop), a 3-vertex
+    loop threaded through a 20,000-segment ring, and far-apart pairs."""
+    import paper_2106_12655_amd as lk
+    cases = []
+    ls = I.knit(3, n_loops=20, cp_min=8, cp_max=64)
+    cases.append((ls, oracle.aabb_pairs(ls.xyz, ls.offsets), {"OPT_TILE_A": 48, "OPT_CHUNK_A": 1000}))
+    ls = I.long_pairs(6, n_pairs=2, n_min=9000, n_max=14000)
+    cases.append((ls, np.ascontiguousarray(ls.pairs, np.int32), {"OPT_CHUNK_A": 5000}))
+    ls = _threaded_triangle(20000)
+    cases.append((ls, np.array([[0, 1], [1, 0], [0, 2], [2, 1], [1, 2]], np.int32), {}))
+    for ls, pairs, opts in cases:
+        res = []
+        try:
+            for k, v in opts.items():
+                cctx.set_option(getattr(lk._lib, k), v)
+            for cull in (1, 0):
+                cctx.set_option(lk._lib.OPT_CROSSING_CULL, cull)
+                res.append(_run(cctx, ls, pairs))
+        finally:
+            cctx.set_option(lk._lib.OPT_CROSSING_CULL, 1)
+            for k in opts:
+                cctx.set_option(getattr(lk._lib, k), 0)
+        (r1, l1, f1), (r0, l0, f0) = res
+        olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)[1]
+        print("%s: pairs %d, lk %s, refits %d" % (ls.name, len(pairs), l1[:8], int((f1 & 1).sum())),
+              flush=True)
+        assert np.array_equal(l1, olk), ls.name
+        assert np.array_equal(r1, r0) and np.array_equal(l1, l0) and np.array_equal(f1, f0), ls.name
+    # the threaded triangle links its ring once and nothing else
+    assert abs(int(l1[0])) == 1 and l1[0] == l1[1] and l1[2] == 0 and l1[3] == 0
