@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
                                               double* part, uint32_t* lf, double* minseg2,
                                               int32_t* zero_counts,
                                               unsigned long long* zero_mismatch,
-                                              int32_t* zero_stop) {
+                                              int32_t* zero_stop, int scan_loops) {
   __shared__ double red[256];
   if (blockIdx.x == 0 && threadIdx.x < 2) zero_counts[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && zero_mismatch) {
@@ -53,6 +53,15 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 
+  if (!scan_loops) {
+    // the crossing count's box kernel scans the vertices (in parallel over
+    // blocks of long loops) and folds its results into these with atomics
+    for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+      lf[l] = off[l + 1] - off[l] < 3 ? kFlagBadloop : 0u;
+      minseg2[l] = INFINITY;
+    }
+    return;
+  }
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
@@ -82,14 +91,21 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
 }
 
 // ------------------------------------------------- crossing-count boxes
-// One 256-thread workgroup per superblock slot: the loop that owns the slot
-// comes from a binary search over the slot bases, each wave boxes every
-// fourth block of the superblock, and the workgroup joins the block boxes
-// into the superblock box.  Coordinates are FP32 on the vertices as the
+// One wavefront per superblock slot: the loop that owns the slot comes from a
+// binary search over the slot bases, and the wave boxes the superblock's
+// blocks one after another (lane t holds vertex 64k + t; lane 0 also the
+// vertex that closes the block).  Coordinates are FP32 on the vertices as the
 // crossing kernel sees them (FP64 input rounded first).  Each box is widened
 // by 8 u (u = 2^-24) times the largest |x|_1 of its vertices, which covers the
 // rounding of the two projections and the FP32 directions' deviation from
-// exact orthogonality to the view direction.
+// exact orthogonality to the view direction.  The slot count comes from the
+// device offsets, so every vertex is scanned whatever the buffers hold; boxes
+// beyond the buffers are not written.
+//
+// The same scan does the per-loop validation of the preparation kernel (which
+// then only initialises it): non-finite coordinates and the shortest squared
+// segment, folded into the loop's entries with atomics (a minimum of
+// non-negative doubles is a minimum of their bit patterns).
 __device__ __forceinline__ float4 box_join(const float4& a, const float4& b) {
   return float4{fminf(a.x, b.x), fmaxf(a.y, b.y), fminf(a.z, b.z), fmaxf(a.w, b.w)};
 }
@@ -97,11 +113,14 @@ __device__ __forceinline__ float4 box_join(const float4& a, const float4& b) {
 template <typename Tin>
 __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* off, int32_t L,
                                                   CcProj pr, float4* blk, int64_t n_blk,
-                                                  float4* sup, int64_t n_slots) {
-  __shared__ float4 part[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                  float4* sup, int64_t n_sup, uint32_t* lf,
+                                                  double* minseg2) {
+  const int lane = threadIdx.x & 63;
   const int64_t o0 = off[0];
-  for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+  const int64_t n_slots = (off[L] - o0) / kCcSuper + L + 1;
+  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t slot = wave; slot < n_slots; slot += nwaves) {
     // largest loop i with (off[i] - off[0]) / kCcSuper + i <= slot
     int32_t lo = 0, hi = L;
     while (hi - lo > 1) {
@@ -113,28 +132,40 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
     }
     const int64_t oi = off[lo], n = off[lo + 1] - oi;
     const int64_t s = slot - ((oi - o0) / kCcSuper + lo);
-    const int64_t nblk = (n + kCcBlock - 1) / kCcBlock;
-    const bool used = s * (kCcSuper / kCcBlock) < nblk;  // uniform over the workgroup
-    if (!used) continue;
+    const int64_t nblk = n > 0 ? (n + kCcBlock - 1) / kCcBlock : 0;
+    constexpr int64_t kPer = kCcSuper / kCcBlock;
+    if (s * kPer >= nblk) continue;  // slot not used by the loop (uniform over the wave)
     const int64_t bbase = (oi - o0) / kCcBlock + lo;
     float4 acc = float4{INFINITY, -INFINITY, INFINITY, -INFINITY};
-    for (int64_t k = s * (kCcSuper / kCcBlock) + wave; k < nblk && k < (s + 1) * (kCcSuper / kCcBlock);
-         k += 4) {
+    uint32_t f = 0u;
+    double mn = INFINITY;
+    const int64_t kend = (s + 1) * kPer < nblk ? (s + 1) * kPer : nblk;
+    for (int64_t k = s * kPer; k < kend; ++k) {
       const int64_t v0 = k * kCcBlock;
       const int64_t m = (n - v0) < kCcBlock ? (n - v0) : kCcBlock;
       float a0 = INFINITY, a1 = -INFINITY, b0 = INFINITY, b1 = -INFINITY, mag = 0.0f;
       for (int t = lane; t <= m; t += 64) {  // m + 1 vertices: the last closes the block
         int64_t v = v0 + t;
         if (v >= n) v -= n;
-        const float x = (float)X[3 * (oi + v)], y = (float)X[3 * (oi + v) + 1],
-                    z = (float)X[3 * (oi + v) + 2];
-        const float a = fmaf(x, pr.e1[0], fmaf(y, pr.e1[1], z * pr.e1[2]));
-        const float b = fmaf(x, pr.e2[0], fmaf(y, pr.e2[1], z * pr.e2[2]));
+        const Tin* p = X + 3 * (oi + v);
+        const double x = (double)p[0], y = (double)p[1], z = (double)p[2];
+        if (t < m) {
+          // the loop's validation: vertex v and its segment to v + 1
+          int64_t w = v + 1;
+          if (w >= n) w -= n;
+          const Tin* q = X + 3 * (oi + w);
+          if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= kFlagNonfinite | kFlagBadloop;
+          const double dx = (double)q[0] - x, dy = (double)q[1] - y, dz = (double)q[2] - z;
+          mn = fmin(mn, dx * dx + dy * dy + dz * dz);
+        }
+        const float xf = (float)x, yf = (float)y, zf = (float)z;
+        const float a = fmaf(xf, pr.e1[0], fmaf(yf, pr.e1[1], zf * pr.e1[2]));
+        const float b = fmaf(xf, pr.e2[0], fmaf(yf, pr.e2[1], zf * pr.e2[2]));
         a0 = fminf(a0, a);
         a1 = fmaxf(a1, a);
         b0 = fminf(b0, b);
         b1 = fmaxf(b1, b);
-        mag = fmaxf(mag, fabsf(x) + fabsf(y) + fabsf(z));
+        mag = fmaxf(mag, fabsf(xf) + fabsf(yf) + fabsf(zf));
       }
       for (int o = 32; o > 0; o >>= 1) {
         a0 = fminf(a0, __shfl_xor(a0, o));
@@ -148,11 +179,17 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
       if (lane == 0 && bbase + k < n_blk) blk[bbase + k] = box;
       acc = box_join(acc, box);
     }
-    if (lane == 0) part[wave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      sup[slot] = box_join(box_join(part[0], part[1]), box_join(part[2], part[3]));
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      f |= (uint32_t)__shfl_xor((int)f, o);
+      mn = fmin(mn, __shfl_xor(mn, o));
+    }
+    if (lane == 0) {
+      if (slot < n_sup) sup[slot] = acc;
+      if (f) atomicOr(&lf[lo], f);
+      if (mn < INFINITY)
+        atomicMin(reinterpret_cast<unsigned long long*>(&minseg2[lo]),
+                  (unsigned long long)__double_as_longlong(mn));
+    }
   }
 }
 
@@ -326,7 +363,10 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
       }
       uint32_t f;
       if (refit) {
-        f = (A.out.flags[p] & ~kFlagNonfinite) | (too_big ? kFlagNonfinite : 0u);
+        // a non-finite value of the previous pass may become finite in FP64;
+        // non-finite coordinates stay non-finite
+        const uint32_t coords = valid ? (li.lf[i] | li.lf[j]) & kFlagNonfinite : 0u;
+        f = (A.out.flags[p] & ~kFlagNonfinite) | coords | (too_big ? kFlagNonfinite : 0u);
       } else if (valid) {
         // Alg. 3's zero-length test: a segment shorter than eps * xi
         const double lim = li.eps * xi;
@@ -558,9 +598,12 @@ __global__ __launch_bounds__(256) void verify_scatter_k(const int32_t* pr, const
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-int prep_blocks(int32_t n_loops) {
-  // one wavefront per loop up to kPrepMaxBlocks * 4 loops
+int prep_blocks(int32_t n_loops, int64_t n_vertices) {
+  // one wavefront per loop up to kPrepMaxBlocks * 4 loops, and (when the
+  // vertex count is known) enough workgroups to stream the coordinates
   int64_t g = ((int64_t)n_loops + 3) / 4;
+  const int64_t gv = n_vertices / 8192;
+  if (gv > g) g = gv;
   if (g < kXiBlocks) g = kXiBlocks;
   if (g > kPrepMaxBlocks) g = kPrepMaxBlocks;
   return (int)g;
@@ -568,25 +611,30 @@ int prep_blocks(int32_t n_loops) {
 
 hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                        double* xi_partials, uint32_t* lf, double* minseg2, int32_t* zero_counts,
-                       unsigned long long* zero_mismatch, int32_t* zero_stop, hipStream_t s) {
-  const int g = prep_blocks(n_loops);
+                       unsigned long long* zero_mismatch, int32_t* zero_stop, bool scan_loops,
+                       int n_blocks, hipStream_t s) {
+  const int g = n_blocks;
+  const int sl = scan_loops ? 1 : 0;
   if (in_f64)
     prep_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, xi_partials, lf, minseg2,
-                                     zero_counts, zero_mismatch, zero_stop);
+                                     zero_counts, zero_mismatch, zero_stop, sl);
   else
     prep_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, xi_partials, lf, minseg2,
-                                    zero_counts, zero_mismatch, zero_stop);
+                                    zero_counts, zero_mismatch, zero_stop, sl);
   return hipGetLastError();
 }
 
 hipError_t launch_cc_boxes(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                            const CcProj& pr, float4* blk, int64_t n_blk, float4* sup,
-                           int64_t n_sup, hipStream_t s) {
-  const int g = blocks_for(n_sup, 1, 65536);
+                           int64_t n_sup, uint32_t* lf, double* minseg2, hipStream_t s) {
+  // four slots (waves) per workgroup; the grid strides over the device's count
+  const int g = blocks_for(n_sup, 4, 16384);
   if (in_f64)
-    cc_boxes_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, pr, blk, n_blk, sup, n_sup);
+    cc_boxes_k<double><<<g, 256, 0, s>>>((const double*)xyz, off, n_loops, pr, blk, n_blk, sup,
+                                         n_sup, lf, minseg2);
   else
-    cc_boxes_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, pr, blk, n_blk, sup, n_sup);
+    cc_boxes_k<float><<<g, 256, 0, s>>>((const float*)xyz, off, n_loops, pr, blk, n_blk, sup, n_sup,
+                                        lf, minseg2);
   return hipGetLastError();
 }
 

@@ -198,23 +198,26 @@ int segs_supported(bool compute_f64, int segs, bool crossings = false);
 constexpr int kXiBlocks = 256;        // least workgroups of the preparation kernel
 constexpr int kPrepMaxBlocks = 4096;  // most workgroups (xi partials buffer size)
 // Workgroups of the preparation kernel for n_loops loops (= xi partials).
-int prep_blocks(int32_t n_loops);
+int prep_blocks(int32_t n_loops, int64_t n_vertices = 0);
 // xi partial sums (one per workgroup) and, one wavefront per loop, the loop's
 // NONFINITE / <3-vertex bits and shortest squared segment; zeroes the main
 // pass's two schedule counts and (when given) the fused check's mismatch
 // count and stop flag.
 // Crossing count: block and superblock boxes of every loop (see kCcBlock)
-// for the slots below n_blk / n_sup (the rest are not written).
+// for the slots below n_blk / n_sup (the rest are not written), and the
+// per-loop validation of the preparation kernel (lf, minseg2, which a
+// preparation launched without its loop scan has initialised).
 struct CcProj {
   float e1[3], e2[3];  // directions spanning the plane orthogonal to the view
 };
 hipError_t launch_cc_boxes(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                            const CcProj& pr, float4* blk, int64_t n_blk, float4* sup,
-                           int64_t n_sup, hipStream_t s);
+                           int64_t n_sup, uint32_t* lf, double* minseg2, hipStream_t s);
 hipError_t launch_prep(const void* xyz, bool in_f64, const int64_t* off, int32_t n_loops,
                        double* xi_partials /*[prep_blocks]*/, uint32_t* lf, double* minseg2,
                        int32_t* zero_counts, unsigned long long* zero_mismatch,
-                       int32_t* zero_stop, hipStream_t s);
+                       int32_t* zero_stop, bool scan_loops, int n_blocks /*prep_blocks*/,
+                       hipStream_t s);
 // Per list position: validate the pair, apply the zero-length test (xi from
 // the partials), zero its accumulator, count its work items and append its
 // record to the small or big list; pairs without work are finalised here.

@@ -233,7 +233,11 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   li.lf = lf;
   li.minseg2 = (const double*)ctx->minseg2.p;
   li.part = xi;
-  li.n_part = prep_blocks(n_loops);
+  // the vertex count is known (and the boxes sized for it) only in CROSSINGS
+  const bool cull = P.crossings && ctx->cc_cull;
+  li.n_part = prep_blocks(n_loops, cull && ctx->cc_off_key == off && ctx->cc_loops_key == n_loops
+                                       ? ctx->cc_vertices
+                                       : 0);
   li.eps = P.in_f64 ? 2.220446049250313080847e-16 : 1.1920928955078125e-07;
 
   Outs out{};
@@ -258,7 +262,6 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   M.acc = acc;
   M.chunk = P.chunk;
   M.bblock = lk::kWave * (P.mixed ? P.segs : P.segs64);
-  const bool cull = P.crossings && ctx->cc_cull;
   M.cc_sup = cull ? (const float4*)ctx->cc_sup.p : nullptr;
   M.cc_nsup = cull ? (int64_t)(ctx->cc_sup.bytes / 16) : 0;
   M.out = out;
@@ -285,11 +288,11 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   A.out = out;
 
   LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
-                     out.n_mismatch, out.stop, s));
+                     out.n_mismatch, out.stop, !cull, li.n_part, s));
   if (cull)
     LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
                            (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
-                           s));
+                           lf, (double*)ctx->minseg2.p, s));
   LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
   LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
   if (timed) LK_HIP(hipEventRecord(ev[0], s));

@@ -303,3 +303,39 @@ def test_culling_matches_brute_force(cctx):
         assert np.array_equal(r1, r0) and np.array_equal(l1, l0) and np.array_equal(f1, f0), ls.name
     # the threaded triangle links its ring once and nothing else
     assert abs(int(l1[0])) == 1 and l1[0] == l1[1] and l1[2] == 0 and l1[3] == 0
+
+
+def test_loop_validation_matches_direct_sum(cctx):
+    """With culling on, the box kernel validates the loops (non-finite
+    coordinates, the zero-length test, fewer than 3 vertices) in place of the
+    preparation kernel: the flags must equal the direct sum's, also for a
+    long loop whose bad vertex lies in a later superblock."""
+    import paper_2106_12655_amd as lk
+    from paper_2106_12655_amd.inputs import _pack
+    t = 2 * np.pi * np.arange(9000) / 9000
+    long_ring = np.stack([np.cos(t), np.sin(t), 0 * t], 1)
+    bad_long = long_ring.copy()
+    bad_long[5000] = np.nan                       # second superblock
+    dup = long_ring[::100].copy()
+    dup[7] = dup[6]                               # a zero-length segment
+    tri = np.array([[0.6, 0.0, -0.5], [1.4, 0.0, -0.45], [1.05, 0.0, 0.7]])
+    two = np.array([[0.0, 0.3, 0.1], [1.0, 0.3, 0.1]])  # clear of the triangle's plane
+    # a NaN coordinate makes xi NaN for its call (the zero-length test then has
+    # no effect), so the non-finite loop gets a call of its own
+    sets = [([long_ring, tri, bad_long, tri + np.array([0.0, 0.0, 0.01])],
+             [[0, 1], [2, 1], [1, 2], [0, 3], [2, 0]], {1: lk.FLAG_NONFINITE, 2: lk.FLAG_NONFINITE}),
+            ([long_ring, tri, dup, two], [[0, 1], [2, 1], [3, 1], [1, 3], [2, 0]],
+             {1: lk.FLAG_BADLOOP, 2: lk.FLAG_BADLOOP, 3: lk.FLAG_BADLOOP})]
+    keep = lk.FLAG_BADLOOP | lk.FLAG_NONFINITE | lk.FLAG_BADPAIR
+    for loops, pairs, want in sets:
+        ls = _pack(loops, np.float32, {}, "validation", 0)
+        pairs = np.array(pairs, np.int32)
+        r_cc, l_cc, f_cc = _run(cctx, ls, pairs, "crossings")
+        r_mx, l_mx, f_mx = _run(cctx, ls, pairs, "mixed")
+        print("validation flags: crossings", f_cc.tolist(), "mixed", f_mx.tolist(), flush=True)
+        assert np.array_equal(f_cc & keep, f_mx & keep)
+        for p_, bit in want.items():
+            assert f_cc[p_] & bit, (p_, f_cc[p_])
+        assert f_cc[0] & keep == 0
+        ok = (f_cc & lk.FLAG_NONFINITE) == 0
+        assert np.array_equal(l_cc[ok], l_mx[ok])
