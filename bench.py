@@ -62,12 +62,13 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 KERNEL_SOURCES = ("lk_ds.hip", "lk_internal.h", "atan_poly.h")
 TRAFFIC = {
     ("chainmail", "mixed"): {
-        "sources": "1ecc67cb3dde5189",
-        "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "small_batch": 4,
-                   "waves_per_cu": 12, "atan_form": 2},
-        "fetch_kib": 23664.7, "write_kib": 2446.7, "fetch_scale": 2.000, "write_scale": 1.000,
+        "sources": "f97649d18050e5de",
+        "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "small_batch": 2,
+                   "waves_per_cu": 0, "atan_form": 2},
+        "fetch_kib": 23703.4, "write_kib": 2548.8, "fetch_scale": 2.000, "write_scale": 1.000,
     },
 }
+
 
 WORKLOADS = {
     "ring_grid": "64 rings x 32 segments on an 8x8 grid, FP64, 105 candidate pairs",
