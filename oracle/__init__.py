@@ -76,6 +76,14 @@ def _load():
         lib.lko_aabb_pairs.argtypes = [p, p, i32, p, i64]
         lib.lko_crossings.restype = d
         lib.lko_crossings.argtypes = [p, i64, p, i64, p, ctypes.POINTER(ctypes.c_int)]
+        lib.lko_bh_pair.restype = d
+        lib.lko_bh_pair.argtypes = [p, i64, p, i64, d, ctypes.c_int, i64, i64,
+                                    ctypes.POINTER(ctypes.c_double)]
+        lib.lko_bh_far_pieces.restype = d
+        lib.lko_bh_far_pieces.argtypes = [p, i64, i64, i64, p, i64, i64, i64, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+        lib.lko_bh_node_moments.restype = None
+        lib.lko_bh_node_moments.argtypes = [p, i64, i64, i64, p]
         lib.lko_set_mutation.restype = None
         lib.lko_set_mutation.argtypes = [ctypes.c_int]
         _lib = lib
@@ -200,3 +208,38 @@ def crossings_random(L, K, seed: int = 0, tries: int = 20) -> float:
         if not deg:
             return v
     raise RuntimeError("no regular projection found")
+
+
+def bh_pair(L, K, beta: float, order: int = 2, leaf: int = 64, arity: int = 8):
+    """Barnes-Hut linking number of loops L (curve 1) and K (curve 2), Alg. 6:
+    trees of ``leaf`` consecutive segments per leaf and ``arity`` children per
+    node, far field to ``order`` (1 dipole, 2 quadrupole).  Returns
+    ``(value, error_estimate)``."""
+    L = _f64(L).reshape(-1, 3)
+    K = _f64(K).reshape(-1, 3)
+    err = ctypes.c_double(0.0)
+    v = _load().lko_bh_pair(_ptr(L), L.shape[0], _ptr(K), K.shape[0], float(beta), int(order),
+                            int(leaf), int(arity), ctypes.byref(err))
+    return v, err.value
+
+
+def bh_node_moments(P, a: int, b: int):
+    """Centre, R and moments (c_M, C_D, C_Q) of the node covering segments
+    [a, b) of loop P, computed directly from its segments."""
+    P = _f64(P).reshape(-1, 3)
+    out = np.zeros(43)
+    _load().lko_bh_node_moments(_ptr(P), P.shape[0], int(a), int(b), _ptr(out))
+    return {"c": out[0:3], "R": out[3], "M": out[4:7], "D": out[7:16].reshape(3, 3),
+            "Q": out[16:43].reshape(3, 3, 3)}
+
+
+def bh_far_pieces(P1, a1: int, b1: int, P2, a2: int, b2: int, order: int = 2):
+    """Far-field estimate of the Gauss integral between segments [a1, b1) of
+    loop P1 and [a2, b2) of loop P2, and the exact Eq. 4 sum over the same
+    segment pairs: ``(estimate, exact)``."""
+    P1 = _f64(P1).reshape(-1, 3)
+    P2 = _f64(P2).reshape(-1, 3)
+    ex = ctypes.c_double(0.0)
+    v = _load().lko_bh_far_pieces(_ptr(P1), P1.shape[0], int(a1), int(b1), _ptr(P2), P2.shape[0],
+                                  int(a2), int(b2), int(order), ctypes.byref(ex))
+    return v, ex.value

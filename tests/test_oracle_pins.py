@@ -104,9 +104,104 @@ def pin_integer_and_refinement():
     return None
 
 
+# ---------------------------------------------------------------- Barnes-Hut
+def _bh_loops():
+    t = np.linspace(0, 2 * np.pi, 200, endpoint=False)
+    P1 = np.stack([np.cos(t), np.sin(t), 0.3 * np.sin(3 * t)], 1)
+    P2 = np.stack([0.7 * np.cos(2 * t), np.sin(t), 0.2 * np.cos(t)], 1)
+    return P1, P2
+
+
+def pin_bh_exact_limit():
+    """With beta -> infinity no node pair is far: Alg. 6 is the direct sum of
+    Eq. 3 over the leaves, for any tree shape."""
+    for ls in (I.hopf(64), I.torus_link(2, 3, 400)):
+        A, B = ls.loop(0), ls.loop(1)
+        ex = oracle.pair(A, B)
+        for leaf, arity in ((1, 2), (4, 8), (64, 8)):
+            v, _ = oracle.bh_pair(A, B, 1e30, 2, leaf, arity)
+            if abs(v - ex) > 1e-10:
+                return "BH with infinite beta differs from the direct sum"
+    return None
+
+
+def pin_bh_segment_moments():
+    """A single segment about its midpoint: c_M = s, C_D = 0,
+    C_Q = s (x) s (x) s / 12 (the closed forms of the appendix)."""
+    P1, _ = _bh_loops()
+    for a in (5, 77):
+        m = oracle.bh_node_moments(P1, a, a + 1)
+        sv = P1[a + 1] - P1[a]
+        if np.abs(m["M"] - sv).max() > 1e-15 or np.abs(m["D"]).max() > 1e-15:
+            return "segment monopole or dipole moment wrong"
+        if np.abs(m["Q"] - np.einsum("i,j,k->ijk", sv, sv, sv) / 12).max() > 1e-15:
+            return "segment quadrupole moment wrong"
+    return None
+
+
+def pin_bh_shift_rule():
+    """Moments of a node equal its children's moments moved to its centre by
+    the appendix's shift rules (c_M sums; C_D gains c_M r^T; C_Q gains the
+    C_D r and c_M r r terms), r = child centre - parent centre."""
+    P1, _ = _bh_loops()
+    for a, m_, b in ((0, 17, 40), (30, 31, 95), (100, 150, 200)):
+        par = oracle.bh_node_moments(P1, a, b)
+        M = np.zeros(3)
+        D = np.zeros((3, 3))
+        Q = np.zeros((3, 3, 3))
+        for lo, hi in ((a, m_), (m_, b)):
+            ch = oracle.bh_node_moments(P1, lo, hi)
+            r = ch["c"] - par["c"]
+            M += ch["M"]
+            D += ch["D"] + np.outer(ch["M"], r)
+            Q += (ch["Q"] + np.einsum("ij,k->ijk", ch["D"], r) + np.einsum("ik,j->ijk", ch["D"], r)
+                  + np.einsum("i,j,k->ijk", ch["M"], r, r))
+        scale = 1.0 + np.abs(par["Q"]).max()
+        if (np.abs(M - par["M"]).max() > 1e-13 or np.abs(D - par["D"]).max() > 1e-13
+                or np.abs(Q - par["Q"]).max() > 1e-13 * scale):
+            return "moment shift rule broken"
+    return None
+
+
+def pin_bh_expansion_order():
+    """The far-field expansion of Sec. 3.4.4 against the exact Eq. 4 sum of
+    two curve pieces at distance d: the error falls like d^-4 with monopole
+    and dipole terms and like d^-5 with the quadrupole term as well."""
+    P1, P2 = _bh_loops()
+    shift = np.array([1.0, 0.3, -0.2])
+    for order, want in ((1, 16.0), (2, 32.0)):
+        errs = []
+        for d in (32.0, 64.0):
+            est, ex = oracle.bh_far_pieces(P1, 10, 40, P2 + d * shift, 100, 150, order)
+            errs.append(abs(est - ex))
+        ratio = errs[0] / errs[1]
+        if not (0.75 * want < ratio < 1.3 * want):
+            return "far-field error of order %d falls by %.1f, not %.0f, per doubling" % (
+                order, ratio, want)
+    return None
+
+
+def pin_bh_accuracy():
+    """On a torus link the quadrupole expansion at beta = 4 is within 1e-3 of
+    the direct sum, and better than the dipole expansion at beta = 2."""
+    ls = I.torus_link(2, 3, 400)
+    A, B = ls.loop(0), ls.loop(1)
+    ex = oracle.pair(A, B)
+    v4, e4 = oracle.bh_pair(A, B, 4.0, 2, 4, 8)
+    v2q, _ = oracle.bh_pair(A, B, 2.0, 2, 4, 8)
+    v2d, _ = oracle.bh_pair(A, B, 2.0, 1, 4, 8)
+    if abs(v4 - ex) > 1e-3 or not e4 > 0:
+        return "BH at beta 4 too far from the direct sum"
+    if not abs(v2q - ex) < abs(v2d - ex):
+        return "quadrupole expansion not better than dipole"
+    return None
+
+
 def run_pins():
     fails = []
-    for f in (pin_segment_terms, pin_hopf, pin_torus, pin_crossings, pin_integer_and_refinement):
+    for f in (pin_segment_terms, pin_hopf, pin_torus, pin_crossings, pin_integer_and_refinement,
+              pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
+              pin_bh_expansion_order, pin_bh_accuracy):
         r = f()
         if r:
             fails.append(r)
@@ -274,10 +369,12 @@ def test_loop_flags():
     assert f[1] & oracle.FLAG_NONFINITE
 
 
-@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_planted_mistakes_are_caught(mutation):
     """A dropped term, a wrong sign, a wrong index, a transposed operand, an
-    open loop or a wrong normalisation each break at least one pin."""
+    open loop, a wrong normalisation, a wrong sign of the Barnes-Hut dipole
+    term or a dropped part of the segment quadrupole moment each break at
+    least one pin."""
     oracle.set_mutation(mutation)
     try:
         fails = run_pins()
@@ -285,3 +382,9 @@ def test_planted_mistakes_are_caught(mutation):
         oracle.set_mutation(0)
     assert fails, "mutation %d went unnoticed" % mutation
     assert run_pins() == []
+
+
+def test_bh_pins():
+    for f in (pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
+              pin_bh_expansion_order, pin_bh_accuracy):
+        assert f() is None, f.__name__
