@@ -75,7 +75,16 @@ typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
  * disjoint from the other loop's block (LK_OPT_CROSSING_CULL).  To size those
  * boxes the first CROSSINGS call with a given offsets array reads its
  * vertex count from the device, which synchronises the stream once. */
-typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1, LK_CROSSINGS = 2 } lk_mode;
+/* BARNES_HUT: the two-tree Barnes-Hut method (Sec. 3.4.4, Alg. 6), an
+ * approximation with the direct sum's Eq. 4 at the leaves: trees over runs of
+ * 64 consecutive segments (8 children per node), node pairs farther apart
+ * than beta times the sum of their box radii use the far-field expansion to
+ * the given order (LK_OPT_BH_BETA_MILLI, LK_OPT_BH_ORDER; default beta 4,
+ * quadrupole order) in FP64, leaf pairs the FP32 term with FP64 sums.  Pairs
+ * whose value is farther than the refit threshold from an integer are
+ * recomputed by the FP64 direct sum, as in MIXED.  Like CROSSINGS, the first
+ * call for an offsets array reads its vertex count (one synchronisation). */
+typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1, LK_CROSSINGS = 2, LK_BARNES_HUT = 3 } lk_mode;
 
 /* Per-pair flags (bit set). */
 enum {
@@ -188,9 +197,13 @@ enum {
   LK_OPT_CROSSING_TOL = 11,       /* CROSSINGS: multiplier of the certainty bounds, 1..2^20
                                      (default 1); larger values send more pairs to the FP64
                                      direct sum, never fewer */
-  LK_OPT_CROSSING_CULL = 12       /* CROSSINGS: 1 = skip vertex blocks and pairs whose projected
+  LK_OPT_CROSSING_CULL = 12,      /* CROSSINGS: 1 = skip vertex blocks and pairs whose projected
                                      boxes are disjoint (default), 0 = test every segment pair;
                                      the results are the same */
+  LK_OPT_BH_BETA_MILLI = 13,      /* BARNES_HUT: far-field ratio beta x 1000, 500..1e6
+                                     (default 4000) */
+  LK_OPT_BH_ORDER = 14            /* BARNES_HUT: 1 = monopole and dipole terms, 2 = also the
+                                     quadrupole term (default) */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */

@@ -17,14 +17,15 @@ _lib = None
 # lk_status
 OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
-PLAIN_F64, MIXED, CROSSINGS = 0, 1, 2
-MODES = {"plain": PLAIN_F64, "mixed": MIXED, "crossings": CROSSINGS}
+PLAIN_F64, MIXED, CROSSINGS, BARNES_HUT = 0, 1, 2, 3
+MODES = {"plain": PLAIN_F64, "mixed": MIXED, "crossings": CROSSINGS, "barnes_hut": BARNES_HUT}
 FLAG_REFIT, FLAG_AMBIGUOUS, FLAG_NONFINITE, FLAG_BADPAIR, FLAG_BADLOOP = 1, 2, 4, 8, 16
 FLAG_SKIPPED = 32
 INT_INVALID = -(2 ** 31)
 OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 3, 4, 5
 OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
 OPT_SMALL_BATCH, OPT_CROSSING_TOL, OPT_CROSSING_CULL = 10, 11, 12
+OPT_BH_BETA_MILLI, OPT_BH_ORDER = 13, 14
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
            "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_set_view_direction",

@@ -410,18 +410,6 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
   }
 }
 
-// 128-bit two's complement -> sign and magnitude -> double (one rounding of
-// the fraction word, one of the sum).
-__device__ __forceinline__ double from_fixed(unsigned long long lo, unsigned long long hi) {
-  const bool neg = (long long)hi < 0;
-  if (neg) {
-    lo = ~lo + 1ull;
-    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
-  }
-  const double mag = (double)hi + (double)lo * 5.421010862427522170e-20;  // 2^-64
-  return neg ? -mag : mag;
-}
-
 __global__ __launch_bounds__(256) void finalize_split_k(Sched S, const unsigned long long* acc,
                                                         Outs o) {
   if (o.stop && *o.stop) return;  // a fused check stopped early: sums may be partial

@@ -1,0 +1,430 @@
+// lk_bh.hip -- Barnes-Hut linking numbers (Sec. 3.4.4, Alg. 6) on the GPU.
+//
+// Trees over consecutive segments (a polyline is already spatially coherent,
+// so no sort): leaves of kBhLeaf segments, kBhArity children per node.  The
+// leaves are boxed and their moments summed by one wavefront each; each level
+// above is one launch, a thread per node, shifting the children's moments to
+// the node's centre with the appendix's rules.  The two-tree traversal of
+// Alg. 6 runs breadth first: every launch takes the node pairs of one step,
+// evaluates the far-field expansion (FP64, monopole + dipole + quadrupole) for
+// pairs farther apart than beta (R_A + R_B), hands pairs of two leaves to the
+// direct sum (lk_ds.hip) and splits the others into child pairs for the next
+// step.  All counts live on the device and every launch has a host-known
+// shape, so the sequence can be captured in a HIP graph.  Sums go into the
+// pair's 128-bit fixed-point accumulator, so they do not depend on order.
+#include "lk_internal.h"
+
+namespace lk {
+namespace {
+
+// Largest loop i with (off[i] - off[0]) / span + i <= slot.
+__device__ __forceinline__ int32_t find_loop(const int64_t* off, int32_t L, int64_t slot,
+                                             int64_t span) {
+  const int64_t o0 = off[0];
+  int32_t lo = 0, hi = L;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((off[mid] - o0) / span + mid <= slot)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t node_slot(const BhArgs& A, int32_t loop, int h, int64_t k) {
+  return A.level_base[h] + (A.off[loop] - A.off[0]) / bh_span(h) + loop + k;
+}
+
+// Slots of level h that the device offsets need.
+__device__ __forceinline__ int64_t level_slots(const BhArgs& A, int h) {
+  return (A.off[A.n_loops] - A.off[0]) / bh_span(h) + A.n_loops + 1;
+}
+
+// Lowest level with a single node for a loop of n segments.
+__device__ __forceinline__ int root_level(int64_t n) {
+  int h = 0;
+  while (bh_count(n, h) > 1) ++h;
+  return h;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// --------------------------------------------------------------- leaves
+// One wavefront per leaf slot: lane t holds segment t of the leaf.  The box
+// covers the leaf's vertices (with the one closing its last segment); a
+// segment with vector s and midpoint offset d from the centre adds s, s d^T
+// and s (x) d (x) d + s (x) s (x) s / 12 (its exact moments).
+template <typename Tin>
+__global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
+  if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 2) A.counts[threadIdx.x] = 0;
+  const Tin* X = static_cast<const Tin*>(A.xyz);
+  const int lane = threadIdx.x & 63;
+  const int64_t n_slots = level_slots(A, 0);
+  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t slot = wave; slot < n_slots; slot += nwaves) {
+    const int32_t i = find_loop(A.off, A.n_loops, slot, kBhLeaf);
+    const int64_t oi = A.off[i], n = A.off[i + 1] - oi;
+    const int64_t k = slot - ((oi - A.off[0]) / kBhLeaf + i);
+    if (k >= bh_count(n, 0)) continue;  // uniform over the wave
+    const int64_t a = k * kBhLeaf;
+    const int m = (int)((n - a) < kBhLeaf ? (n - a) : kBhLeaf);
+    double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0};
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (lane < m) {
+      int64_t v1 = a + lane + 1;
+      if (v1 >= n) v1 -= n;
+      for (int q = 0; q < 3; ++q) {
+        x0[q] = (double)X[3 * (oi + a + lane) + q];
+        x1[q] = (double)X[3 * (oi + v1) + q];
+        lo[q] = fmin(x0[q], x1[q]);
+        hi[q] = fmax(x0[q], x1[q]);
+      }
+    }
+    for (int q = 0; q < 3; ++q)
+      for (int o = 32; o > 0; o >>= 1) {
+        lo[q] = fmin(lo[q], __shfl_xor(lo[q], o));
+        hi[q] = fmax(hi[q], __shfl_xor(hi[q], o));
+      }
+    BhNode nd;
+    for (int q = 0; q < 3; ++q) {
+      nd.c[q] = 0.5 * (lo[q] + hi[q]);
+      nd.e[q] = 0.5 * (hi[q] - lo[q]);
+    }
+    double s[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+    if (lane < m)
+      for (int q = 0; q < 3; ++q) {
+        s[q] = x1[q] - x0[q];
+        d[q] = 0.5 * (x0[q] + x1[q]) - nd.c[q];
+      }
+    for (int p = 0; p < 3; ++p) {
+      nd.M[p] = wave_sum(s[p]);
+      for (int b = 0; b < 3; ++b) {
+        nd.D[3 * p + b] = wave_sum(s[p] * d[b]);
+        for (int c = 0; c < 3; ++c)
+          nd.Q[9 * p + 3 * b + c] =
+              wave_sum(s[p] * d[b] * d[c] + s[p] * s[b] * s[c] * (1.0 / 12.0));
+      }
+    }
+    const int64_t dst = A.level_base[0] + slot;
+    if (lane == 0 && slot < A.level_cap[0]) A.nodes[dst] = nd;
+  }
+}
+
+// ---------------------------------------------------------------- levels
+// One thread per node of level h (>= 1): the box of its children's boxes,
+// and their moments moved to its centre (r = child centre - node centre):
+//   c_M += c_Mc;  C_D += C_Dc + c_Mc r^T;
+//   C_Q[p][b][c] += C_Qc[p][b][c] + C_Dc[p][b] r_c + C_Dc[p][c] r_b + c_Mc[p] r_b r_c.
+__global__ __launch_bounds__(256) void bh_level_k(BhArgs A, int h) {
+  const int64_t n_slots = level_slots(A, h);
+  const int64_t span = bh_span(h);
+  for (int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x; slot < n_slots;
+       slot += (int64_t)gridDim.x * 256) {
+    const int32_t i = find_loop(A.off, A.n_loops, slot, span);
+    const int64_t n = A.off[i + 1] - A.off[i];
+    const int64_t k = slot - ((A.off[i] - A.off[0]) / span + i);
+    const int64_t nch = bh_count(n, h - 1);
+    if (k >= bh_count(n, h) || nch <= 1) continue;  // no such node, or above the root
+    if (slot >= A.level_cap[h]) continue;
+    const int64_t c0 = k * kBhArity, c1 = (c0 + kBhArity) < nch ? c0 + kBhArity : nch;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool ok = true;
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t cs = node_slot(A, i, h - 1, c);
+      if (cs - A.level_base[h - 1] >= A.level_cap[h - 1]) {
+        ok = false;
+        break;
+      }
+      const BhNode& ch = A.nodes[cs];
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = fmin(lo[q], ch.c[q] - ch.e[q]);
+        hi[q] = fmax(hi[q], ch.c[q] + ch.e[q]);
+      }
+    }
+    BhNode nd;
+    for (int q = 0; q < 3; ++q) {
+      nd.c[q] = ok ? 0.5 * (lo[q] + hi[q]) : __builtin_nan("");
+      nd.e[q] = ok ? 0.5 * (hi[q] - lo[q]) : __builtin_nan("");
+    }
+    for (int q = 0; q < 3; ++q) nd.M[q] = 0.0;
+    for (int q = 0; q < 9; ++q) nd.D[q] = 0.0;
+    for (int q = 0; q < 27; ++q) nd.Q[q] = 0.0;
+    if (ok)
+      for (int64_t c = c0; c < c1; ++c) {
+        const BhNode& ch = A.nodes[node_slot(A, i, h - 1, c)];
+        double r[3];
+        for (int q = 0; q < 3; ++q) r[q] = ch.c[q] - nd.c[q];
+        for (int p = 0; p < 3; ++p) {
+          nd.M[p] += ch.M[p];
+          for (int b = 0; b < 3; ++b) {
+            nd.D[3 * p + b] += ch.D[3 * p + b] + ch.M[p] * r[b];
+            for (int cc = 0; cc < 3; ++cc)
+              nd.Q[9 * p + 3 * b + cc] += ch.Q[9 * p + 3 * b + cc] + ch.D[3 * p + b] * r[cc] +
+                                          ch.D[3 * p + cc] * r[b] + ch.M[p] * r[b] * r[cc];
+          }
+        }
+      }
+    A.nodes[A.level_base[h] + slot] = nd;
+  }
+}
+
+// ------------------------------------------------------------------ roots
+__global__ __launch_bounds__(256) void bh_roots_k(BhArgs A, int64_t n_pairs) {
+  const int lane = threadIdx.x & 63;
+  // the same trip count in every lane (the append is wavefront-collective)
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n_pairs; base += (int64_t)gridDim.x * 256) {
+    const int64_t p = base + threadIdx.x;
+    bool push = false;
+    BhPair root{0, 0, 0, 0};
+    if (p < n_pairs) {
+      const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
+      const bool valid = i >= 0 && j >= 0 && i < A.n_loops && j < A.n_loops && i != j;
+      const int64_t na = valid ? A.off[i + 1] - A.off[i] : 0, nb = valid ? A.off[j + 1] - A.off[j] : 0;
+      // pairs without work were finalised by the plan
+      if (valid && na >= 1 && nb >= 1 && na <= 0x7fffffffLL && nb <= 0x7fffffffLL) {
+        push = true;
+        root = BhPair{(int32_t)p, 0, 0, root_level(na) | (root_level(nb) << 8)};
+      }
+    }
+    const unsigned long long m = __ballot(push);
+    const int leader = m ? __ffsll((long long)m) - 1 : 0;
+    int32_t b0 = 0;
+    if (m && lane == leader) b0 = atomicAdd(&A.counts[0], (int32_t)__popcll(m));
+    b0 = __shfl(b0, leader);
+    if (push) {
+      const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const int64_t at = (int64_t)b0 + __popcll(m & below);
+      if (at < A.list_cap)
+        A.list[0][at] = root;
+      else
+        atomicOr(&A.out.flags[root.p], kFlagNonfinite);  // list full: the pair is refitted
+    }
+  }
+}
+
+// ------------------------------------------------------------- far field
+// The expansion of the Gauss integral about the two node centres, with the
+// derivatives of G = -1/(4 pi |r1 - r2|) at r = c_B - c_A:
+//   g = r / (4 pi |r|^3),  H = (I |r|^2 - 3 r r^T) / (4 pi |r|^5),
+//   K_abc = -3 (r_a d_bc + r_b d_ac + r_c d_ab) / (4 pi |r|^5) + 15 r_a r_b r_c / (4 pi |r|^7);
+//   lambda ~ -[ (M_A x M_B) . g
+//             + sum_ab H_ab eps_apq (-D_A[p][b] M_B[q] + M_A[p] D_B[q][b])
+//             + 1/2 sum_abc K_abc eps_apq (Q_A[p][b][c] M_B[q] - D_A[p][b] D_B[q][c]
+//                                         - D_A[p][c] D_B[q][b] + M_A[p] Q_B[q][b][c]) ].
+// eps_apq is non-zero for the six cyclic and anti-cyclic index triples only.
+__device__ double far_field(const BhNode& u, const BhNode& v, int order) {
+  double r[3];
+  for (int q = 0; q < 3; ++q) r[q] = v.c[q] - u.c[q];
+  const double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double id = 1.0 / sqrt(d2);
+  const double f = 0.07957747154594766788;  // 1 / (4 pi)
+  const double i3 = f * id * id * id, i5 = i3 * id * id, i7 = i5 * id * id;
+  // cross-type contractions: X_a = eps_apq x_p y_q for the index triples
+  constexpr int P[3] = {1, 2, 0}, Qx[3] = {2, 0, 1};  // (a, p, q) cyclic: +1, (a, q, p): -1
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int p = P[a], q = Qx[a];
+    // eps_apq = +1, eps_aqp = -1
+    t1 += (u.M[p] * v.M[q] - u.M[q] * v.M[p]) * r[a] * i3;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double Hab = ((a == b) ? d2 : 0.0) * i5 - 3.0 * r[a] * r[b] * i5;
+      const double m = (-u.D[3 * p + b] * v.M[q] + u.M[p] * v.D[3 * q + b]) -
+                       (-u.D[3 * q + b] * v.M[p] + u.M[q] * v.D[3 * p + b]);
+      t2 += Hab * m;
+      if (order >= 2) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double sym = r[a] * (b == c) + r[b] * (a == c) + r[c] * (a == b);
+          const double Kabc = -3.0 * sym * i5 + 15.0 * r[a] * r[b] * r[c] * i7;
+          const double mp = u.Q[9 * p + 3 * b + c] * v.M[q] - u.D[3 * p + b] * v.D[3 * q + c] -
+                            u.D[3 * p + c] * v.D[3 * q + b] + u.M[p] * v.Q[9 * q + 3 * b + c];
+          const double mq = u.Q[9 * q + 3 * b + c] * v.M[p] - u.D[3 * q + b] * v.D[3 * p + c] -
+                            u.D[3 * q + c] * v.D[3 * p + b] + u.M[q] * v.Q[9 * p + 3 * b + c];
+          t3 += 0.5 * Kabc * (mp - mq);
+        }
+      }
+    }
+  }
+  return -(t1 + t2 + t3);
+}
+
+// ------------------------------------------------------------ traversal
+// One breadth-first step over the node pairs of iteration `it`.
+__global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
+  const int lane = threadIdx.x & 63;
+  const BhPair* in = A.list[it & 1];
+  BhPair* out = A.list[(it + 1) & 1];
+  int32_t* n_out = &A.counts[it + 1];
+  int32_t* n_near = &A.counts[kBhMaxIters + 1];
+  const int64_t n_in = A.counts[it] < A.list_cap ? A.counts[it] : A.list_cap;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  // the same trip count in every lane (the appends are wavefront-collective)
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n_in; base += stride) {
+    const int64_t e = base + threadIdx.x;
+    const bool has = e < n_in;
+    BhPair w = has ? in[e] : BhPair{-1, 0, 0, 0};
+    double val = 0.0;
+    bool near = false, fail = false;
+    int nch = 0, split_a = 0, hc = 0;
+    int64_t cbase = 0;
+    if (has) {
+      const int ha = w.lev & 255, hb = w.lev >> 8;
+      const int32_t i = A.pairs[2 * (int64_t)w.p], j = A.pairs[2 * (int64_t)w.p + 1];
+      const int64_t sa = node_slot(A, i, ha, w.ka), sb = node_slot(A, j, hb, w.kb);
+      if (sa - A.level_base[ha] >= A.level_cap[ha] || sb - A.level_base[hb] >= A.level_cap[hb]) {
+        fail = true;
+      } else {
+        const BhNode& u = A.nodes[sa];
+        const BhNode& v = A.nodes[sb];
+        double d2 = 0.0, ra2 = 0.0, rb2 = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          const double dq = v.c[q] - u.c[q];
+          d2 += dq * dq;
+          ra2 += u.e[q] * u.e[q];
+          rb2 += v.e[q] * v.e[q];
+        }
+        const double ra = sqrt(ra2), rb = sqrt(rb2);
+        if (sqrt(d2) > A.beta * (ra + rb)) {
+          val = far_field(u, v, A.order);
+        } else if (ha == 0 && hb == 0) {
+          near = true;
+        } else {
+          split_a = ha > 0 && (hb == 0 || ra > rb);
+          const int64_t n = split_a ? A.off[i + 1] - A.off[i] : A.off[j + 1] - A.off[j];
+          hc = (split_a ? ha : hb) - 1;
+          const int64_t cnt = bh_count(n, hc);
+          cbase = (int64_t)(split_a ? w.ka : w.kb) * kBhArity;
+          const int64_t c1 = (cbase + kBhArity) < cnt ? cbase + kBhArity : cnt;
+          nch = (int)(c1 - cbase);
+        }
+      }
+    }
+    if (fail) atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+    // far-field values: one fixed-point add per pair present in the wave
+    unsigned long long rem = __ballot(val != 0.0);
+    while (rem) {
+      const int leader = __ffsll((long long)rem) - 1;
+      const int32_t pl = __shfl(w.p, leader);
+      const bool mine = val != 0.0 && w.p == pl;
+      const unsigned long long m = __ballot(mine);
+      const double sum = wave_sum(mine ? val : 0.0);
+      if (lane == leader) {
+        if (fabs(sum) < 1.0e14)
+          fixed_add(&A.acc[2 * (int64_t)pl], sum);
+        else
+          atomicOr(&A.out.flags[pl], kFlagNonfinite);  // NaN or absurd: refitted
+      }
+      rem &= ~m;
+    }
+    // leaf pairs to the direct sum
+    {
+      const unsigned long long m = __ballot(near);
+      int32_t nb = 0;
+      const int leader = m ? __ffsll((long long)m) - 1 : 0;
+      if (m && lane == leader) nb = atomicAdd(n_near, (int32_t)__popcll(m));
+      nb = __shfl(nb, leader);
+      const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+      if (near) {
+        const int64_t at = (int64_t)nb + __popcll(m & below);
+        if (at < A.near_cap)
+          A.near[at] = w;
+        else
+          atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+      }
+    }
+    // child pairs to the next step
+    {
+      int32_t x = nch;  // inclusive scan of the child counts
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      const int32_t total = __shfl(x, 63);
+      int32_t b0 = 0;
+      if (total > 0 && lane == 0) b0 = atomicAdd(n_out, total);
+      b0 = __shfl(b0, 0);
+      if (nch > 0) {
+        const int ha = w.lev & 255, hb = w.lev >> 8;
+        int64_t at = (int64_t)b0 + x - nch;
+        bool over = false;
+        for (int c = 0; c < nch; ++c, ++at) {
+          if (at >= A.list_cap) {
+            over = true;
+            break;
+          }
+          BhPair ch = w;
+          if (split_a) {
+            ch.ka = (int32_t)(cbase + c);
+            ch.lev = hc | (hb << 8);
+          } else {
+            ch.kb = (int32_t)(cbase + c);
+            ch.lev = ha | (hc << 8);
+          }
+          out[at] = ch;
+        }
+        if (over) atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- finalise
+__global__ __launch_bounds__(256) void bh_finalize_k(BhArgs A, int64_t n_pairs) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n_pairs;
+       p += (int64_t)gridDim.x * 256) {
+    const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
+    if (i < 0 || j < 0 || i >= A.n_loops || j >= A.n_loops || i == j) continue;
+    const int64_t na = A.off[i + 1] - A.off[i], nb = A.off[j + 1] - A.off[j];
+    if (na < 1 || nb < 1 || na > 0x7fffffffLL || nb > 0x7fffffffLL) continue;
+    finalize_pair(A.out, (int32_t)p, from_fixed(A.acc[2 * p], A.acc[2 * p + 1]), A.out.flags[p]);
+  }
+}
+
+inline int grid_for(int64_t n, int per_block, int cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_bh_leaves(const BhArgs& a, bool in_f64, hipStream_t s) {
+  const int g = grid_for(a.level_cap[0], 4, 16384);
+  if (in_f64)
+    bh_leaves_k<double><<<g, 256, 0, s>>>(a);
+  else
+    bh_leaves_k<float><<<g, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_level(const BhArgs& a, int level, hipStream_t s) {
+  bh_level_k<<<grid_for(a.level_cap[level], 256, 4096), 256, 0, s>>>(a, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_roots(const BhArgs& a, int64_t n_pairs, hipStream_t s) {
+  bh_roots_k<<<grid_for(n_pairs, 256, 1024), 256, 0, s>>>(a, n_pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_expand(const BhArgs& a, int it, hipStream_t s) {
+  bh_expand_k<<<2048, 256, 0, s>>>(a, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_finalize(const BhArgs& a, int64_t n_pairs, hipStream_t s) {
+  bh_finalize_k<<<grid_for(n_pairs, 256, 1024), 256, 0, s>>>(a, n_pairs);
+  return hipGetLastError();
+}
+
+}  // namespace lk

@@ -275,44 +275,6 @@ __device__ __forceinline__ T walk_step(Walk<T, R>& w, const V3<T>& l1, const Seg
   return sum;
 }
 
-// 128-bit two's-complement fixed point with 64 fraction bits, accumulated with
-// 64-bit integer atomics: integer addition is associative, so the pair sum is
-// the same whatever order the work items finish in.  The conversion is exact
-// except for bits below 2^-64, which are dropped by an arithmetic shift (always
-// towards -infinity, so deterministically).  |v| < 2^50 is required.
-__device__ __forceinline__ void to_fixed(double v, unsigned long long& lo, unsigned long long& hi) {
-  lo = 0ull;
-  hi = 0ull;
-  if (v == 0.0) return;
-  int e = 0;
-  const double f = frexp(v, &e);                   // v = f 2^e, 0.5 <= |f| < 1
-  const long long m = (long long)ldexp(f, 53);     // exact: |m| < 2^53
-  const int s = e + 11;                            // v 2^64 = m 2^s
-  if (s > 0) {
-    lo = (unsigned long long)m << s;
-    hi = (unsigned long long)(m >> (64 - s));
-  } else if (s == 0) {
-    lo = (unsigned long long)m;
-    hi = m < 0 ? ~0ull : 0ull;
-  } else if (s > -64) {
-    const long long t = m >> (-s);
-    lo = (unsigned long long)t;
-    hi = t < 0 ? ~0ull : 0ull;
-  } else {
-    lo = m < 0 ? ~0ull : 0ull;
-    hi = lo;
-  }
-}
-
-__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
-  unsigned long long lo, hi;
-  to_fixed(v, lo, hi);
-  if (lo == 0ull && hi == 0ull) return;
-  const unsigned long long old = atomicAdd(&acc[0], lo);
-  const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
-  atomicAdd(&acc[1], hi + carry);
-}
-
 // Where the lanes of one work item sit: B block [b0, b0 + nbh) of loop B split
 // into `slots` lanes of R segments; if that leaves lanes over, they form
 // `groups` that split the item's A range [a0, a0 + nah) into [js, je).
@@ -635,6 +597,12 @@ __device__ __forceinline__ double value_scale() {
   return AT == kCrossings ? 0.5 : kInvTwoPi;
 }
 
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // Wave sum of the lanes' partials.  `whole`: this item is the pair's only one,
 // so its value is final and the pair is finalised at once (`fpre`: the pair's
 // flags as the plan left them, loaded when the item started so that finishing
@@ -806,6 +774,74 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   }
 }
 
+// Leaf pairs of the Barnes-Hut traversal (Alg. 6, both nodes leaves): Eq. 4
+// over their kBhLeaf x kBhLeaf segment pairs with the walk above (one B
+// segment per lane, the A leaf's vertices in LDS; FP32 terms, FP64 sums).  A
+// wave takes 32 consecutive entries of the list and adds one sum per run of
+// entries of the same pair into its fixed-point accumulator.
+template <typename Tin>
+__global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
+  __shared__ Vtx<float> lds[kBhLeaf + 1];
+  const int lane = threadIdx.x;
+  const Tin* X = static_cast<const Tin*>(A.xyz);
+  const int64_t cnt = A.counts[kBhMaxIters + 1];
+  const int64_t n = cnt < A.near_cap ? cnt : A.near_cap;
+  constexpr int kChunk = 32;
+  for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < n; c0 += (int64_t)gridDim.x * kChunk) {
+    const int64_t c1 = (c0 + kChunk) < n ? c0 + kChunk : n;
+    double run = 0.0;
+    int32_t pr = -1;
+    for (int64_t e = c0; e <= c1; ++e) {
+      const int32_t pe = e < c1 ? A.near[e].p : -1;
+      if (pe != pr && pr >= 0) {
+        const double v = wave_sum_d(run) * kInvTwoPi;
+        if (lane == 0) {
+          if (fabs(v) < 1.0e14)
+            fixed_add(&A.acc[2 * (int64_t)pr], v);
+          else
+            atomicOr(&A.out.flags[pr], kFlagNonfinite);
+        }
+        run = 0.0;
+      }
+      if (e == c1) break;
+      pr = pe;
+      const BhPair w = A.near[e];
+      const int32_t i = A.pairs[2 * (int64_t)w.p], j = A.pairs[2 * (int64_t)w.p + 1];
+      const int64_t oa = A.off[i], na = A.off[i + 1] - oa;
+      const int64_t ob = A.off[j], nb = A.off[j + 1] - ob;
+      const int64_t a0 = (int64_t)w.ka * kBhLeaf, b0 = (int64_t)w.kb * kBhLeaf;
+      const int ma = (int)((na - a0) < kBhLeaf ? (na - a0) : kBhLeaf);
+      const int mb = (int)((nb - b0) < kBhLeaf ? (nb - b0) : kBhLeaf);
+      __syncthreads();
+      for (int t = lane; t <= ma; t += kWave) {
+        int64_t idx = a0 + t;
+        if (idx >= na) idx -= na;  // closing vertex of the loop
+        const V3<float> x = load_vertex<float>(X, oa + idx);
+        lds[t] = Vtx<float>{x.x, x.y, x.z, 0.0f};
+      }
+      Segs<float, 1> sg;
+      {
+        const int64_t ib = b0 + (lane < mb ? lane : mb - 1);
+        const int64_t ib1 = ib + 1 < nb ? ib + 1 : 0;
+        sg.k[0] = load_vertex<float>(X, ob + ib);
+        sg.k[1] = load_vertex<float>(X, ob + ib1);
+        sg.s[0] = sg.k[1] - sg.k[0];
+        sg.m[0] = V3<float>{0.0f, 0.0f, 0.0f};
+        sg.valid[0] = lane < mb;
+      }
+      __syncthreads();
+      Walk<float, 1> wk;
+      walk_init(wk, V3<float>{lds[0].x, lds[0].y, lds[0].z}, sg);
+      double acc = 0.0;
+      for (int jj = 0; jj < ma; ++jj) {
+        const Vtx<float> v1 = lds[jj + 1];
+        acc += (double)walk_step<float, 2, 1>(wk, V3<float>{v1.x, v1.y, v1.z}, sg);
+      }
+      run += acc;
+    }
+  }
+}
+
 // A tile plus its closing vertex, or R small pairs' loops A side by side.
 template <typename Tc, int R>
 size_t lds_bytes(int tile) {
@@ -880,6 +916,14 @@ int segs_supported(bool compute_f64, int segs, bool crossings) {
   if (compute_f64) return segs >= 2 ? 2 : 1;
   if (crossings && segs >= 8) return 8;
   return segs >= 4 ? 4 : (segs >= 2 ? 2 : 1);
+}
+
+hipError_t launch_bh_near(const BhArgs& a, bool in_f64, hipStream_t s) {
+  if (in_f64)
+    bh_near_k<double><<<4096, kWave, 0, s>>>(a);
+  else
+    bh_near_k<float><<<4096, kWave, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,

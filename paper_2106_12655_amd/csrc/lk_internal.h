@@ -180,6 +180,123 @@ __device__ __forceinline__ void finalize_pair(const Outs& o, int32_t p, double v
     check_pair(o, p, ival, f);
 }
 
+// 128-bit two's-complement fixed point with 64 fraction bits, accumulated with
+// 64-bit integer atomics: integer addition is associative, so the pair sum is
+// the same whatever order the work items finish in.  The conversion is exact
+// except for bits below 2^-64, which are dropped by an arithmetic shift (always
+// towards -infinity, so deterministically).  |v| < 2^50 is required.
+__device__ __forceinline__ void to_fixed(double v, unsigned long long& lo, unsigned long long& hi) {
+  lo = 0ull;
+  hi = 0ull;
+  if (v == 0.0) return;
+  int e = 0;
+  const double f = frexp(v, &e);                   // v = f 2^e, 0.5 <= |f| < 1
+  const long long m = (long long)ldexp(f, 53);     // exact: |m| < 2^53
+  const int s = e + 11;                            // v 2^64 = m 2^s
+  if (s > 0) {
+    lo = (unsigned long long)m << s;
+    hi = (unsigned long long)(m >> (64 - s));
+  } else if (s == 0) {
+    lo = (unsigned long long)m;
+    hi = m < 0 ? ~0ull : 0ull;
+  } else if (s > -64) {
+    const long long t = m >> (-s);
+    lo = (unsigned long long)t;
+    hi = t < 0 ? ~0ull : 0ull;
+  } else {
+    lo = m < 0 ? ~0ull : 0ull;
+    hi = lo;
+  }
+}
+
+__device__ __forceinline__ void fixed_add(unsigned long long* acc, double v) {
+  unsigned long long lo, hi;
+  to_fixed(v, lo, hi);
+  if (lo == 0ull && hi == 0ull) return;
+  const unsigned long long old = atomicAdd(&acc[0], lo);
+  const unsigned long long carry = (old + lo < old) ? 1ull : 0ull;
+  atomicAdd(&acc[1], hi + carry);
+}
+
+// 128-bit two's complement -> sign and magnitude -> double (one rounding of
+// the fraction word, one of the sum).
+__device__ __forceinline__ double from_fixed(unsigned long long lo, unsigned long long hi) {
+  const bool neg = (long long)hi < 0;
+  if (neg) {
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0ull ? 1ull : 0ull);
+  }
+  const double mag = (double)hi + (double)lo * 5.421010862427522170e-20;  // 2^-64
+  return neg ? -mag : mag;
+}
+
+// --- Barnes-Hut (Sec. 3.4.4, Alg. 6): lk_bh.hip, and the leaf pairs in lk_ds.hip
+// Trees over consecutive segments: a leaf holds kBhLeaf segments of a loop, a
+// node of level h holds kBhLeaf * kBhArity^h (the last one of a level fewer)
+// and its children are the level h - 1 nodes inside it; a loop's root is its
+// lowest level with a single node.  Node k of level h of loop i sits at slot
+// level_base[h] + (off[i] - off[0]) / span_h + i + k (span_h = kBhLeaf *
+// kBhArity^h), which leaves room for every loop without a prefix sum.
+constexpr int kBhLeaf = 64;
+constexpr int kBhArity = 8;
+constexpr int kBhMaxLevels = 10;
+constexpr int kBhMaxIters = 2 * kBhMaxLevels;
+
+// Box centre and half extents (R = |e|, half the box diagonal), and the
+// moments about the centre: c_M, C_D[p][b], C_Q[p][b][c] (row-major).
+struct BhNode {
+  double c[3], e[3];
+  double M[3], D[9], Q[27];
+};
+
+// One pair of tree nodes of one loop pair: node ka of level ha of loop A
+// (gamma_1) against node kb of level hb of loop B.
+struct BhPair {
+  int32_t p, ka, kb, lev;  // lev = ha | hb << 8
+};
+
+struct BhArgs {
+  const void* xyz;
+  const int64_t* off;
+  const int32_t* pairs;
+  int32_t n_loops;
+  BhNode* nodes;
+  int64_t level_base[kBhMaxLevels];  // first slot of each level
+  int64_t level_cap[kBhMaxLevels];   // slots of each level (a slot beyond fails the pair)
+  int32_t levels;                    // levels built
+  BhPair* list[2];                   // ping-pong node-pair lists
+  BhPair* near;                      // leaf pairs for the direct sum
+  int64_t list_cap, near_cap;
+  int32_t* counts;                   // [kBhMaxIters + 2]: list entries per iteration, then near
+  unsigned long long* acc;           // per-pair fixed point [n_pairs][2]
+  double beta;
+  int32_t order;
+  Outs out;
+};
+
+__device__ __forceinline__ int64_t bh_span(int h) {
+  int64_t s = kBhLeaf;
+  for (int q = 0; q < h; ++q) s *= kBhArity;
+  return s;
+}
+__device__ __forceinline__ int64_t bh_count(int64_t n, int h) {
+  const int64_t s = bh_span(h);
+  return (n + s - 1) / s;
+}
+
+// Tree build (one launch for the leaves, one per level above).
+hipError_t launch_bh_leaves(const BhArgs& a, bool in_f64, hipStream_t s);
+hipError_t launch_bh_level(const BhArgs& a, int level, hipStream_t s);
+// After the planning kernel (validation, flags, zeroed accumulators): push
+// the root pair of every pair that has work.
+hipError_t launch_bh_roots(const BhArgs& a, int64_t n_pairs, hipStream_t s);
+// One breadth-first step: node pairs of list iteration `it`.
+hipError_t launch_bh_expand(const BhArgs& a, int it, hipStream_t s);
+// Eq. 4 over every leaf pair of the near list (FP32 terms, FP64 sums).
+hipError_t launch_bh_near(const BhArgs& a, bool in_f64, hipStream_t s);
+// Round and flag every pair that has work (refit list as in the mixed mode).
+hipError_t launch_bh_finalize(const BhArgs& a, int64_t n_pairs, hipStream_t s);
+
 // --- lk_ds.hip
 // in_f64: input dtype; compute_f64: arithmetic (true = plain FP64 / refit);
 // form (FP32 only): 0 / 2 = own minimax arctangent (phased / inline), 1 = HIP

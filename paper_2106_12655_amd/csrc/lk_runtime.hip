@@ -66,6 +66,9 @@ struct lk_ctx {
   DevBuf loop_flags, minseg2, xi, recs, big_prefix, meta, acc, flags, refit_list;
   DevBuf boxes, vcounts, vprefix;
   DevBuf cc_blk, cc_sup;  // crossing count: projected block and superblock boxes
+  DevBuf bh_nodes, bh_lists, bh_counts;  // Barnes-Hut trees, node-pair lists, counts
+  double bh_beta = 4.0;
+  int bh_order = 2;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
   // graphs
   struct Cached {
@@ -129,8 +132,9 @@ int default_chunk(bool f64) { return f64 ? 2048 : 4096; }
 
 struct Plan {
   bool in_f64;
-  bool mixed;      // FP32 main pass + FP64 refit (MIXED and CROSSINGS)
+  bool mixed;      // FP32 main pass + FP64 refit (MIXED, CROSSINGS, BARNES_HUT)
   bool crossings;  // main pass counts crossings
+  bool bh;         // main pass is the Barnes-Hut traversal
   int tile, chunk, grid, grid64, grid_refit, atan_form;
   int segs, segs64;  // segments of loop B per lane, FP32 and FP64 kernels
   int grid_cc64;     // CROSSINGS: grid of the FP64 crossing count
@@ -216,6 +220,35 @@ lk::CcProj cc_projection(const float* view) {
   return P;
 }
 
+// Barnes-Hut: tree levels, node slots and list capacities for the call's
+// vertex count (read as for the crossing count).  The trees need levels up
+// to the one whose node spans the longest possible loop (the vertex count).
+struct BhLayout {
+  int levels = 1;
+  int64_t base[lk::kBhMaxLevels] = {}, cap[lk::kBhMaxLevels] = {};
+  int64_t nodes = 0, list_cap = 0, near_cap = 0;
+};
+
+BhLayout bh_layout(int64_t v, int32_t n_loops, int64_t n_pairs) {
+  BhLayout Y;
+  int64_t span = lk::kBhLeaf;
+  while (span < v && Y.levels < lk::kBhMaxLevels) {
+    span *= lk::kBhArity;
+    ++Y.levels;
+  }
+  span = lk::kBhLeaf;
+  for (int h = 0; h < Y.levels; ++h) {
+    Y.base[h] = Y.nodes;
+    Y.cap[h] = v / span + n_loops + 1;
+    Y.nodes += Y.cap[h];
+    span *= lk::kBhArity;
+  }
+  const int64_t leaves = v / lk::kBhLeaf + n_loops;
+  Y.list_cap = 8 * leaves + 8 * n_pairs + 65536;
+  Y.near_cap = 32 * leaves + 2 * n_pairs + 65536;
+  return Y;
+}
+
 // Enqueue the whole direct-sum sequence (no graph logic here).
 lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const int64_t* off,
                              int32_t n_loops, const int32_t* pairs, int64_t n_pairs,
@@ -293,13 +326,61 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
                            (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
                            lf, (double*)ctx->minseg2.p, s));
-  LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
-  LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
-  if (timed) LK_HIP(hipEventRecord(ev[0], s));
-  LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
-                           P.mixed ? P.grid : P.grid64, s));
-  if (timed) LK_HIP(hipEventRecord(ev[1], s));
-  LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
+  if (P.bh) {
+    // Barnes-Hut: the plan validates, flags and zeroes (every pair one item);
+    // the trees, the breadth-first traversal and the leaf pairs replace the
+    // direct-sum kernel
+    PlanArgs Mb = M;
+    Mb.chunk = 1 << 24;
+    Mb.bblock = 1 << 30;
+    const int64_t v = ctx->cc_off_key == off && ctx->cc_loops_key == n_loops ? ctx->cc_vertices : 0;
+    const BhLayout Y = bh_layout(v, n_loops, n_pairs);
+    BhArgs H{};
+    H.xyz = xyz;
+    H.off = off;
+    H.pairs = pairs;
+    H.n_loops = n_loops;
+    H.nodes = (BhNode*)ctx->bh_nodes.p;
+    const int64_t node_room = (int64_t)(ctx->bh_nodes.bytes / sizeof(BhNode));
+    for (int h = 0; h < kBhMaxLevels; ++h) {
+      H.level_base[h] = h < Y.levels ? Y.base[h] : 0;
+      // a level that does not fit the buffer (a capture before the vertex
+      // count was read) gets no slots: its pairs fail and are refitted
+      H.level_cap[h] = h < Y.levels && Y.base[h] + Y.cap[h] <= node_room ? Y.cap[h] : 0;
+    }
+    H.levels = Y.levels;
+    BhPair* lists = (BhPair*)ctx->bh_lists.p;
+    const int64_t room = (int64_t)(ctx->bh_lists.bytes / sizeof(BhPair));
+    const bool fits = 2 * Y.list_cap + Y.near_cap <= room;
+    H.list[0] = lists;
+    H.list[1] = lists + (fits ? Y.list_cap : 0);
+    H.near = lists + (fits ? 2 * Y.list_cap : 0);
+    H.list_cap = fits ? Y.list_cap : 0;
+    H.near_cap = fits ? Y.near_cap : 0;
+    H.counts = (int32_t*)ctx->bh_counts.p;
+    H.acc = acc;
+    H.beta = ctx->bh_beta;
+    H.order = ctx->bh_order;
+    H.out = out;
+    LK_HIP(launch_plan(Mb, n_loops, li, A.s, false, s));
+    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
+    if (timed) LK_HIP(hipEventRecord(ev[0], s));
+    LK_HIP(launch_bh_leaves(H, P.in_f64, s));
+    for (int h = 1; h < Y.levels; ++h) LK_HIP(launch_bh_level(H, h, s));
+    LK_HIP(launch_bh_roots(H, n_pairs, s));
+    for (int it = 0; it < 2 * (Y.levels - 1) + 1; ++it) LK_HIP(launch_bh_expand(H, it, s));
+    LK_HIP(launch_bh_near(H, P.in_f64, s));
+    if (timed) LK_HIP(hipEventRecord(ev[1], s));
+    LK_HIP(launch_bh_finalize(H, n_pairs, s));
+  } else {
+    LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
+    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
+    if (timed) LK_HIP(hipEventRecord(ev[0], s));
+    LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
+                             P.mixed ? P.grid : P.grid64, s));
+    if (timed) LK_HIP(hipEventRecord(ev[1], s));
+    LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
+  }
   if (P.mixed) {
     // refit: the FP64 direct sum (MIXED), or the FP64 crossing count
     // (CROSSINGS), which queues what it cannot decide for the FP64 direct sum
@@ -367,6 +448,7 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
   P.in_f64 = in_f64;
   P.mixed = mixed;
   P.crossings = mode == LK_CROSSINGS;
+  P.bh = mode == LK_BARNES_HUT;
   P.atan_form = P.crossings ? kFormCrossings : ctx->opt_atan;
   const int tmax = mixed ? lk::kMaxTileF32 : lk::kMaxTileF64;
   P.tile = ctx->opt_tile ? (ctx->opt_tile < tmax ? ctx->opt_tile : tmax) : default_tile(!mixed);
@@ -404,8 +486,8 @@ lk_status ensure_workspace(lk_ctx* ctx, int32_t n_loops, int64_t n_pairs) {
 // is read from the device (one synchronisation) the first time an offsets
 // array is seen.  Inside a stream capture nothing is read and the boxes keep
 // their size; the kernels never cull through a slot beyond it.
-lk_status cc_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream_t s,
-                     bool can_sync) {
+lk_status read_vertices(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream_t s,
+                        bool can_sync, int64_t* v) {
   if (can_sync && (ctx->cc_off_key != off || ctx->cc_loops_key != n_loops)) {
     int64_t ends[2] = {0, 0};
     LK_HIP(hipMemcpyAsync(&ends[0], off, 8, hipMemcpyDeviceToHost, s));
@@ -415,11 +497,31 @@ lk_status cc_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream
     ctx->cc_loops_key = n_loops;
     ctx->cc_vertices = ends[1] - ends[0] > 0 ? ends[1] - ends[0] : 0;
   }
-  const int64_t v = ctx->cc_off_key == off && ctx->cc_loops_key == n_loops ? ctx->cc_vertices : 0;
+  *v = ctx->cc_off_key == off && ctx->cc_loops_key == n_loops ? ctx->cc_vertices : 0;
+  return LK_OK;
+}
+
+lk_status cc_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream_t s,
+                     bool can_sync) {
+  int64_t v = 0;
   lk_status st;
+  if ((st = read_vertices(ctx, off, n_loops, s, can_sync, &v)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->cc_blk, 16 * (size_t)(v / lk::kCcBlock + n_loops + 1))) != LK_OK)
     return st;
   return ensure(ctx, ctx->cc_sup, 16 * (size_t)(v / lk::kCcSuper + n_loops + 1));
+}
+
+lk_status bh_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, int64_t n_pairs,
+                     hipStream_t s, bool can_sync) {
+  int64_t v = 0;
+  lk_status st;
+  if ((st = read_vertices(ctx, off, n_loops, s, can_sync, &v)) != LK_OK) return st;
+  const BhLayout Y = bh_layout(v, n_loops, n_pairs);
+  if ((st = ensure(ctx, ctx->bh_nodes, sizeof(lk::BhNode) * (size_t)Y.nodes)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->bh_lists,
+                   sizeof(lk::BhPair) * (size_t)(2 * Y.list_cap + Y.near_cap))) != LK_OK)
+    return st;
+  return ensure(ctx, ctx->bh_counts, 4 * (size_t)(lk::kBhMaxIters + 2));
 }
 
 bool check_dtype(int d) { return d == LK_F32 || d == LK_F64; }
@@ -469,7 +571,8 @@ void lk_destroy(lk_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->loop_flags, &ctx->minseg2, &ctx->xi,      &ctx->recs,
                     &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
                     &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix,
-                    &ctx->cc_blk,     &ctx->cc_sup};
+                    &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
+                    &ctx->bh_counts};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -539,6 +642,15 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "crossing culling must be 0 or 1");
       ctx->cc_cull = v != 0;
       break;
+    case LK_OPT_BH_BETA_MILLI:
+      if (v < 500 || v > 1000000)
+        return ctx->fail(LK_EINVAL, "Barnes-Hut beta (x 1000) must be in [500, 1e6]");
+      ctx->bh_beta = (double)v * 1e-3;
+      break;
+    case LK_OPT_BH_ORDER:
+      if (v != 1 && v != 2) return ctx->fail(LK_EINVAL, "Barnes-Hut order must be 1 or 2");
+      ctx->bh_order = (int)v;
+      break;
     case LK_OPT_SEGS_PER_LANE_F64:
       if (v != 0 && v != 1 && v != 2)
         return ctx->fail(LK_EINVAL, "FP64 segments per lane must be 0, 1 or 2");
@@ -588,7 +700,7 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   if (!ctx) return LK_EINVAL;
   ctx->err.clear();
   if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
-  if (mode != LK_PLAIN_F64 && mode != LK_MIXED && mode != LK_CROSSINGS)
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED && mode != LK_CROSSINGS && mode != LK_BARNES_HUT)
     return ctx->fail(LK_EINVAL, "unknown mode %d", mode);
   if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
   if (n_pairs < 0) return ctx->fail(LK_EINVAL, "n_pairs must be >= 0");
@@ -608,11 +720,12 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   const bool mixed = mode != LK_PLAIN_F64;
   const Plan P = make_plan(ctx, in_f64, mode);
   if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
-  if (P.crossings) {
+  if (P.crossings || P.bh) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (s && hipStreamIsCapturing(s, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
-    if ((st = cc_prepare(ctx, off, n_loops, s, cs == hipStreamCaptureStatusNone)) != LK_OK)
-      return st;
+    const bool can_sync = cs == hipStreamCaptureStatusNone;
+    if (P.crossings && (st = cc_prepare(ctx, off, n_loops, s, can_sync)) != LK_OK) return st;
+    if (P.bh && (st = bh_prepare(ctx, off, n_loops, n_pairs, s, can_sync)) != LK_OK) return st;
   }
   if (!flags) {
     if ((st = ensure(ctx, ctx->flags, 4 * (size_t)n_pairs)) != LK_OK) return st;

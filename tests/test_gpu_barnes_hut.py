@@ -1,0 +1,121 @@
+"""Barnes-Hut on the GPU (mode "barnes_hut", Sec. 3.4.4, Alg. 6) against the oracle.
+
+The GPU builds the same trees as the oracle's lko_bh_pair with leaf 64 and
+arity 8 (runs of consecutive segments, box centres, the same far-field test),
+so for the same beta and order the two evaluate the same node pairs: the
+values agree to the FP32 error of the leaf pairs (BH_TOL), and the integers
+equal the FP64 direct sum's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12655_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BH_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def bctx():
+    import paper_2106_12655_amd as lk
+    c = lk.Context(0)
+    yield c
+    c.close()
+
+
+def _run(c, ls, pairs, mode="barnes_hut"):
+    import torch
+    xyz = torch.from_numpy(np.ascontiguousarray(ls.xyz)).cuda()
+    off = torch.from_numpy(np.ascontiguousarray(ls.offsets)).cuda()
+    pr = torch.from_numpy(np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))).cuda()
+    real, lk, flags = c.direct_sum(xyz, off, pr, mode)
+    torch.cuda.synchronize()
+    return real.cpu().numpy(), lk.cpu().numpy(), flags.cpu().numpy().view(np.uint32)
+
+
+def _set(c, beta, order):
+    import paper_2106_12655_amd as lk
+    c.set_option(lk._lib.OPT_BH_BETA_MILLI, int(round(beta * 1000)))
+    c.set_option(lk._lib.OPT_BH_ORDER, order)
+
+
+def _cases():
+    ls_long = I.long_pairs(7, n_pairs=2, n_min=20000, n_max=40000)
+    return [(I.hopf(64), [[0, 1], [1, 0]], "hopf"),
+            (I.torus_link(2, 3, 400), [[0, 1], [1, 0]], "torus(2,3)"),
+            (I.torus_link(3, -2, 2000), [[0, 1]], "torus(3,-2) 2000"),
+            (ls_long, ls_long.pairs, "long pairs 20k-40k")]
+
+
+@pytest.mark.parametrize("beta,order", [(2.0, 2), (4.0, 2), (4.0, 1), (8.0, 2)])
+def test_matches_oracle_barnes_hut(bctx, beta, order):
+    try:
+        _set(bctx, beta, order)
+        for ls, pairs, label in _cases():
+            pairs = np.asarray(pairs, np.int32)
+            real, lk_int, flags = _run(bctx, ls, pairs)
+            ov = np.array([oracle.bh_pair(ls.loop(i), ls.loop(j), beta, order, 64, 8)[0]
+                           for i, j in pairs])
+            olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)[1]
+            err = np.abs(real - ov)
+            print("beta %g order %d %s: max |gpu - oracle BH| %.2e, |BH - integer| %.2e, flags %s"
+                  % (beta, order, label, err.max(), np.abs(ov - olk).max(), flags.tolist()),
+                  flush=True)
+            refit = (flags & 1) != 0
+            assert err[~refit].max(initial=0.0) <= BH_TOL, label
+            assert np.array_equal(lk_int, olk), label
+    finally:
+        _set(bctx, 4.0, 2)
+
+
+def test_infinite_beta_is_the_direct_sum(bctx):
+    """With a huge beta no node pair is far: Barnes-Hut sums every leaf pair,
+    which is the mixed direct sum up to FP32 rounding."""
+    ls = I.torus_link(2, 3, 1500)
+    pairs = np.array([[0, 1]], np.int32)
+    try:
+        _set(bctx, 1000.0, 2)
+        real, lk_int, flags = _run(bctx, ls, pairs)
+    finally:
+        _set(bctx, 4.0, 2)
+    ex = oracle.pair(ls.loop(0), ls.loop(1))
+    assert abs(real[0] - ex) < 1e-5 and lk_int[0] == -6
+
+
+def test_workloads_integers_and_check(bctx):
+    """Small chainmail, knit rows and the ring grid: every integer equals the
+    FP64 oracle; the fused check counts no mismatch; graph replays agree."""
+    import torch
+    for ls in (I.ring_grid(0), I.chainmail(5, rows=10, cols=12), I.knit(4, n_loops=16, cp_max=48)):
+        pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+        olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)[1]
+        xyz = torch.from_numpy(ls.xyz).cuda()
+        off = torch.from_numpy(ls.offsets).cuda()
+        pr = torch.from_numpy(pairs).cuda()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            outs = [[t.cpu().numpy() for t in bctx.direct_sum(xyz, off, pr, "barnes_hut")]
+                    for _ in range(3)]
+            real, lkv, fl, nm = bctx.direct_sum_check(xyz, off, pr, torch.from_numpy(olk).cuda(),
+                                                      False, "barnes_hut")
+        torch.cuda.synchronize()
+        for o in outs[1:]:
+            assert all(np.array_equal(a, b) for a, b in zip(o, outs[0])), ls.name
+        assert np.array_equal(outs[0][1], olk), ls.name
+        assert int(nm.item()) == 0, ls.name
+        print("%s: pairs %d, refits %d" % (ls.name, len(pairs), int((outs[0][2] & 1).sum())),
+              flush=True)
+
+
+def test_options_and_bad_pairs(bctx):
+    import paper_2106_12655_amd as lk
+    for key, bad in ((lk._lib.OPT_BH_BETA_MILLI, 100), (lk._lib.OPT_BH_ORDER, 3)):
+        with pytest.raises(lk.LkError):
+            bctx.set_option(key, bad)
+    ls = I.hopf(64)
+    real, lk_int, flags = _run(bctx, ls, np.array([[0, 0], [0, 5], [1, 0]], np.int32))
+    assert lk_int[0] == lk.INT_INVALID and flags[0] & lk.FLAG_BADPAIR
+    assert lk_int[1] == lk.INT_INVALID and flags[1] & lk.FLAG_BADPAIR
+    assert lk_int[2] == -1
