@@ -24,11 +24,11 @@ and reports throughput beside p50/p99 latency.
 Prints ONE JSON line.  Options:
   --steps K --warmup W   timed / untimed steps (default 20 / 3)
   --config NAME          ring_grid | chainmail | knit | long_pairs | serving
-  --mode mixed|plain|crossings
+  --mode mixed|plain|crossings|barnes_hut
                          mode of the headline value (default mixed); with mixed,
-                         plain FP64 and the crossing count (Alg. 4) are timed on
-                         the same input and reported beside it
-  --no-plain, --no-crossings   skip those companion legs
+                         plain FP64, the crossing count (Alg. 4) and Barnes-Hut
+                         (Alg. 6) are timed on the same input and reported beside it
+  --no-plain, --no-crossings, --no-bh   skip those companion legs
   --no-cpu-baseline      skip the oracle leg
   --no-tune              keep the default kernel configuration
   --gpus N               only N = 1 is supported (one GPU per process)
@@ -105,12 +105,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="chainmail", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="mixed", choices=["mixed", "plain", "crossings"])
+    ap.add_argument("--mode", default="mixed", choices=["mixed", "plain", "crossings", "barnes_hut"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-FP64 companion run")
     ap.add_argument("--no-crossings", action="store_true",
                     help="skip the crossing-count companion run")
+    ap.add_argument("--no-bh", action="store_true", help="skip the Barnes-Hut companion run")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
@@ -237,6 +238,9 @@ def main():
                                                      args.tune_cache)
         other = time_mode(ctx, xyz, off, pairs, "plain", max(args.steps // 2, 1),
                           min(args.warmup, 1), lk)
+    bh = None
+    if not args.no_bh and args.mode == "mixed":
+        bh = time_mode(ctx, xyz, off, pairs, "barnes_hut", args.steps, args.warmup, lk)
     cc, tuned_cc = None, None
     if not args.no_crossings and args.mode == "mixed":
         tuned_cc = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "crossings", lk,
@@ -253,7 +257,7 @@ def main():
     value = T / (res["ms_per_step"] * 1e-3)
     fp64 = args.mode == "plain"
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
-    fpt = FLOP_PER_TERM_CC if args.mode == "crossings" else FLOP_PER_TERM
+    fpt = FLOP_PER_TERM_CC if args.mode == "crossings" else FLOP_PER_TERM  # (BH: covered pairs)
     achieved = fpt * T / (res["kernel_ms"] * 1e-3) / 1e12 if res["kernel_ms"] > 0 else 0.0
     line = {
         "metric": "segment-pair evals/s",
@@ -323,6 +327,19 @@ def main():
                 "flop_per_term": FLOP_PER_TERM_CC,
                 "int_mismatch_vs_culled": int(np.sum(ex["lk"] != cc["lk"])),
             }
+    if bh is not None:
+        line["barnes_hut"] = {
+            "value": T / (bh["ms_per_step"] * 1e-3),
+            "ms_per_step": bh["ms_per_step"],
+            "eager_ms_per_step": bh["eager_ms_per_step"],
+            "kernel_ms": bh["kernel_ms"],
+            "refit_kernel_ms": bh["refit_kernel_ms"],
+            "refits": bh["refits"],
+            "beta": 4.0, "order": 2,
+            "max_abs_diff_vs_mixed": float(np.max(np.abs(bh["real"] - res["real"]))) if len(pr) else 0.0,
+            "int_mismatch_vs_mixed": int(np.sum(bh["lk"] != res["lk"])),
+            "int_mismatch_vs_construction": int(np.sum(bh["lk"] != exp)),
+        }
     if not args.no_cpu_baseline:
         line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)

@@ -228,6 +228,10 @@ typedef struct {
                             (atan_form 3: the crossing count) */
   int64_t refits_direct_sum; /* CROSSINGS: pairs the FP64 crossing count could not decide
                                 either, computed by the FP64 direct sum */
+  int64_t bh_list_peak;      /* BARNES_HUT: most node pairs in one traversal step */
+  int64_t bh_near_pairs;     /* BARNES_HUT: leaf pairs summed directly */
+  int64_t bh_list_cap;       /* BARNES_HUT: capacity of a step's list (pairs beyond it are
+                                refitted) */
 } lk_stats;
 
 /* ------------------------------------------------------------ autotuner */

@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("timed_calls", ctypes.c_int32), ("graph_replayed", ctypes.c_int32), ("tile_a", ctypes.c_int32),
                 ("chunk_a", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32),
-                ("refits_direct_sum", ctypes.c_int64)]
+                ("refits_direct_sum", ctypes.c_int64), ("bh_list_peak", ctypes.c_int64),
+                ("bh_near_pairs", ctypes.c_int64), ("bh_list_cap", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):

@@ -257,7 +257,47 @@ __device__ double far_field(const BhNode& u, const BhNode& v, int order) {
 }
 
 // ------------------------------------------------------------ traversal
-// One breadth-first step over the node pairs of iteration `it`.
+// Wave-collective append of `n` entries per lane to a list: returns the
+// lane's first position (one atomic per wave).
+__device__ __forceinline__ int64_t wave_reserve(int32_t* count, int n) {
+  const int lane = threadIdx.x & 63;
+  int32_t x = n;  // inclusive scan
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  const int32_t total = __shfl(x, 63);
+  int32_t b0 = 0;
+  if (total > 0 && lane == 0) b0 = atomicAdd(count, total);
+  b0 = __shfl(b0, 0);
+  return (int64_t)b0 + x - n;
+}
+
+// Node (level h, index k) of loop `loop`: its slot, or -1 beyond the buffer.
+__device__ __forceinline__ int64_t checked_slot(const BhArgs& A, int32_t loop, int h, int64_t k) {
+  const int64_t s = node_slot(A, loop, h, k);
+  return s - A.level_base[h] < A.level_cap[h] ? s : -1;
+}
+
+__device__ __forceinline__ double node_radius(const BhNode& n) {
+  return sqrt(n.e[0] * n.e[0] + n.e[1] * n.e[1] + n.e[2] * n.e[2]);
+}
+
+__device__ __forceinline__ bool is_far(const BhArgs& A, const BhNode& u, const BhNode& v) {
+  double d2 = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    const double dq = v.c[q] - u.c[q];
+    d2 += dq * dq;
+  }
+  return sqrt(d2) > A.beta * (node_radius(u) + node_radius(v));
+}
+
+// One breadth-first step over the node pairs of iteration `it`.  A pair that
+// is far is evaluated, a pair of two leaves goes to the leaf list, any other
+// is split (the node with children and the larger radius); its child pairs
+// are classified at once, so the next step's list holds only pairs that must
+// be split again.
 __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
   const int lane = threadIdx.x & 63;
   const BhPair* in = A.list[it & 1];
@@ -270,50 +310,63 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
   for (int64_t base = (int64_t)blockIdx.x * 256; base < n_in; base += stride) {
     const int64_t e = base + threadIdx.x;
     const bool has = e < n_in;
-    BhPair w = has ? in[e] : BhPair{-1, 0, 0, 0};
+    const BhPair w = has ? in[e] : BhPair{-1, 0, 0, 0};
     double val = 0.0;
-    bool near = false, fail = false;
-    int nch = 0, split_a = 0, hc = 0;
+    bool fail = false;
+    // classification of the pair itself (roots arrive unclassified), then of
+    // its children: bit c of near_m / next_m marks child c for that list
+    int self = 0;  // 0 none, 1 near, 2 split
+    unsigned near_m = 0u, next_m = 0u;
+    int split_a = 0, hc = 0;
     int64_t cbase = 0;
     if (has) {
       const int ha = w.lev & 255, hb = w.lev >> 8;
       const int32_t i = A.pairs[2 * (int64_t)w.p], j = A.pairs[2 * (int64_t)w.p + 1];
-      const int64_t sa = node_slot(A, i, ha, w.ka), sb = node_slot(A, j, hb, w.kb);
-      if (sa - A.level_base[ha] >= A.level_cap[ha] || sb - A.level_base[hb] >= A.level_cap[hb]) {
+      const int64_t sa = checked_slot(A, i, ha, w.ka), sb = checked_slot(A, j, hb, w.kb);
+      if (sa < 0 || sb < 0) {
         fail = true;
       } else {
         const BhNode& u = A.nodes[sa];
         const BhNode& v = A.nodes[sb];
-        double d2 = 0.0, ra2 = 0.0, rb2 = 0.0;
-        for (int q = 0; q < 3; ++q) {
-          const double dq = v.c[q] - u.c[q];
-          d2 += dq * dq;
-          ra2 += u.e[q] * u.e[q];
-          rb2 += v.e[q] * v.e[q];
-        }
-        const double ra = sqrt(ra2), rb = sqrt(rb2);
-        if (sqrt(d2) > A.beta * (ra + rb)) {
+        if (is_far(A, u, v)) {
           val = far_field(u, v, A.order);
         } else if (ha == 0 && hb == 0) {
-          near = true;
+          self = 1;
         } else {
-          split_a = ha > 0 && (hb == 0 || ra > rb);
-          const int64_t n = split_a ? A.off[i + 1] - A.off[i] : A.off[j + 1] - A.off[j];
+          self = 2;
+          split_a = ha > 0 && (hb == 0 || node_radius(u) > node_radius(v));
+          const int32_t loop = split_a ? i : j;
+          const int64_t n = A.off[loop + 1] - A.off[loop];
           hc = (split_a ? ha : hb) - 1;
           const int64_t cnt = bh_count(n, hc);
           cbase = (int64_t)(split_a ? w.ka : w.kb) * kBhArity;
           const int64_t c1 = (cbase + kBhArity) < cnt ? cbase + kBhArity : cnt;
-          nch = (int)(c1 - cbase);
+          for (int c = 0; c < (int)(c1 - cbase); ++c) {
+            const int64_t sc = checked_slot(A, loop, hc, cbase + c);
+            if (sc < 0) {
+              fail = true;
+              break;
+            }
+            const BhNode& ch = A.nodes[sc];
+            const bool far = split_a ? is_far(A, ch, v) : is_far(A, u, ch);
+            if (far) {
+              val += split_a ? far_field(ch, v, A.order) : far_field(u, ch, A.order);
+            } else if (hc == 0 && (split_a ? hb : ha) == 0) {
+              near_m |= 1u << c;
+            } else {
+              next_m |= 1u << c;
+            }
+          }
         }
       }
     }
-    if (fail) atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+    if (fail) atomicOr(&A.out.flags[w.p], kFlagNonfinite);  // refitted
     // far-field values: one fixed-point add per pair present in the wave
-    unsigned long long rem = __ballot(val != 0.0);
+    unsigned long long rem = __ballot(val != 0.0 && !fail);
     while (rem) {
       const int leader = __ffsll((long long)rem) - 1;
       const int32_t pl = __shfl(w.p, leader);
-      const bool mine = val != 0.0 && w.p == pl;
+      const bool mine = val != 0.0 && !fail && w.p == pl;
       const unsigned long long m = __ballot(mine);
       const double sum = wave_sum(mine ? val : 0.0);
       if (lane == leader) {
@@ -324,56 +377,54 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
       }
       rem &= ~m;
     }
+    if (fail) {
+      self = 0;
+      near_m = next_m = 0u;
+    }
     // leaf pairs to the direct sum
-    {
-      const unsigned long long m = __ballot(near);
-      int32_t nb = 0;
-      const int leader = m ? __ffsll((long long)m) - 1 : 0;
-      if (m && lane == leader) nb = atomicAdd(n_near, (int32_t)__popcll(m));
-      nb = __shfl(nb, leader);
-      const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-      if (near) {
-        const int64_t at = (int64_t)nb + __popcll(m & below);
-        if (at < A.near_cap)
-          A.near[at] = w;
-        else
-          atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+    const int n_near_me = (self == 1 ? 1 : 0) + __popc(near_m);
+    int64_t at = wave_reserve(n_near, n_near_me);
+    bool over = false;
+    if (n_near_me > 0) {
+      const int ha = w.lev & 255, hb = w.lev >> 8;
+      if (self == 1) {
+        if (at < A.near_cap) A.near[at] = w; else over = true;
+        ++at;
       }
-    }
-    // child pairs to the next step
-    {
-      int32_t x = nch;  // inclusive scan of the child counts
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-      }
-      const int32_t total = __shfl(x, 63);
-      int32_t b0 = 0;
-      if (total > 0 && lane == 0) b0 = atomicAdd(n_out, total);
-      b0 = __shfl(b0, 0);
-      if (nch > 0) {
-        const int ha = w.lev & 255, hb = w.lev >> 8;
-        int64_t at = (int64_t)b0 + x - nch;
-        bool over = false;
-        for (int c = 0; c < nch; ++c, ++at) {
-          if (at >= A.list_cap) {
-            over = true;
-            break;
-          }
-          BhPair ch = w;
-          if (split_a) {
-            ch.ka = (int32_t)(cbase + c);
-            ch.lev = hc | (hb << 8);
-          } else {
-            ch.kb = (int32_t)(cbase + c);
-            ch.lev = ha | (hc << 8);
-          }
-          out[at] = ch;
+      for (int c = 0; c < kBhArity; ++c) {
+        if (!(near_m >> c & 1u)) continue;
+        BhPair ch = w;
+        if (split_a) {
+          ch.ka = (int32_t)(cbase + c);
+          ch.lev = hc | (hb << 8);
+        } else {
+          ch.kb = (int32_t)(cbase + c);
+          ch.lev = ha | (hc << 8);
         }
-        if (over) atomicOr(&A.out.flags[w.p], kFlagNonfinite);
+        if (at < A.near_cap) A.near[at] = ch; else over = true;
+        ++at;
       }
     }
+    // pairs to split again, for the next step
+    const int n_next_me = __popc(next_m);
+    at = wave_reserve(n_out, n_next_me);
+    if (n_next_me > 0) {
+      const int ha = w.lev & 255, hb = w.lev >> 8;
+      for (int c = 0; c < kBhArity; ++c) {
+        if (!(next_m >> c & 1u)) continue;
+        BhPair ch = w;
+        if (split_a) {
+          ch.ka = (int32_t)(cbase + c);
+          ch.lev = hc | (hb << 8);
+        } else {
+          ch.kb = (int32_t)(cbase + c);
+          ch.lev = ha | (hc << 8);
+        }
+        if (at < A.list_cap) out[at] = ch; else over = true;
+        ++at;
+      }
+    }
+    if (over) atomicOr(&A.out.flags[w.p], kFlagNonfinite);  // a list was full: refitted
   }
 }
 

@@ -84,6 +84,8 @@ struct lk_ctx {
   hipStream_t last_stream = nullptr;
   bool last_mixed = false;
   bool last_crossings = false;
+  bool last_bh = false;
+  int64_t last_bh_list_cap = 0;
   bool last_timed = false;
 
   lk_status fail(lk_status st, const char* fmt, ...) {
@@ -243,9 +245,13 @@ BhLayout bh_layout(int64_t v, int32_t n_loops, int64_t n_pairs) {
     Y.nodes += Y.cap[h];
     span *= lk::kBhArity;
   }
+  // generous (measured: a step of the long-loop and knit workloads holds up
+  // to 2 and 12 node pairs per leaf, the leaf list up to 330 per leaf of the
+  // knit workload at beta 8); a pair whose entries do not fit is refitted,
+  // not lost
   const int64_t leaves = v / lk::kBhLeaf + n_loops;
-  Y.list_cap = 8 * leaves + 8 * n_pairs + 65536;
-  Y.near_cap = 32 * leaves + 2 * n_pairs + 65536;
+  Y.list_cap = 32 * leaves + 8 * n_pairs + 65536;
+  Y.near_cap = 512 * leaves + 4 * n_pairs + 65536;
   return Y;
 }
 
@@ -356,6 +362,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     H.list[1] = lists + (fits ? Y.list_cap : 0);
     H.near = lists + (fits ? 2 * Y.list_cap : 0);
     H.list_cap = fits ? Y.list_cap : 0;
+    ctx->last_bh_list_cap = H.list_cap;
     H.near_cap = fits ? Y.near_cap : 0;
     H.counts = (int32_t*)ctx->bh_counts.p;
     H.acc = acc;
@@ -740,6 +747,7 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   ctx->last_stream = s;
   ctx->last_mixed = mixed;
   ctx->last_crossings = P.crossings;
+  ctx->last_bh = P.bh;
   ctx->last_timed = false;
 
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -842,6 +850,15 @@ lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
       LK_HIP(hipMemcpy(&rn2, meta_at<int32_t>(ctx, kMetaRefitN2), 4, hipMemcpyDeviceToHost));
     ctx->stats.refits = rn;
     ctx->stats.refits_direct_sum = rn2;
+    if (ctx->last_bh && ctx->bh_counts.p) {
+      int32_t c[lk::kBhMaxIters + 2];
+      LK_HIP(hipMemcpy(c, ctx->bh_counts.p, sizeof(c), hipMemcpyDeviceToHost));
+      int64_t peak = 0;
+      for (int k = 0; k <= lk::kBhMaxIters; ++k) peak = std::max<int64_t>(peak, c[k]);
+      ctx->stats.bh_list_peak = peak;
+      ctx->stats.bh_near_pairs = c[lk::kBhMaxIters + 1];
+      ctx->stats.bh_list_cap = ctx->last_bh_list_cap;
+    }
   }
   if (ctx->timing && ctx->ring_count > 0) {
     LK_HIP(hipStreamSynchronize(ctx->last_stream));
