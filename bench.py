@@ -230,7 +230,9 @@ def main():
     T = int(np.sum(sizes[pr[:, 0]].astype(np.int64) * sizes[pr[:, 1]]))
     exp = ls.expected_for(pr)
 
-    tuned = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, args.mode, lk, args.tune_cache)
+    # (Barnes-Hut has no tuned launch parameters)
+    tuned = None if args.no_tune or args.mode == "barnes_hut" else tune(
+        ctx, ls, xyz, off, pairs, args.mode, lk, args.tune_cache)
     res = time_mode(ctx, xyz, off, pairs, args.mode, args.steps, args.warmup, lk)
     other, tuned_plain = None, None
     if not args.no_plain and args.mode == "mixed":

@@ -58,7 +58,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One wavefront per leaf slot: lane t holds segment t of the leaf.  The box
 // covers the leaf's vertices (with the one closing its last segment); a
 // segment with vector s and midpoint offset d from the centre adds s, s d^T
-// and s (x) d (x) d + s (x) s (x) s / 12 (its exact moments).
+// and s (x) d (x) d + s (x) s (x) s / 12 (its exact moments).  The same pass
+// validates the loops in parallel over their leaves (non-finite coordinates,
+// shortest squared segment), folding into the per-loop entries with atomics
+// (a minimum of non-negative doubles is a minimum of their bit patterns).
 template <typename Tin>
 __global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
   if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 2) A.counts[threadIdx.x] = 0;
@@ -84,6 +87,25 @@ __global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
         x1[q] = (double)X[3 * (oi + v1) + q];
         lo[q] = fmin(x0[q], x1[q]);
         hi[q] = fmax(x0[q], x1[q]);
+      }
+    }
+    {
+      uint32_t f = 0u;
+      double mn = INFINITY;
+      if (lane < m) {
+        if (!isfinite(x0[0]) || !isfinite(x0[1]) || !isfinite(x0[2])) f = kFlagNonfinite | kFlagBadloop;
+        const double dx = x1[0] - x0[0], dy = x1[1] - x0[1], dz = x1[2] - x0[2];
+        mn = dx * dx + dy * dy + dz * dz;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        f |= (uint32_t)__shfl_xor((int)f, o);
+        mn = fmin(mn, __shfl_xor(mn, o));
+      }
+      if (lane == 0) {
+        if (f) atomicOr(&A.lf[i], f);
+        if (mn < INFINITY)
+          atomicMin(reinterpret_cast<unsigned long long*>(&A.minseg2[i]),
+                    (unsigned long long)__double_as_longlong(mn));
       }
     }
     for (int q = 0; q < 3; ++q)

@@ -775,37 +775,30 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
 }
 
 // Leaf pairs of the Barnes-Hut traversal (Alg. 6, both nodes leaves): Eq. 4
-// over their kBhLeaf x kBhLeaf segment pairs with the walk above (one B
-// segment per lane, the A leaf's vertices in LDS; FP32 terms, FP64 sums).  A
-// wave takes 32 consecutive entries of the list and adds one sum per run of
-// entries of the same pair into its fixed-point accumulator.
+// over their kBhLeaf x kBhLeaf segment pairs with the walk above.  Like the
+// packed small pairs of the direct sum, a wave takes four leaf pairs at a
+// time, 16 lanes each: a lane holds 4 consecutive segments of the B leaf, the
+// A leaf's vertices are in LDS (FP32 terms, FP64 sums).  A wave works through
+// 32 consecutive entries of the list and adds one sum per run of entries of
+// the same pair into its fixed-point accumulator.
 template <typename Tin>
 __global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
-  __shared__ Vtx<float> lds[kBhLeaf + 1];
-  const int lane = threadIdx.x;
+  constexpr int K = 4, S = kWave / K, R = 4;  // S * R == kBhLeaf
+  static_assert(S * R == kBhLeaf, "a segment of S lanes covers one leaf");
+  __shared__ Vtx<float> lds[K][kBhLeaf + 1];
+  const int lane = threadIdx.x, seg = lane / S, sl = lane - seg * S;
   const Tin* X = static_cast<const Tin*>(A.xyz);
   const int64_t cnt = A.counts[kBhMaxIters + 1];
   const int64_t n = cnt < A.near_cap ? cnt : A.near_cap;
   constexpr int kChunk = 32;
   for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < n; c0 += (int64_t)gridDim.x * kChunk) {
     const int64_t c1 = (c0 + kChunk) < n ? c0 + kChunk : n;
-    double run = 0.0;
+    double run = 0.0;  // uniform over the wave
     int32_t pr = -1;
-    for (int64_t e = c0; e <= c1; ++e) {
-      const int32_t pe = e < c1 ? A.near[e].p : -1;
-      if (pe != pr && pr >= 0) {
-        const double v = wave_sum_d(run) * kInvTwoPi;
-        if (lane == 0) {
-          if (fabs(v) < 1.0e14)
-            fixed_add(&A.acc[2 * (int64_t)pr], v);
-          else
-            atomicOr(&A.out.flags[pr], kFlagNonfinite);
-        }
-        run = 0.0;
-      }
-      if (e == c1) break;
-      pr = pe;
-      const BhPair w = A.near[e];
+    for (int64_t e0 = c0; e0 < c1; e0 += K) {
+      const int64_t e = e0 + seg;
+      const bool has = e < c1;
+      const BhPair w = A.near[has ? e : e0];
       const int32_t i = A.pairs[2 * (int64_t)w.p], j = A.pairs[2 * (int64_t)w.p + 1];
       const int64_t oa = A.off[i], na = A.off[i + 1] - oa;
       const int64_t ob = A.off[j], nb = A.off[j + 1] - ob;
@@ -813,31 +806,69 @@ __global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
       const int ma = (int)((na - a0) < kBhLeaf ? (na - a0) : kBhLeaf);
       const int mb = (int)((nb - b0) < kBhLeaf ? (nb - b0) : kBhLeaf);
       __syncthreads();
-      for (int t = lane; t <= ma; t += kWave) {
+      for (int t = sl; t <= ma; t += S) {
         int64_t idx = a0 + t;
         if (idx >= na) idx -= na;  // closing vertex of the loop
         const V3<float> x = load_vertex<float>(X, oa + idx);
-        lds[t] = Vtx<float>{x.x, x.y, x.z, 0.0f};
+        lds[seg][t] = Vtx<float>{x.x, x.y, x.z, 0.0f};
       }
-      Segs<float, 1> sg;
+      Segs<float, R> sg;
       {
-        const int64_t ib = b0 + (lane < mb ? lane : mb - 1);
-        const int64_t ib1 = ib + 1 < nb ? ib + 1 : 0;
-        sg.k[0] = load_vertex<float>(X, ob + ib);
-        sg.k[1] = load_vertex<float>(X, ob + ib1);
-        sg.s[0] = sg.k[1] - sg.k[0];
-        sg.m[0] = V3<float>{0.0f, 0.0f, 0.0f};
-        sg.valid[0] = lane < mb;
+        const int first = sl * R;
+        V3<float> kv[R + 1];
+#pragma unroll
+        for (int r = 0; r <= R; ++r) {
+          int64_t ib = b0 + (first + r < mb ? first + r : mb);  // vertex b0 + mb closes the leaf
+          if (ib >= nb) ib -= nb;
+          kv[r] = load_vertex<float>(X, ob + ib);
+        }
+#pragma unroll
+        for (int r = 0; r <= R; ++r) sg.k[r] = kv[r];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          sg.s[r] = sg.k[r + 1] - sg.k[r];
+          sg.m[r] = cross(sg.s[r], sg.k[r] - sg.k[0]);
+          sg.valid[r] = first + r < mb;
+        }
       }
       __syncthreads();
-      Walk<float, 1> wk;
-      walk_init(wk, V3<float>{lds[0].x, lds[0].y, lds[0].z}, sg);
       double acc = 0.0;
-      for (int jj = 0; jj < ma; ++jj) {
-        const Vtx<float> v1 = lds[jj + 1];
-        acc += (double)walk_step<float, 2, 1>(wk, V3<float>{v1.x, v1.y, v1.z}, sg);
+      if (has) {
+        Walk<float, R> wk;
+        walk_init(wk, V3<float>{lds[seg][0].x, lds[seg][0].y, lds[seg][0].z}, sg);
+        for (int jj = 0; jj < ma; ++jj) {
+          const Vtx<float> v1 = lds[seg][jj + 1];
+          acc += (double)walk_step<float, 2, R>(wk, V3<float>{v1.x, v1.y, v1.z}, sg);
+        }
       }
-      run += acc;
+#pragma unroll
+      for (int o = S / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      // the K entries in order: extend the run or flush it (uniform logic)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        if (e0 + q >= c1) break;
+        const int32_t pq = __shfl(w.p, q * S);
+        const double vq = __shfl(acc, q * S);
+        if (pq != pr) {
+          if (pr >= 0 && lane == 0) {
+            const double v = run * kInvTwoPi;
+            if (fabs(v) < 1.0e14)
+              fixed_add(&A.acc[2 * (int64_t)pr], v);
+            else
+              atomicOr(&A.out.flags[pr], kFlagNonfinite);
+          }
+          pr = pq;
+          run = 0.0;
+        }
+        run += vq;
+      }
+    }
+    if (pr >= 0 && lane == 0) {
+      const double v = run * kInvTwoPi;
+      if (fabs(v) < 1.0e14)
+        fixed_add(&A.acc[2 * (int64_t)pr], v);
+      else
+        atomicOr(&A.out.flags[pr], kFlagNonfinite);
     }
   }
 }

@@ -269,6 +269,8 @@ struct BhArgs {
   int64_t list_cap, near_cap;
   int32_t* counts;                   // [kBhMaxIters + 2]: list entries per iteration, then near
   unsigned long long* acc;           // per-pair fixed point [n_pairs][2]
+  uint32_t* lf;                      // per-loop validation, folded in by the leaf kernel
+  double* minseg2;                   //   (the preparation kernel only initialises it)
   double beta;
   int32_t order;
   Outs out;

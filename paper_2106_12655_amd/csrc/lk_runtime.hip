@@ -274,7 +274,8 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   li.part = xi;
   // the vertex count is known (and the boxes sized for it) only in CROSSINGS
   const bool cull = P.crossings && ctx->cc_cull;
-  li.n_part = prep_blocks(n_loops, cull && ctx->cc_off_key == off && ctx->cc_loops_key == n_loops
+  li.n_part = prep_blocks(n_loops, (cull || P.bh) && ctx->cc_off_key == off &&
+                                           ctx->cc_loops_key == n_loops
                                        ? ctx->cc_vertices
                                        : 0);
   li.eps = P.in_f64 ? 2.220446049250313080847e-16 : 1.1920928955078125e-07;
@@ -326,8 +327,10 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   A.off = off;
   A.out = out;
 
+  // the crossing count's box kernel and the Barnes-Hut leaf kernel validate
+  // the loops in parallel; the preparation kernel then only initialises
   LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
-                     out.n_mismatch, out.stop, !cull, li.n_part, s));
+                     out.n_mismatch, out.stop, !cull && !P.bh, li.n_part, s));
   if (cull)
     LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
                            (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
@@ -366,14 +369,17 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     H.near_cap = fits ? Y.near_cap : 0;
     H.counts = (int32_t*)ctx->bh_counts.p;
     H.acc = acc;
+    H.lf = lf;
+    H.minseg2 = (double*)ctx->minseg2.p;
     H.beta = ctx->bh_beta;
     H.order = ctx->bh_order;
     H.out = out;
-    LK_HIP(launch_plan(Mb, n_loops, li, A.s, false, s));
-    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
     if (timed) LK_HIP(hipEventRecord(ev[0], s));
+    // the leaf kernel also validates the loops, so the plan follows it
     LK_HIP(launch_bh_leaves(H, P.in_f64, s));
     for (int h = 1; h < Y.levels; ++h) LK_HIP(launch_bh_level(H, h, s));
+    LK_HIP(launch_plan(Mb, n_loops, li, A.s, false, s));
+    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
     LK_HIP(launch_bh_roots(H, n_pairs, s));
     for (int it = 0; it < 2 * (Y.levels - 1) + 1; ++it) LK_HIP(launch_bh_expand(H, it, s));
     LK_HIP(launch_bh_near(H, P.in_f64, s));

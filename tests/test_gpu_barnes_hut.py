@@ -119,3 +119,31 @@ def test_options_and_bad_pairs(bctx):
     assert lk_int[0] == lk.INT_INVALID and flags[0] & lk.FLAG_BADPAIR
     assert lk_int[1] == lk.INT_INVALID and flags[1] & lk.FLAG_BADPAIR
     assert lk_int[2] == -1
+
+
+def test_loop_validation_matches_direct_sum(bctx):
+    """The leaf kernel validates the loops (non-finite coordinates, the
+    zero-length test, fewer than 3 vertices) in place of the preparation
+    kernel: the flags must equal the direct sum's."""
+    import paper_2106_12655_amd as lk
+    from paper_2106_12655_amd.inputs import _pack
+    t = 2 * np.pi * np.arange(9000) / 9000
+    ring = np.stack([np.cos(t), np.sin(t), 0 * t], 1)
+    bad = ring.copy()
+    bad[5000] = np.nan
+    dup = ring[::100].copy()
+    dup[7] = dup[6]
+    tri = np.array([[0.6, 0.0, -0.5], [1.4, 0.0, -0.45], [1.05, 0.0, 0.7]])
+    two = np.array([[0.0, 0.3, 0.1], [1.0, 0.3, 0.1]])
+    keep = lk.FLAG_BADLOOP | lk.FLAG_NONFINITE | lk.FLAG_BADPAIR
+    for loops, pairs in (([ring, tri, bad], [[0, 1], [2, 1], [1, 2], [2, 0]]),
+                         ([ring, tri, dup, two], [[0, 1], [2, 1], [3, 1], [1, 3]])):
+        ls = _pack(loops, np.float32, {}, "validation", 0)
+        pairs = np.array(pairs, np.int32)
+        r_b, l_b, f_b = _run(bctx, ls, pairs, "barnes_hut")
+        r_m, l_m, f_m = _run(bctx, ls, pairs, "mixed")
+        print("validation flags: barnes_hut", f_b.tolist(), "mixed", f_m.tolist(), flush=True)
+        assert np.array_equal(f_b & keep, f_m & keep)
+        ok = (f_b & lk.FLAG_NONFINITE) == 0
+        assert np.array_equal(l_b[ok], l_m[ok])
+        assert f_b[0] & keep == 0
