@@ -82,6 +82,9 @@ def _load():
         lib.lko_bh_far_pieces.restype = d
         lib.lko_bh_far_pieces.argtypes = [p, i64, i64, i64, p, i64, i64, i64, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_double)]
+        lib.lko_discretize.restype = i64
+        lib.lko_discretize.argtypes = [p, p, i32, ctypes.c_int, p, i64, d, ctypes.c_int,
+                                       ctypes.c_uint32, p, p, i64, p]
         lib.lko_bh_node_moments.restype = None
         lib.lko_bh_node_moments.argtypes = [p, i64, i64, i64, p]
         lib.lko_set_mutation.restype = None
@@ -243,3 +246,35 @@ def bh_far_pieces(P1, a1: int, b1: int, P2, a2: int, b2: int, order: int = 2):
     v = _load().lko_bh_far_pieces(_ptr(P1), P1.shape[0], int(a1), int(b1), _ptr(P2), P2.shape[0],
                                   int(a2), int(b2), int(order), ctypes.byref(ex))
     return v, ex.value
+
+
+FLAG_INTERSECT = 64
+DZ_BSPLINE = 0
+DZ_POLYLINE = 1
+
+
+def discretize(ctrl, cp_offsets, pairs, kind: int = DZ_BSPLINE,
+               eps: float = float(np.finfo(np.float64).eps), max_passes: int = 64):
+    """Alg. 3 (Sec. 3.3): closed curves (``kind`` DZ_BSPLINE: uniform cubic
+    B-spline control points; DZ_POLYLINE: vertices) given as ``ctrl`` [N][3]
+    and ``cp_offsets`` [L+1], refined against the candidate ``pairs`` until no
+    two pieces of a pair's loops have overlapping boxes.  Returns
+    ``(xyz [V][3] float64, offsets [L+1] int64, loop_flags [L] uint32)``; flag
+    16 = invalid loop (fewer than 3 points, non-finite, or a piece shorter
+    than eps * xi), FLAG_INTERSECT = refinement reached eps * xi (curves
+    within about that distance) or did not finish in ``max_passes``."""
+    ctrl = _f64(ctrl).reshape(-1, 3)
+    off = np.ascontiguousarray(cp_offsets, dtype=np.int64)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    L = off.shape[0] - 1
+    out_off = np.zeros(L + 1, dtype=np.int64)
+    flags = np.zeros(max(L, 1), dtype=np.uint32)
+    lib = _load()
+    args = (_ptr(ctrl), _ptr(off), L, int(kind), _ptr(pr), pr.shape[0], float(eps),
+            int(max_passes), FLAG_INTERSECT)
+    n = lib.lko_discretize(*args, None, _ptr(out_off), 0, _ptr(flags))
+    if n < 0:
+        raise MemoryError("oracle discretization failed")
+    xyz = np.zeros((max(n, 1), 3))
+    lib.lko_discretize(*args, _ptr(xyz), _ptr(out_off), n, _ptr(flags))
+    return xyz[:n], out_off, flags[:L]

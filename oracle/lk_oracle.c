@@ -48,7 +48,8 @@
  *
  * A global mutation switch (lko_set_mutation) plants deliberate mistakes for
  * the tests that prove the pins catch them; it is 0 (off) by default
- * (1-6: the Eq. 4 term and the pair sum; 7, 8: the Barnes-Hut expansion).
+ * (1-6: the Eq. 4 term and the pair sum; 7, 8: the Barnes-Hut expansion;
+ * 9-12: the discretization of Alg. 3).
  */
 #include <math.h>
 #include <pthread.h>
@@ -772,4 +773,247 @@ double lko_bh_far_pieces(const double* P1, int64_t n1, int64_t a1, int64_t b1, c
     *exact = s;
   }
   return bh_far(&u, &v, order, NULL);
+}
+
+/* ---------------------------------------------------------- discretization */
+/*
+ * Adaptive discretization of Sec. 3.3 (Alg. 3), FP64.
+ *
+ * Input loops (kind 0): closed uniform cubic B-splines.  Loop i has control
+ * points ctrl[cp_off[i] .. cp_off[i+1]) (m of them) and m spans; span s uses
+ * control points s-1, s, s+1, s+2 (cyclic) and is written as the cubic Bezier
+ * piece b0 = (q0 + 4 q1 + q2)/6, b1 = (2 q1 + q2)/3, b2 = (q1 + 2 q2)/3,
+ * b3 = (q1 + 4 q2 + q3)/6.  Kind 1: closed polylines; segment s from vertex s
+ * to s+1 is the piece (v_s, v_s, v_s+1, v_s+1) and is split at its midpoint.
+ * A piece's bounding box is the box of its four points (the curve lies in
+ * their convex hull, which the paper's proofs require of the bounding
+ * volume).
+ *
+ * Validation first: a loop with fewer than 3 points, a non-finite
+ * coordinate, or a piece whose box diagonal is below eps * xi (the
+ * zero-length test; xi = mean over all points of (|x| + |y| + |z|) / 3) is
+ * flagged BADLOOP (16), and pairs that name such a loop, name a loop outside
+ * [0, L) or name the same loop twice take no part in the refinement.
+ *
+ * Passes: every unprocessed piece of loop i whose box overlaps (closed
+ * intervals) the box of an unprocessed piece of loop j, for a pair (i, j), is
+ * under-refined and is split at t = 1/2 by de Casteljau's construction; every
+ * other unprocessed piece becomes final.  Pieces keep the curve's parameter
+ * order, so the polyline is the list of the pieces' start points (the final
+ * sort of the paper is implicit).  When a split gives a child whose box
+ * diagonal is below eps * xi the loop is flagged `intersect_flag` (the
+ * paper's "curves intersect" error) and both children become final; pieces
+ * still unprocessed after max_passes get the same flag.
+ *
+ * Returns the number of output vertices (writing xyz only when it fits
+ * `cap`), out_off[L+1] and loop_flags[L] (may be NULL); -1 on allocation
+ * failure.
+ */
+typedef struct {
+  double b[4][3];
+  int done;
+} dz_piece;
+
+typedef struct {
+  dz_piece* p;
+  int64_t n, cap;
+} dz_list;
+
+static int dz_push(dz_list* l, const dz_piece* x) {
+  if (l->n == l->cap) {
+    int64_t nc = l->cap ? 2 * l->cap : 16;
+    dz_piece* q = (dz_piece*)realloc(l->p, sizeof(dz_piece) * (size_t)nc);
+    if (!q) return 0;
+    l->p = q;
+    l->cap = nc;
+  }
+  l->p[l->n++] = *x;
+  return 1;
+}
+
+static void dz_box(const dz_piece* x, double* lo, double* hi) {
+  for (int q = 0; q < 3; ++q) {
+    lo[q] = x->b[0][q];
+    hi[q] = x->b[0][q];
+    for (int k = 1; k < 4; ++k) {
+      if (x->b[k][q] < lo[q]) lo[q] = x->b[k][q];
+      if (x->b[k][q] > hi[q]) hi[q] = x->b[k][q];
+    }
+  }
+}
+
+/* squared diagonal of the box */
+static double dz_diag2(const dz_piece* x) {
+  double lo[3], hi[3];
+  dz_box(x, lo, hi);
+  const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+static int dz_overlap(const dz_piece* a, const dz_piece* b) {
+  double la[3], ha[3], lb[3], hb[3];
+  dz_box(a, la, ha);
+  dz_box(b, lb, hb);
+  for (int q = 0; q < 3; ++q)
+    if (!(la[q] <= hb[q] && lb[q] <= ha[q])) return 0;
+  return 1;
+}
+
+/* halves of the parameter domain */
+static void dz_split(const dz_piece* x, int linear, dz_piece* l, dz_piece* r) {
+  for (int q = 0; q < 3; ++q) {
+    if (linear) {
+      const double m = 0.5 * (x->b[0][q] + x->b[3][q]);
+      l->b[0][q] = l->b[1][q] = x->b[0][q];
+      l->b[2][q] = l->b[3][q] = m;
+      r->b[0][q] = r->b[1][q] = m;
+      r->b[2][q] = r->b[3][q] = x->b[3][q];
+      continue;
+    }
+    const double m01 = 0.5 * (x->b[0][q] + x->b[1][q]);
+    const double m12 = 0.5 * (x->b[1][q] + x->b[2][q]);
+    const double m23 = 0.5 * (x->b[2][q] + x->b[3][q]);
+    const double m012 = 0.5 * (m01 + m12);
+    const double m123 = 0.5 * (m12 + m23);
+    const double m = (g_mutation == 10) ? 0.5 * (m01 + m23) : 0.5 * (m012 + m123);
+    l->b[0][q] = x->b[0][q];
+    l->b[1][q] = m01;
+    l->b[2][q] = m012;
+    l->b[3][q] = m;
+    r->b[0][q] = m;
+    r->b[1][q] = m123;
+    r->b[2][q] = m23;
+    r->b[3][q] = x->b[3][q];
+  }
+  l->done = r->done = 0;
+}
+
+int64_t lko_discretize(const double* ctrl, const int64_t* cp_off, int32_t L, int kind,
+                       const int32_t* pairs, int64_t P, double eps, int max_passes,
+                       uint32_t intersect_flag, double* out_xyz, int64_t* out_off, int64_t cap,
+                       uint32_t* loop_flags) {
+  const int linear = kind == 1;
+  dz_list* lists = (dz_list*)calloc((size_t)(L > 0 ? L : 1), sizeof(dz_list));
+  uint32_t* flags = (uint32_t*)calloc((size_t)(L > 0 ? L : 1), sizeof(uint32_t));
+  if (!lists || !flags) {
+    free(lists);
+    free(flags);
+    return -1;
+  }
+  /* xi: mean of (|x| + |y| + |z|) / 3 over every input point */
+  const int64_t ncp = cp_off[L] - cp_off[0];
+  double xs = 0.0;
+  for (int64_t v = cp_off[0]; v < cp_off[L]; ++v)
+    xs += fabs(ctrl[3 * v]) + fabs(ctrl[3 * v + 1]) + fabs(ctrl[3 * v + 2]);
+  const double xi = ncp > 0 ? xs / (3.0 * (double)ncp) : 0.0;
+  const double lim = eps * xi;
+  const double lim2 = lim * lim;
+  int ok = 1;
+  for (int32_t i = 0; i < L && ok; ++i) {
+    const int64_t o = cp_off[i], m = cp_off[i + 1] - o;
+    if (m < 3) flags[i] |= 16u;
+    for (int64_t v = 0; v < 3 * m; ++v)
+      if (!isfinite(ctrl[3 * o + v])) flags[i] |= 16u;
+    for (int64_t s = 0; s < m; ++s) {
+      dz_piece x;
+      const double* q1 = ctrl + 3 * (o + s);
+      const double* q2 = ctrl + 3 * (o + (s + 1) % m);
+      if (linear) {
+        for (int q = 0; q < 3; ++q) {
+          x.b[0][q] = x.b[1][q] = q1[q];
+          x.b[2][q] = x.b[3][q] = q2[q];
+        }
+      } else {
+        const double* q0 = ctrl + 3 * (o + (s + m - 1) % m);
+        const double* q3 = ctrl + 3 * (o + (s + 2) % m);
+        for (int q = 0; q < 3; ++q) {
+          x.b[0][q] = (g_mutation == 11) ? q1[q] : (q0[q] + 4.0 * q1[q] + q2[q]) / 6.0;
+          x.b[1][q] = (2.0 * q1[q] + q2[q]) / 3.0;
+          x.b[2][q] = (q1[q] + 2.0 * q2[q]) / 3.0;
+          x.b[3][q] = (q1[q] + 4.0 * q2[q] + q3[q]) / 6.0;
+        }
+      }
+      x.done = 0;
+      if (dz_diag2(&x) < lim2) flags[i] |= 16u;
+      ok &= dz_push(&lists[i], &x);
+    }
+  }
+  /* passes */
+  for (int pass = 0; pass < max_passes && ok; ++pass) {
+    int64_t unproc = 0;
+    for (int32_t i = 0; i < L; ++i)
+      for (int64_t k = 0; k < lists[i].n; ++k) unproc += !lists[i].p[k].done;
+    if (unproc == 0) break;
+    char** mark = (char**)calloc((size_t)L, sizeof(char*));
+    if (!mark) {
+      ok = 0;
+      break;
+    }
+    for (int32_t i = 0; i < L; ++i) {
+      mark[i] = (char*)calloc((size_t)(lists[i].n + 1), 1);
+      if (!mark[i]) ok = 0;
+    }
+    for (int64_t p = 0; p < P && ok; ++p) {
+      const int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+      if (i < 0 || j < 0 || i >= L || j >= L || i == j) continue;
+      if ((flags[i] | flags[j]) & 16u) continue;
+      for (int64_t a = 0; a < lists[i].n; ++a) {
+        if (lists[i].p[a].done) continue;
+        for (int64_t b = 0; b < lists[j].n; ++b) {
+          if (lists[j].p[b].done) continue;
+          if (dz_overlap(&lists[i].p[a], &lists[j].p[b])) {
+            mark[i][a] = 1;
+            if (g_mutation != 9) mark[j][b] = 1; /* mutation 9: one side only */
+          }
+        }
+      }
+    }
+    for (int32_t i = 0; i < L && ok; ++i) {
+      dz_list nl = {0, 0, 0};
+      for (int64_t k = 0; k < lists[i].n; ++k) {
+        dz_piece x = lists[i].p[k];
+        if (!x.done && !mark[i][k]) x.done = 1;
+        if (x.done) {
+          ok &= dz_push(&nl, &x);
+          continue;
+        }
+        dz_piece l, r;
+        dz_split(&x, linear, &l, &r);
+        if (dz_diag2(&l) < lim2 || dz_diag2(&r) < lim2) {
+          flags[i] |= intersect_flag;
+          l.done = r.done = 1;
+        }
+        if (g_mutation == 12) { /* mutation 12: children out of order */
+          ok &= dz_push(&nl, &r);
+          ok &= dz_push(&nl, &l);
+        } else {
+          ok &= dz_push(&nl, &l);
+          ok &= dz_push(&nl, &r);
+        }
+      }
+      free(lists[i].p);
+      lists[i] = nl;
+    }
+    for (int32_t i = 0; i < L; ++i) free(mark[i]);
+    free(mark);
+  }
+  int64_t total = -1;
+  if (ok) {
+    total = 0;
+    for (int32_t i = 0; i < L; ++i) {
+      out_off[i] = total;
+      for (int64_t k = 0; k < lists[i].n; ++k) {
+        if (!lists[i].p[k].done) flags[i] |= intersect_flag;
+        if (total < cap && out_xyz)
+          for (int q = 0; q < 3; ++q) out_xyz[3 * total + q] = lists[i].p[k].b[0][q];
+        ++total;
+      }
+    }
+    out_off[L] = total;
+    if (loop_flags) memcpy(loop_flags, flags, sizeof(uint32_t) * (size_t)L);
+  }
+  for (int32_t i = 0; i < L; ++i) free(lists[i].p);
+  free(lists);
+  free(flags);
+  return total;
 }

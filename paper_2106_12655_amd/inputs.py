@@ -372,6 +372,8 @@ def knit_tube(stitches: int, rows: int, per_span: int = 32, pattern: str = "alte
     (the stockinette-like default) alternates the signs, so an even stitch
     count links 0; ``uniform`` makes every sign +1 (linking number = stitch
     count).  ``flip``: set of (row, stitch) clasps whose sign is reversed.
+    ``per_span`` = 0 returns the control polygons themselves (the spline
+    input of a discretizer) instead of uniform samples.
     """
     radius = max(stitches / (2 * np.pi), _KNIT_RMIN)
     loops, exp = [], {}
@@ -384,7 +386,8 @@ def knit_tube(stitches: int, rows: int, per_span: int = 32, pattern: str = "alte
             for s in range(stitches):
                 if (r, s) in flip:
                     sg[s] = -sg[s]
-        loops.append(bspline_closed(knit_row_controls(stitches, r, radius, sg), per_span))
+        ctrl = knit_row_controls(stitches, r, radius, sg)
+        loops.append(bspline_closed(ctrl, per_span) if per_span > 0 else ctrl)
         if r > 0:
             exp[(r - 1, r)] = int(round(sg.sum()))
     return loops, exp
@@ -410,6 +413,10 @@ def knit(seed: int = 0, n_loops: int = 2000, cp_min: int = 16, cp_max: int = 512
     ``pull``: global loop indices of rows whose first clasp is pulled through
     (its sign reversed), which changes the row's linking number with the row
     below by -2 times the clasp's sign; the expected values include the change.
+    ``per_span`` = 0: each row is its control polygon (closed uniform cubic
+    B-spline control points, for a discretizer); the rotation and placement
+    are affine, so they map the spline of the polygon to the spline of the
+    mapped polygon.
     ``sigma``: per-vertex Gaussian noise added after construction (seeded by
     ``noise_seed``, default ``seed``); keep it well below the 0.13 clearance
     between clasping rows.

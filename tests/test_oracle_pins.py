@@ -197,11 +197,229 @@ def pin_bh_accuracy():
     return None
 
 
+# ------------------------------------------------------------ discretization
+def _bspline_at(P, s, t):
+    """Closed uniform cubic B-spline of control polygon P at span s, local
+    parameter t in [0, 1], from its basis polynomials."""
+    n = len(P)
+    b0 = (1 - t) ** 3 / 6
+    b1 = (3 * t ** 3 - 6 * t ** 2 + 4) / 6
+    b2 = (-3 * t ** 3 + 3 * t ** 2 + 3 * t + 1) / 6
+    b3 = t ** 3 / 6
+    return b0 * P[(s - 1) % n] + b1 * P[s % n] + b2 * P[(s + 1) % n] + b3 * P[(s + 2) % n]
+
+
+def _polyline_at(P, s, t):
+    n = len(P)
+    return (1 - t) * P[s % n] + t * P[(s + 1) % n]
+
+
+def _dyadic_parse(P, V, curve, tol=1e-12):
+    """Read the vertices V of a discretized closed curve as the start points of
+    a partition of every span's parameter interval [0, 1] into dyadic pieces
+    [t, t + 2^-d] (t a multiple of 2^-d), in order.  Returns the list of
+    (span, t, d) or a message saying where V is not such a list."""
+    scale = 1.0 + np.abs(P).max()
+    out = []
+    k = 0
+    n = len(V)
+    for s in range(len(P)):
+        t = 0.0
+        while t < 1.0:
+            if k >= n or np.abs(V[k] - curve(P, s, t)).max() > tol * scale:
+                return "vertex %d is not the curve point of span %d at t = %r" % (k, s, t)
+            nxt = V[(k + 1) % n]
+            for d in range(0, 64):
+                h = 2.0 ** -d
+                if t + h > 1.0 or (t / h) != np.floor(t / h):
+                    continue
+                if np.abs(nxt - curve(P, s, t + h)).max() <= tol * scale:
+                    break
+            else:
+                return "vertex %d of span %d has no dyadic successor" % (k, s)
+            out.append((s, t, d))
+            t += h
+            k += 1
+    if k != n:
+        return "%d vertices left over" % (n - k)
+    return out
+
+
+def _piece_sample_box(P, curve, s, t, d, m=9):
+    h = 2.0 ** -d
+    pts = np.array([curve(P, s, t + h * a / (m - 1)) for a in range(m)])
+    return pts.min(0), pts.max(0)
+
+
+def _dz_loops(res, ctrl_loops, curve):
+    xyz, off, flags = res
+    parsed = []
+    for i, P in enumerate(ctrl_loops):
+        r = _dyadic_parse(P, xyz[off[i]:off[i + 1]], curve)
+        if isinstance(r, str):
+            return "loop %d: %s" % (i, r)
+        parsed.append(r)
+    return parsed
+
+
+def _pack_loops(loops):
+    off = np.zeros(len(loops) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(x) for x in loops])
+    return np.concatenate(loops, 0).astype(np.float64), off
+
+
+def _knit_rows(stitches=4, rows=3, pattern="uniform"):
+    loops, exp = I.knit_tube(stitches, rows, per_span=0, pattern=pattern)
+    return loops, exp
+
+
+def _through_arc():
+    """B: a coarse closed B-spline (4 control points, a rounded diamond in the
+    xz-plane); A: a small ring (12 control points) around the arc of B's span
+    from +x to +z, placed so that the arc passes through A's disk but the
+    chord between the span's end points does not.  The curves link once; the
+    polyline through B's knots does not link A."""
+    B = np.array([[1.0, 0, 0], [0, 0, 1.0], [-1.0, 0, 0], [0, 0, -1.0]])
+    u = np.array([1.0, 0, 1.0]) / np.sqrt(2)
+    v = np.array([0, 1.0, 0])
+    c = 0.70 * u
+    th = 2 * np.pi * np.arange(12) / 12
+    A = c + 0.125 * (np.outer(np.cos(th), u) + np.outer(np.sin(th), v))
+    return [A, B]
+
+
+def _square_triangle():
+    """A square in the xy-plane and a triangle in the xz-plane that links it,
+    with a triangle edge whose box overlaps a square edge's box."""
+    sq = np.array([[1.0, 1, 0], [-1, 1, 0], [-1, -1, 0], [1, -1, 0]])
+    tri = np.array([[0.4, 0, 1.0], [1.4, 0, -1.0], [3.0, 0, 0]])
+    return sq, tri
+
+
+def pin_dz_on_curve():
+    """Alg. 3 splits a piece's parameter domain in halves and keeps the
+    curve: every output vertex is the curve point at a dyadic parameter, the
+    vertices run in parameter order, and each span's pieces partition [0, 1]."""
+    loops, _ = _knit_rows()
+    xyz, off = _pack_loops(loops)
+    res = oracle.discretize(xyz, off, [[0, 1], [1, 2], [0, 2]])
+    parsed = _dz_loops(res, loops, _bspline_at)
+    if isinstance(parsed, str):
+        return "b-spline: " + parsed
+    if res[1][-1] <= len(xyz):
+        return "clasped rows were not refined"
+    sq, tri = _square_triangle()
+    xyz, off = _pack_loops([sq, tri])
+    res = oracle.discretize(xyz, off, [[0, 1]], kind=oracle.DZ_POLYLINE)
+    parsed = _dz_loops(res, [sq, tri], _polyline_at)
+    if isinstance(parsed, str):
+        return "polyline: " + parsed
+    if res[1][-1] <= 7:
+        return "a coarse polyline link was not refined"
+    x, o, _ = res
+    if abs(abs(oracle.pair(x[o[0]:o[1]], x[o[1]:o[2]])) - 1) > 1e-12:
+        return "refining polylines changed their linking number"
+    return None
+
+
+def pin_dz_separated():
+    """On exit no piece of loop i has a box that overlaps a piece of loop j
+    for a listed pair (the convex volumes of the homotopy argument of
+    App. A): boxes of points sampled on each final piece are disjoint."""
+    loops, _ = _knit_rows()
+    xyz, off = _pack_loops(loops)
+    pairs = [[0, 1], [1, 2], [0, 2]]
+    res = oracle.discretize(xyz, off, pairs)
+    parsed = _dz_loops(res, loops, _bspline_at)
+    if isinstance(parsed, str):
+        return parsed
+    boxes = [[_piece_sample_box(loops[i], _bspline_at, *pc) for pc in parsed[i]]
+             for i in range(len(loops))]
+    for i, j in pairs:
+        for la, ha in boxes[i]:
+            for lb, hb in boxes[j]:
+                if np.all(la <= hb) and np.all(lb <= ha):
+                    return "pieces of loops %d and %d still overlap" % (i, j)
+    return None
+
+
+def pin_dz_unrefined():
+    """Only pieces whose boxes overlap are refined: with no pair, or with the
+    loops far apart, the output is the knot points (the span end points)."""
+    loops, _ = _knit_rows()
+    far = [loops[0], loops[1] + np.array([100.0, 0, 0])]
+    for ls, pairs in ((loops, []), (far, [[0, 1]])):
+        xyz, off = _pack_loops(ls)
+        res = oracle.discretize(xyz, off, pairs)
+        if res[1][-1] != len(xyz):
+            return "refined without overlapping boxes"
+        for i, P in enumerate(ls):
+            knots = np.array([_bspline_at(P, s, 0.0) for s in range(len(P))])
+            if np.abs(res[0][res[1][i]:res[1][i + 1]] - knots).max() > 1e-12 * (1 + np.abs(P).max()):
+                return "unrefined output is not the knot points"
+    return None
+
+
+def pin_dz_homotopy():
+    """The output polylines are link-homotopic to the splines (Sec. 3.3,
+    App. A): the linking number of the discretization equals that of a fine
+    uniform sampling, in both pair orders, where the knot polyline is wrong."""
+    loops = _through_arc()
+    fine = [I.bspline_closed(P, 256) for P in loops]
+    ref = oracle.pair(fine[0], fine[1])
+    knot = [I.bspline_closed(P, 1) for P in loops]
+    if abs(abs(ref) - 1) > 1e-6 or abs(oracle.pair(knot[0], knot[1])) > 1e-6:
+        return "construction: fine %r, knots %r" % (ref, oracle.pair(knot[0], knot[1]))
+    xyz, off = _pack_loops(loops)
+    for pairs in ([[0, 1]], [[1, 0]]):
+        res = oracle.discretize(xyz, off, pairs)
+        x, o, _ = res
+        v = oracle.pair(x[o[0]:o[1]], x[o[1]:o[2]])
+        if abs(v - ref) > 1e-6:
+            return "discretization with pairs %s links %r, not %r" % (pairs, v, ref)
+    # knit rows: the construction's linking numbers
+    loops, exp = _knit_rows()
+    xyz, off = _pack_loops(loops)
+    pairs = [[0, 1], [0, 2], [1, 2]]
+    x, o, _ = oracle.discretize(xyz, off, pairs)
+    for i, j in pairs:
+        v = oracle.pair(x[o[i]:o[i + 1]], x[o[j]:o[j + 1]])
+        if abs(v - exp.get((i, j), 0)) > 1e-6:
+            return "knit rows %d %d link %r" % (i, j, v)
+    return None
+
+
+def pin_dz_termination():
+    """App. A: at pass P every unprocessed piece spans 2^-P of its span, and
+    its box diagonal is at most 2^-P times G, the largest control-polygon edge
+    (the derivative's control points); boxes of loops at distance d can only
+    overlap while 2^-P * 2G >= d, so no piece is deeper than
+    floor(log2(2G / d)) + 1."""
+    loops = _through_arc()
+    xyz, off = _pack_loops(loops)
+    res = oracle.discretize(xyz, off, [[0, 1]])
+    parsed = _dz_loops(res, loops, _bspline_at)
+    if isinstance(parsed, str):
+        return parsed
+    G = max(np.linalg.norm(np.roll(P, -1, 0) - P, axis=1).max() for P in loops)
+    K = 64
+    fa = I.bspline_closed(loops[0], K)
+    fb = I.bspline_closed(loops[1], K)
+    ds = np.sqrt(((fa[:, None, :] - fb[None, :, :]) ** 2).sum(-1)).min()
+    d = ds - G / K
+    depth = max(pc[2] for lp in parsed for pc in lp)
+    bound = int(np.floor(np.log2(2 * G / d))) + 1
+    if depth > bound or depth < 1:
+        return "depth %d outside (1, %d]" % (depth, bound)
+    return None
+
+
 def run_pins():
     fails = []
     for f in (pin_segment_terms, pin_hopf, pin_torus, pin_crossings, pin_integer_and_refinement,
               pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
-              pin_bh_expansion_order, pin_bh_accuracy):
+              pin_bh_expansion_order, pin_bh_accuracy, pin_dz_on_curve, pin_dz_separated,
+              pin_dz_unrefined, pin_dz_homotopy, pin_dz_termination):
         r = f()
         if r:
             fails.append(r)
@@ -369,12 +587,14 @@ def test_loop_flags():
     assert f[1] & oracle.FLAG_NONFINITE
 
 
-@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mutation", list(range(1, 13)))
 def test_planted_mistakes_are_caught(mutation):
     """A dropped term, a wrong sign, a wrong index, a transposed operand, an
     open loop, a wrong normalisation, a wrong sign of the Barnes-Hut dipole
-    term or a dropped part of the segment quadrupole moment each break at
-    least one pin."""
+    term, a dropped part of the segment quadrupole moment, a discretization
+    that refines only one loop of a pair, a wrong de Casteljau midpoint, a
+    wrong B-spline end point or halves out of order each break at least one
+    pin."""
     oracle.set_mutation(mutation)
     try:
         fails = run_pins()
@@ -388,3 +608,38 @@ def test_bh_pins():
     for f in (pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
               pin_bh_expansion_order, pin_bh_accuracy):
         assert f() is None, f.__name__
+
+
+def test_dz_pins():
+    for f in (pin_dz_on_curve, pin_dz_separated, pin_dz_unrefined, pin_dz_homotopy,
+              pin_dz_termination):
+        assert f() is None, f.__name__
+
+
+def test_dz_flags():
+    """Alg. 3's errors become loop flags: a zero-length piece or fewer than 3
+    points is an invalid loop (its pairs take no part); curves that touch
+    refine down to eps * xi and are flagged; so are pieces left unprocessed
+    when the pass limit is reached."""
+    sq = np.array([[1.0, 1, 0], [-1, 1, 0], [-1, -1, 0], [1, -1, 0]])
+    tri = np.array([[1.0, 0, 0], [3, 0.5, 1], [3, -0.5, -1]])  # through sq's edge x = 1
+    rep = sq.copy()
+    rep[2] = rep[1]
+    xyz, off = _pack_loops([sq, tri + [0, 0, 0], rep + [0, 0, 0.5], sq[:2] + [0, 0, 2]])
+    x, o, f = oracle.discretize(xyz, off, [[0, 1], [0, 2], [0, 3]], kind=oracle.DZ_POLYLINE)
+    assert f[0] & oracle.FLAG_INTERSECT and f[1] & oracle.FLAG_INTERSECT
+    assert f[2] == 16 and f[3] == 16
+    assert o[3] - o[2] == 4 and o[4] - o[3] == 2  # invalid loops are not refined
+    assert not np.isnan(x).any()
+    loops, _ = _knit_rows()
+    xyz, off = _pack_loops(loops)
+    _, _, f = oracle.discretize(xyz, off, [[0, 1]], max_passes=1)
+    assert f[0] & oracle.FLAG_INTERSECT and f[1] & oracle.FLAG_INTERSECT and f[2] == 0
+    _, _, f = oracle.discretize(xyz, off, [[0, 1]])
+    assert (f == 0).all()
+    # a NaN control point: the loop is invalid, the others are untouched
+    bad = loops[1].copy()
+    bad[3, 1] = np.nan
+    xyz, off = _pack_loops([loops[0], bad])
+    x, o, f = oracle.discretize(xyz, off, [[0, 1]])
+    assert f[1] == 16 and o[-1] == len(xyz)
