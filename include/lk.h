@@ -96,8 +96,11 @@ enum {
                              segment shorter than eps * xi (Alg. 3 zero-length test,
                              xi = mean |coordinate| over the call's vertices,
                              eps = machine epsilon of the input dtype) */
-  LK_FLAG_SKIPPED = 32u   /* lk_direct_sum_check with early exit stopped before this
+  LK_FLAG_SKIPPED = 32u,  /* lk_direct_sum_check with early exit stopped before this
                              pair's sum was complete (no value, LK_INT_INVALID) */
+  LK_FLAG_INTERSECT = 64u /* lk_discretize (a loop flag): refinement of this loop reached
+                             a piece shorter than eps * xi, or the pass limit, so the
+                             curve comes within about that distance of a paired loop */
 };
 
 /* Integer reported for pairs whose value is not finite or whose indices are bad. */
@@ -172,6 +175,58 @@ lk_status lk_direct_sum_check(lk_ctx* ctx, const void* xyz, int dtype,
  * written to mismatches [cap][4] as (i, j, got, expected).  With
  * early_exit != 0 the call stops at the first mismatch in pair order:
  * *n_mismatch is 0 or 1 and at most that record is written. */
+/* --------------------------------------------------------- discretization */
+/* Curve kinds of lk_discretize. */
+typedef enum {
+  LK_DZ_BSPLINE = 0, /* closed uniform cubic B-spline: loop l's points are its m control
+                        points and it has m spans; span s is the cubic of control points
+                        s-1, s, s+1, s+2 (cyclic) */
+  LK_DZ_POLYLINE = 1 /* closed polyline: m vertices, m segments */
+} lk_curve_kind;
+
+typedef struct {
+  int32_t passes;      /* refinement passes run */
+  int32_t reserved;
+  int64_t input_spans; /* spans (B-spline) or segments (polyline) of the input */
+  int64_t vertices;    /* output vertices (= output segments) */
+  int64_t splits;      /* pieces split over all passes */
+  int64_t unfinished;  /* pieces still unprocessed when the pass limit stopped the
+                          refinement (their loops are flagged LK_FLAG_INTERSECT) */
+} lk_dz_info;
+
+/* Discretization (Sec. 3.3, Alg. 3): closed curves -> closed polylines with
+ * the same linking numbers.  Every span is a cubic Bezier piece (a polyline
+ * segment is a linear one) bounded by the box of its control points, which
+ * contains the curve.  Each pass splits every unprocessed piece whose box
+ * overlaps (closed intervals) the box of an unprocessed piece of a loop it is
+ * paired with, at the middle of its parameter domain (de Casteljau; the
+ * midpoint of a segment); every other unprocessed piece becomes final.  When
+ * nothing is unprocessed, loop l's polyline is its pieces' start points in
+ * parameter order.  By the argument of App. A, every loop can then be
+ * deformed into its polyline inside boxes that no other paired loop enters.
+ *   ctrl [N][3] FP64 and ctrl_offsets [n_loops+1] (int64, non-decreasing) give
+ *     the points of each loop as in the geometry convention above; kind is an
+ *     lk_curve_kind; pairs [n_pairs][2] are the candidate loop pairs (e.g. from
+ *     lk_build_pairs on the control points, whose boxes contain the curves).
+ *   xyz_out [capacity][3] FP64 receives the vertices, offsets_out [n_loops+1]
+ *     (int64, from 0) the loops' ranges, loop_flags [n_loops] (may be NULL)
+ *     LK_FLAG_BADLOOP (fewer than 3 points, a non-finite coordinate, or a
+ *     span whose box diagonal is below eps * xi, eps = 2^-52; such a loop's
+ *     pairs take no part and it is not refined) and LK_FLAG_INTERSECT.
+ *   *n_vertices (host) receives the output vertex count; *info (host, may be
+ *     NULL) the pass statistics.
+ * All arrays but n_vertices and info are device arrays.  Synchronises the
+ * stream after every pass (the next pass is sized from the counts), so it
+ * cannot be captured (LK_EBUSY on a capturing stream).  If the vertices do not
+ * fit `capacity`, offsets_out and loop_flags are still written, xyz_out is
+ * not, and LK_ECAPACITY is returned.  The result is bitwise reproducible and
+ * does not depend on the order of the pairs. */
+lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_offsets,
+                        int32_t n_loops, int kind, const int32_t* pairs, int64_t n_pairs,
+                        double* xyz_out, int64_t capacity, int64_t* offsets_out,
+                        uint32_t* loop_flags, int64_t* n_vertices /* host */,
+                        lk_dz_info* info /* host */, void* stream);
+
 lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_t n,
                     const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp, int early_exit,
                     int64_t* n_mismatch /* host */, int32_t* mismatches, int64_t cap, void* stream);
@@ -202,8 +257,10 @@ enum {
                                      the results are the same */
   LK_OPT_BH_BETA_MILLI = 13,      /* BARNES_HUT: far-field ratio beta x 1000, 500..1e6
                                      (default 4000) */
-  LK_OPT_BH_ORDER = 14            /* BARNES_HUT: 1 = monopole and dipole terms, 2 = also the
+  LK_OPT_BH_ORDER = 14,           /* BARNES_HUT: 1 = monopole and dipole terms, 2 = also the
                                      quadrupole term (default) */
+  LK_OPT_DZ_MAX_PASSES = 15       /* lk_discretize: most refinement passes, 1..1000 (default 64;
+                                     pieces left unprocessed flag their loop INTERSECT) */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */

@@ -6,7 +6,8 @@ memory and the current stream) into the C ABI.  It has no CPU fallback: without
 a built library or a GPU every call raises.
 
 Functions follow the paper's pipeline (Qu & James 2021, Alg. 1):
-``build_pairs`` (potential link search, Alg. 2), ``direct_sum`` (stage 3 by
+``build_pairs`` (potential link search, Alg. 2), ``discretize`` (curves to
+polylines with the same linking numbers, Alg. 3), ``direct_sum`` (stage 3 by
 direct summation of Eq. 4, Alg. 5), ``direct_sum_check`` (the same fused with
 the certificate comparison and its early exit, Sec. 3.1) and ``verify`` (the
 before/after comparison of two sparse matrices, Sec. 3.1).
@@ -16,12 +17,12 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (FLAG_AMBIGUOUS, FLAG_BADLOOP, FLAG_BADPAIR, FLAG_NONFINITE, FLAG_REFIT,
-                   FLAG_SKIPPED, INT_INVALID, LkError)
+from ._lib import (FLAG_AMBIGUOUS, FLAG_BADLOOP, FLAG_BADPAIR, FLAG_INTERSECT, FLAG_NONFINITE,
+                   FLAG_REFIT, FLAG_SKIPPED, INT_INVALID, LkError)
 
-__all__ = ["Context", "build_pairs", "direct_sum", "direct_sum_check", "verify", "LkError",
-           "FLAG_REFIT", "FLAG_AMBIGUOUS", "FLAG_NONFINITE", "FLAG_BADPAIR", "FLAG_BADLOOP",
-           "FLAG_SKIPPED", "INT_INVALID"]
+__all__ = ["Context", "build_pairs", "discretize", "direct_sum", "direct_sum_check", "verify",
+           "LkError", "FLAG_REFIT", "FLAG_AMBIGUOUS", "FLAG_NONFINITE", "FLAG_BADPAIR",
+           "FLAG_BADLOOP", "FLAG_SKIPPED", "FLAG_INTERSECT", "INT_INVALID"]
 
 
 def _torch():
@@ -126,6 +127,41 @@ class Context:
                                          _ptr(out), cap, ctypes.byref(n), _stream(self.device))
         self._check(st)
         return out[: int(n.value)]
+
+    def discretize(self, ctrl, offsets, pairs, kind: str = "bspline",
+                   capacity: int | None = None):
+        """Alg. 3 (lk_discretize): closed curves -> polylines with the same
+        linking numbers.  ``ctrl`` float64 [N, 3] (B-spline control points or
+        polyline vertices, ``kind``), ``offsets`` int64 [L+1], ``pairs`` int32
+        [P, 2], all on the device.  Returns ``(xyz float64 [V, 3], offsets int64
+        [L+1], loop_flags int32 [L], info dict)`` on the device."""
+        torch = _torch()
+        self._dev(ctrl, torch.float64, "ctrl")
+        self._dev(offsets, torch.int64, "offsets")
+        self._dev(pairs, torch.int32, "pairs")
+        if pairs.numel() and (pairs.dim() != 2 or pairs.shape[1] != 2):
+            raise ValueError("pairs must be [P, 2]")
+        P = pairs.shape[0] if pairs.dim() == 2 else 0
+        L = offsets.numel() - 1
+        dev = ctrl.device
+        cap = int(capacity) if capacity is not None else 4 * (ctrl.numel() // 3) + 1024
+        off_out = torch.empty(L + 1, dtype=torch.int64, device=dev)
+        flags = torch.empty(max(L, 1), dtype=torch.int32, device=dev)
+        n = ctypes.c_int64(0)
+        info = _lib.DzInfo()
+        for attempt in range(2):
+            xyz = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=dev)
+            st = self.lib.lk_discretize(self.h, _ptr(ctrl), _ptr(offsets), L,
+                                        _lib.DZ_KINDS[kind], _ptr(pairs), P, _ptr(xyz), cap,
+                                        _ptr(off_out), _ptr(flags), ctypes.byref(n),
+                                        ctypes.byref(info), _stream(self.device))
+            if st == _lib.ECAPACITY and capacity is None and attempt == 0:
+                cap = int(n.value)
+                continue
+            break
+        self._check(st)
+        return (xyz[: int(n.value)], off_out, flags[:L],
+                {k: getattr(info, k) for k, _ in info._fields_ if k != "reserved"})
 
     def direct_sum(self, xyz, offsets, pairs, mode: str = "mixed", out=None):
         """Eq. 4 summed over every segment pair of every loop pair.
@@ -245,6 +281,10 @@ def direct_sum(xyz, offsets, pairs, mode="mixed", out=None):
 def direct_sum_check(xyz, offsets, pairs, expected, early_exit=False, mode="mixed", out=None):
     return context(xyz.device.index or 0).direct_sum_check(xyz, offsets, pairs, expected,
                                                            early_exit, mode, out)
+
+
+def discretize(ctrl, offsets, pairs, kind="bspline", capacity=None):
+    return context(ctrl.device.index or 0).discretize(ctrl, offsets, pairs, kind, capacity)
 
 
 def verify(pairs, lk, exp_pairs, exp_lk, early_exit=False, cap=1024):

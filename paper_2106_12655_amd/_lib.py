@@ -25,11 +25,14 @@ INT_INVALID = -(2 ** 31)
 OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 3, 4, 5
 OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
 OPT_SMALL_BATCH, OPT_CROSSING_TOL, OPT_CROSSING_CULL = 10, 11, 12
-OPT_BH_BETA_MILLI, OPT_BH_ORDER = 13, 14
+OPT_BH_BETA_MILLI, OPT_BH_ORDER, OPT_DZ_MAX_PASSES = 13, 14, 15
+FLAG_INTERSECT = 64
+DZ_BSPLINE, DZ_POLYLINE = 0, 1
+DZ_KINDS = {"bspline": DZ_BSPLINE, "polyline": DZ_POLYLINE}
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
            "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_set_view_direction",
-           "lk_get_view_direction", "lk_get_stats", "lk_autotune", "lk_reserve",
+           "lk_get_view_direction", "lk_get_stats", "lk_autotune", "lk_reserve", "lk_discretize",
            "lk_server_create", "lk_server_destroy", "lk_server_last_error",
            "lk_server_open_session", "lk_server_close_session", "lk_server_submit",
            "lk_server_wait"]
@@ -62,6 +65,12 @@ class Result(ctypes.Structure):
                 ("terms", ctypes.c_double), ("bytes", ctypes.c_int64),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_done", ctypes.c_double)]
+
+
+class DzInfo(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("input_spans", ctypes.c_int64), ("vertices", ctypes.c_int64),
+                ("splits", ctypes.c_int64), ("unfinished", ctypes.c_int64)]
 
 
 class LkError(RuntimeError):
@@ -115,6 +124,9 @@ def load():
         lib.lk_autotune.argtypes = [p, p, ctypes.c_int, p, i32, p, i64, ctypes.c_int, p, p, p,
                                     ctypes.c_char_p, ctypes.POINTER(Tuning), p]
         lib.lk_autotune.restype = st
+        lib.lk_discretize.argtypes = [p, p, p, i32, ctypes.c_int, p, i64, p, i64, p, p,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(DzInfo), p]
+        lib.lk_discretize.restype = st
         lib.lk_reserve.argtypes = [p, i32, i64, i64]
         lib.lk_reserve.restype = st
         lib.lk_server_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, i32, i64, ctypes.c_int,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblk.so")
-SOURCES = ["lk_ds.hip", "lk_aux.hip", "lk_bh.hip", "lk_runtime.hip", "lk_server.hip"]
+SOURCES = ["lk_ds.hip", "lk_aux.hip", "lk_bh.hip", "lk_dz.hip", "lk_runtime.hip", "lk_server.hip"]
 ARCH = os.environ.get("LK_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP translation unit: the

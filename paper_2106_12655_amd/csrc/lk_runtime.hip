@@ -67,6 +67,11 @@ struct lk_ctx {
   DevBuf boxes, vcounts, vprefix;
   DevBuf cc_blk, cc_sup;  // crossing count: projected block and superblock boxes
   DevBuf bh_nodes, bh_lists, bh_counts;  // Barnes-Hut trees, node-pair lists, counts
+  // discretization: two piece arrays and two unprocessed lists (swapped every
+  // pass), piece and group boxes, marks, split prefixes, per-pair item
+  // prefixes, scan partials, and the small per-loop arrays
+  DevBuf dz_piece[2], dz_list[2], dz_pbox, dz_gbox, dz_mark, dz_pre, dz_pair_pre, dz_part, dz_loops;
+  int dz_max_passes = 64;
   double bh_beta = 4.0;
   int bh_order = 2;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
@@ -585,7 +590,9 @@ void lk_destroy(lk_ctx* ctx) {
                     &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
                     &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix,
                     &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
-                    &ctx->bh_counts};
+                    &ctx->bh_counts,  &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
+                    &ctx->dz_list[1], &ctx->dz_pbox, &ctx->dz_gbox, &ctx->dz_mark,
+                    &ctx->dz_pre,     &ctx->dz_pair_pre, &ctx->dz_part, &ctx->dz_loops};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -664,6 +671,10 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       if (v != 1 && v != 2) return ctx->fail(LK_EINVAL, "Barnes-Hut order must be 1 or 2");
       ctx->bh_order = (int)v;
       break;
+    case LK_OPT_DZ_MAX_PASSES:
+      if (v < 1 || v > 1000) return ctx->fail(LK_EINVAL, "discretization passes must be in [1, 1000]");
+      ctx->dz_max_passes = (int)v;
+      return LK_OK;  // no captured graph depends on it
     case LK_OPT_SEGS_PER_LANE_F64:
       if (v != 0 && v != 1 && v != 2)
         return ctx->fail(LK_EINVAL, "FP64 segments per lane must be 0, 1 or 2");
@@ -919,6 +930,151 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
   if (total > capacity)
     return ctx->fail(LK_ECAPACITY, "%lld pairs do not fit capacity %lld", (long long)total,
                      (long long)capacity);
+  return LK_OK;
+}
+
+lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_offsets,
+                        int32_t n_loops, int kind, const int32_t* pairs, int64_t n_pairs,
+                        double* xyz_out, int64_t capacity, int64_t* offsets_out,
+                        uint32_t* loop_flags, int64_t* n_vertices, lk_dz_info* info,
+                        void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (kind != LK_DZ_BSPLINE && kind != LK_DZ_POLYLINE)
+    return ctx->fail(LK_EINVAL, "unknown curve kind %d", kind);
+  if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
+  if (n_pairs < 0 || capacity < 0) return ctx->fail(LK_EINVAL, "negative size");
+  if (!ctrl || !ctrl_offsets || !offsets_out || !n_vertices || (n_pairs > 0 && !pairs) ||
+      (capacity > 0 && !xyz_out))
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return ctx->fail(LK_EBUSY, "lk_discretize synchronises and cannot be captured");
+  }
+  // the point count sizes every buffer: read it (one synchronisation)
+  int64_t ends[2] = {0, 0};
+  LK_HIP(hipMemcpyAsync(&ends[0], ctrl_offsets, 8, hipMemcpyDeviceToHost, s));
+  LK_HIP(hipMemcpyAsync(&ends[1], ctrl_offsets + n_loops, 8, hipMemcpyDeviceToHost, s));
+  LK_HIP(hipStreamSynchronize(s));
+  const int64_t N = ends[1] - ends[0];
+  if (N < 0) return ctx->fail(LK_EINVAL, "offsets decrease");
+  // piece indices are int32 and the split packs two 32-bit counts
+  const int64_t kMaxPieces = (int64_t)1 << 30;
+  if (N > kMaxPieces) return ctx->fail(LK_EINVAL, "more than 2^30 input spans");
+  const size_t L = (size_t)n_loops;
+  // per-loop block: lflags [L] u32 | lsum [L] f64 | 4 offset arrays [L+1] i64 |
+  // totals [4] u64 | lim2 f64
+  const size_t o_lsum = (4 * L + 7) / 8 * 8, o_off = o_lsum + 8 * L;
+  const size_t o_tot = o_off + 4 * 8 * (L + 1), o_lim = o_tot + 32;
+  if ((st = ensure(ctx, ctx->dz_loops, o_lim + 8)) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->dz_pair_pre, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  auto piece_cap = [](const DevBuf& b) { return (int64_t)(b.bytes / lk::kDzBytesPerPiece); };
+  auto pieces_of = [&](const DevBuf& b) {
+    lk::DzPieces P;
+    P.cap = piece_cap(b);
+    P.bz = (double*)b.p;
+    P.loop = (int32_t*)((char*)b.p + 96 * (size_t)P.cap);
+    P.state = (uint32_t*)((char*)b.p + 100 * (size_t)P.cap);
+    return P;
+  };
+  // sizes the buffers of a pass over n pieces of which nu are unprocessed
+  auto size_pass = [&](int64_t n, int64_t nu, int cur) -> lk_status {
+    lk_status r;
+    const size_t want = (size_t)(n + nu > 0 ? n + nu : 1);
+    if ((size_t)piece_cap(ctx->dz_piece[cur ^ 1]) < want &&
+        (r = ensure(ctx, ctx->dz_piece[cur ^ 1], lk::kDzBytesPerPiece * want)) != LK_OK)
+      return r;
+    if ((r = ensure(ctx, ctx->dz_list[cur ^ 1], 4 * (size_t)(2 * nu + 1))) != LK_OK) return r;
+    if ((r = ensure(ctx, ctx->dz_pbox, 48 * (size_t)(nu + 1))) != LK_OK) return r;
+    if ((r = ensure(ctx, ctx->dz_gbox, 48 * (size_t)(nu / lk::kDzGroup + L + 1))) != LK_OK)
+      return r;
+    if ((r = ensure(ctx, ctx->dz_mark, 4 * (size_t)(n + 1))) != LK_OK) return r;
+    if ((r = ensure(ctx, ctx->dz_pre, 8 * (size_t)(n + 1))) != LK_OK) return r;
+    const int64_t nb = (std::max(n, n_pairs) + lk::kDzScanBlock - 1) / lk::kDzScanBlock + 1;
+    return ensure(ctx, ctx->dz_part, 8 * (size_t)nb);
+  };
+  int cur = 0;
+  if ((st = ensure(ctx, ctx->dz_piece[0], lk::kDzBytesPerPiece * (size_t)(N > 0 ? N : 1))) != LK_OK)
+    return st;
+  if ((st = ensure(ctx, ctx->dz_list[0], 4 * (size_t)(N + 1))) != LK_OK) return st;
+  if ((st = size_pass(N, N, cur)) != LK_OK) return st;
+  // every buffer is final for this pass; the pointers are taken after sizing
+  auto args = [&](int c, int64_t n, int64_t nu) {
+    lk::DzArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ctrl = ctrl;
+    a.cp_off = ctrl_offsets;
+    a.n_loops = n_loops;
+    a.kind = kind;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.eps = 2.220446049250313e-16;  // FP64 machine epsilon (2^-52)
+    a.cur = pieces_of(ctx->dz_piece[c]);
+    a.nxt = pieces_of(ctx->dz_piece[c ^ 1]);
+    a.uidx_cur = (int32_t*)ctx->dz_list[c].p;
+    a.uidx_nxt = (int32_t*)ctx->dz_list[c ^ 1].p;
+    char* lb = (char*)ctx->dz_loops.p;
+    a.lflags = (uint32_t*)lb;
+    a.lsum = (double*)(lb + o_lsum);
+    int64_t* offs = (int64_t*)(lb + o_off);
+    a.aoff_cur = offs + (c ? 2 : 0) * (L + 1);
+    a.aoff_nxt = offs + (c ? 0 : 2) * (L + 1);
+    a.uoff_cur = offs + (c ? 3 : 1) * (L + 1);
+    a.uoff_nxt = offs + (c ? 1 : 3) * (L + 1);
+    a.totals = (uint64_t*)(lb + o_tot);
+    a.lim2 = (double*)(lb + o_lim);
+    a.cap_u = (int64_t)(ctx->dz_pbox.bytes / 48);
+    a.pbox = (double*)ctx->dz_pbox.p;
+    a.cap_g = (int64_t)(ctx->dz_gbox.bytes / 48);
+    a.gbox = (double*)ctx->dz_gbox.p;
+    a.mark = (uint32_t*)ctx->dz_mark.p;
+    a.pre = (uint64_t*)ctx->dz_pre.p;
+    a.pair_pre = (int64_t*)ctx->dz_pair_pre.p;
+    a.part = (uint64_t*)ctx->dz_part.p;
+    a.n = n;
+    a.n_u = nu;
+    return a;
+  };
+  LK_HIP(lk::launch_dz_setup(args(cur, N, N), N, s));
+  int64_t n = N, nu = N;
+  int passes = 0;
+  int64_t splits = 0;
+  while (nu > 0 && passes < ctx->dz_max_passes) {
+    if ((st = size_pass(n, nu, cur)) != LK_OK) return st;
+    lk::DzArgs a = args(cur, n, nu);
+    LK_HIP(lk::launch_dz_pass(a, ctx->n_cu, s));
+    uint64_t tot = 0;
+    LK_HIP(hipMemcpyAsync(&tot, a.totals, 8, hipMemcpyDeviceToHost, s));
+    LK_HIP(hipStreamSynchronize(s));
+    const int64_t n2 = (int64_t)(tot >> 32), nu2 = (int64_t)(tot & 0xffffffffull);
+    splits += n2 - n;
+    n = n2;
+    nu = nu2;
+    cur ^= 1;
+    ++passes;
+    if (n > kMaxPieces)
+      return ctx->fail(LK_ENOMEM, "refinement exceeds 2^30 pieces (curves nearly touch?)");
+  }
+  *n_vertices = n;
+  lk::DzArgs a = args(cur, n, nu);
+  LK_HIP(lk::launch_dz_finish(a, xyz_out, capacity, offsets_out, loop_flags, s));
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->passes = passes;
+    info->input_spans = N;
+    info->vertices = n;
+    info->splits = splits;
+    info->unfinished = nu;
+  }
+  if (n > capacity) {
+    LK_HIP(hipStreamSynchronize(s));
+    return ctx->fail(LK_ECAPACITY, "%lld vertices do not fit capacity %lld", (long long)n,
+                     (long long)capacity);
+  }
   return LK_OK;
 }
 
