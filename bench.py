@@ -28,7 +28,10 @@ Prints ONE JSON line.  Options:
                          mode of the headline value (default mixed); with mixed,
                          plain FP64, the crossing count (Alg. 4) and Barnes-Hut
                          (Alg. 6) are timed on the same input and reported beside it
-  --no-plain, --no-crossings, --no-bh   skip those companion legs
+  --no-plain, --no-crossings, --no-bh, --no-dz   skip those companion legs
+                         (dz: the discretization of Alg. 3, timed on the knit
+                         workload's B-spline control points, 314k spans)
+  --dz-only              only the discretization leg (profiling)
   --no-cpu-baseline      skip the oracle leg
   --no-tune              keep the default kernel configuration
   --gpus N               only N = 1 is supported (one GPU per process)
@@ -112,6 +115,10 @@ def parse():
     ap.add_argument("--no-crossings", action="store_true",
                     help="skip the crossing-count companion run")
     ap.add_argument("--no-bh", action="store_true", help="skip the Barnes-Hut companion run")
+    ap.add_argument("--no-dz", action="store_true",
+                    help="skip the discretization companion run (knit B-spline rows)")
+    ap.add_argument("--dz-only", action="store_true",
+                    help="time only the discretization leg (for profiling it)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
@@ -213,8 +220,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ls = inputs.config(args.config, args.seed)
     ctx = lk.Context(0)
+    if args.dz_only:
+        line = {"discretization": time_discretize(ctx, args, lk, inputs)}
+        ctx.close()
+        print(json.dumps(line), flush=True)
+        return
+    ls = inputs.config(args.config, args.seed)
     xyz = torch.from_numpy(ls.xyz).cuda()
     off = torch.from_numpy(ls.offsets).cuda()
     torch.cuda.synchronize()
@@ -345,8 +357,72 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)
+    if not args.no_dz:
+        line["discretization"] = time_discretize(ctx, args, lk, inputs)
     ctx.close()
     print(json.dumps(line), flush=True)
+
+
+def time_discretize(ctx, args, lk, inputs):
+    """Alg. 3 on the knit workload's control polygons (2,000 closed uniform
+    cubic B-spline rows, 314k spans): wall time per lk_discretize call (it
+    synchronises once per pass), the output size, and the linking numbers of
+    the output polylines (MIXED direct sum) against the construction's.  The
+    oracle's discretization is timed on a bounded sample: the first rows of
+    the same workload."""
+    import torch
+    import oracle
+    k = inputs.knit(args.seed, per_span=0, dtype=np.float64)
+    x = torch.from_numpy(k.xyz).cuda()
+    o = torch.from_numpy(k.offsets).cuda()
+    pr = ctx.build_pairs(x, o)
+    cap = 4 * len(k.xyz) + 1024
+    for _ in range(max(args.warmup, 1)):
+        out = ctx.discretize(x, o, pr, "bspline", cap)
+    torch.cuda.synchronize()
+    steps = max(args.steps, 1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.discretize(x, o, pr, "bspline", cap)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    xyz, off, flags, info = out
+    _, lk_int, _ = ctx.direct_sum(xyz, off, pr, "mixed")
+    pairs = pr.cpu().numpy()
+    exp = k.expected_for(pairs)
+    got = lk_int.cpu().numpy()
+    # the polyline through the knots (one vertex per span) for contrast
+    knots = torch.from_numpy(inputs.knit(args.seed, per_span=1, dtype=np.float64).xyz).cuda()
+    _, lk_knots, _ = ctx.direct_sum(knots, o, pr, "mixed")
+    leg = {
+        "workload": "knit control polygons: %d closed B-spline rows, %d spans, %d pairs" % (
+            k.n_loops, len(k.xyz), len(pairs)),
+        "value": len(k.xyz) / (ms * 1e-3), "unit": "input spans/s", "ms_per_call": ms,
+        "steps": steps, "passes": info["passes"], "input_spans": info["input_spans"],
+        "vertices": info["vertices"], "splits": info["splits"],
+        "loops_flagged": int((flags.cpu().numpy() != 0).sum()),
+        "int_mismatch_vs_construction": int(np.sum(got != exp)),
+        "knot_polyline_int_mismatch_vs_construction": int(np.sum(lk_knots.cpu().numpy() != exp)),
+        "linked_pairs": int(np.sum(exp != 0)),
+    }
+    if not args.no_cpu_baseline:
+        sub = inputs.knit(args.seed, n_loops=150, per_span=0, dtype=np.float64)
+        spr = oracle.aabb_pairs(sub.xyz, sub.offsets)
+        t0 = time.perf_counter()
+        ox, oo, of = oracle.discretize(sub.xyz, sub.offsets, spr)
+        dt = time.perf_counter() - t0
+        g = ctx.discretize(torch.from_numpy(sub.xyz).cuda(), torch.from_numpy(sub.offsets).cuda(),
+                           torch.from_numpy(spr).cuda())
+        leg["cpu_baseline"] = {
+            "value": len(sub.xyz) / dt, "unit": "input spans/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d rows of the same workload (%d spans, %d pairs)" % (
+                sub.n_loops, len(sub.xyz), len(spr)),
+            "seconds": dt,
+            "bitwise_equal_gpu": bool(np.array_equal(g[1].cpu().numpy(), oo)
+                                      and np.array_equal(g[0].cpu().numpy().view(np.uint64),
+                                                         ox.view(np.uint64))),
+        }
+    return leg
 
 
 def run_serving(args):

@@ -15,7 +15,10 @@
 //   split   a device scan over all pieces of (pieces out, unprocessed out):
 //           final pieces are copied, unmarked unprocessed pieces become
 //           final, marked pieces are replaced by their two de Casteljau
-//           halves at t = 1/2, which form the next unprocessed list;
+//           halves at t = 1/2, which form the next unprocessed list.  The
+//           ordered array carries only start points, loops and states; the
+//           control points live in the compact unprocessed list, so a final
+//           piece costs 32 bytes per pass instead of 104;
 //   offsets the per-loop offsets of the new array and list.
 // The host reads the new counts after each pass (one synchronisation) and
 // sizes the next launches from them.  Arithmetic is FP64 without fused
@@ -97,17 +100,27 @@ __device__ __forceinline__ int64_t dz_slot(const int64_t* uoff, int32_t i, int64
   return uoff[i] / kDzGroup + i + g;
 }
 
-// Largest loop i with uoff[i] / 64 + i <= slot.
-__device__ __forceinline__ int32_t dz_slot_loop(const int64_t* uoff, int32_t L, int64_t slot) {
-  int32_t lo = 0, hi = L;
+// Largest i in [0, n) with key(i) <= x, for a non-decreasing key with
+// key(0) <= x and a wave-uniform x: the wavefront probes 64 evenly spaced
+// keys per step (the lanes that pass form a prefix), so a search over n
+// entries takes log64(n) dependent loads instead of log2(n).
+template <typename Key>
+__device__ __forceinline__ int64_t wave_search(int64_t n, int64_t x, Key key) {
+  const int lane = threadIdx.x & 63;
+  int64_t lo = 0, hi = n;
   while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (uoff[mid] / kDzGroup + mid <= slot)
-      lo = mid;
-    else
-      hi = mid;
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t idx = lo + lane * step;
+    const uint64_t m = __ballot(idx < hi && key(idx) <= x);
+    lo += (int64_t)(63 - __builtin_clzll(m)) * step;
+    hi = lo + step < hi ? lo + step : hi;
   }
   return lo;
+}
+
+// Largest loop i with uoff[i] / 64 + i <= slot.
+__device__ __forceinline__ int32_t dz_slot_loop(const int64_t* uoff, int32_t L, int64_t slot) {
+  return (int32_t)wave_search(L, slot, [&](int64_t i) { return uoff[i] / kDzGroup + i; });
 }
 
 // Squared diagonal of the box of four points (min/max in point order, then
@@ -127,19 +140,28 @@ __device__ __forceinline__ double diag2(const double (&b)[4][3]) {
   return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
 }
 
-__device__ __forceinline__ void load_piece(const DzPieces& P, int64_t i, double (&b)[4][3]) {
+// Control points of unprocessed piece u.
+__device__ __forceinline__ void load_open(const double* ubz, int64_t cap, int64_t u,
+                                          double (&b)[4][3]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) b[k][q] = P.bz[(3 * k + q) * P.cap + i];
+    for (int q = 0; q < 3; ++q) b[k][q] = ubz[(3 * k + q) * cap + u];
 }
 
-__device__ __forceinline__ void store_piece(const DzPieces& P, int64_t i, const double (&b)[4][3],
-                                            int32_t loop, uint32_t state) {
+__device__ __forceinline__ void store_open(double* ubz, int64_t cap, int64_t u,
+                                           const double (&b)[4][3]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) P.bz[(3 * k + q) * P.cap + i] = b[k][q];
+    for (int q = 0; q < 3; ++q) ubz[(3 * k + q) * cap + u] = b[k][q];
+}
+
+// Entry i of the ordered array: start point, loop, state.
+__device__ __forceinline__ void store_piece(const DzPieces& P, int64_t i, const double* x0,
+                                            int32_t loop, uint32_t state) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) P.start[q * P.cap + i] = x0[q];
   P.loop[i] = loop;
   P.state[i] = state;
 }
@@ -310,8 +332,8 @@ __global__ __launch_bounds__(kThreads) void dz_init_k(DzArgs A, int64_t n_points
       b[3][c] = (q1[c] + 4.0 * q2[c] + q3[c]) / 6.0;
     }
   }
-  store_piece(A.cur, q, b, i, 0u);
-  A.uidx_cur[q] = (int32_t)q;
+  store_piece(A.cur, q, b[0], i, (uint32_t)q);
+  store_open(A.ubz_cur, A.cap_o, q, b);
   if (diag2(b) < A.lim2[0]) atomicOr(&A.lflags[i], kFlagBadloop);
 }
 
@@ -330,9 +352,8 @@ __global__ __launch_bounds__(kThreads) void dz_boxes_k(DzArgs A, int64_t n_slots
     if (g < dz_groups(nu)) {
       const int64_t u = u0 + g * kDzGroup + lane;
       if (u < u0 + nu) {
-        const int32_t pc = A.uidx_cur[u];
         double b[4][3];
-        load_piece(A.cur, pc, b);
+        load_open(A.ubz_cur, A.cap_o, u, b);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           double lo = b[0][q], hi = b[0][q];
@@ -346,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void dz_boxes_k(DzArgs A, int64_t n_slots
           A.pbox[q * A.cap_u + u] = lo;
           A.pbox[(3 + q) * A.cap_u + u] = hi;
         }
-        A.mark[pc] = 0u;
+        A.mark[u] = 0u;
       }
     }
 #pragma unroll
@@ -396,34 +417,54 @@ __global__ __launch_bounds__(kThreads) void dz_items_reduce_k(DzArgs A) {
 
 __global__ __launch_bounds__(kThreads) void dz_items_apply_k(DzArgs A) {
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  int32_t a, b;
+  int32_t a = 0, b = 0;
   const uint64_t v = p < A.n_pairs ? (uint64_t)pair_items(A, p, &a, &b) : 0;
   uint64_t t;
   const uint64_t e = block_excl_scan(v, &t) + A.part[blockIdx.x];
-  if (p < A.n_pairs) A.pair_pre[p] = (int64_t)e;
+  if (p < A.n_pairs) {
+    A.pair_pre[p] = (int64_t)e;
+    A.pair_ab[2 * p] = a;
+    A.pair_ab[2 * p + 1] = b;
+  }
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const int64_t v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ Box readlane_box(const Box& b, int l) {
+  Box r;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    r.lo[q] = readlane_d(b.lo[q], l);
+    r.hi[q] = readlane_d(b.hi[q], l);
+  }
+  return r;
 }
 
 // One wavefront per (pair, group of a): lane t holds piece t of the group;
 // the groups of b whose boxes overlap the group's box are visited in turn,
-// and inside them only the pieces of b whose boxes overlap it.
+// and inside them only the pieces of b whose boxes overlap it, each broadcast
+// from its lane.  A wavefront takes a contiguous run of items, so it finds
+// its first pair by one search and then steps through the prefix.
 __global__ __launch_bounds__(kThreads) void dz_test_k(DzArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kThreads) >> 6;
   const int64_t P = A.n_pairs;
   const int64_t total = P > 0 ? A.pair_pre[P] : 0;
-  for (int64_t w = wave; w < total; w += nwaves) {
-    int64_t lo = 0, hi = P;  // largest p with pair_pre[p] <= w
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (A.pair_pre[mid] <= w)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    int32_t a = 0, b = 0;
-    pair_items(A, lo, &a, &b);
-    const int64_t ga = w - A.pair_pre[lo];
+  const int64_t chunk = (total + nwaves - 1) / nwaves;
+  const int64_t w0 = wave * chunk;
+  const int64_t w1 = w0 + chunk < total ? w0 + chunk : total;
+  if (w0 >= w1) return;
+  int64_t p = wave_search(P, w0, [&](int64_t i) { return A.pair_pre[i]; });
+  for (int64_t w = w0; w < w1; ++w) {
+    while (A.pair_pre[p + 1] <= w) ++p;  // pair_pre[P] = total > w
+    const int32_t a = A.pair_ab[2 * p], b = A.pair_ab[2 * p + 1];
+    const int64_t ga = w - A.pair_pre[p];
     const int64_t ua0 = A.uoff_cur[a] + ga * kDzGroup;
     const int64_t ua_end = A.uoff_cur[a + 1];
     const bool has_a = ua0 + lane < ua_end;
@@ -444,19 +485,19 @@ __global__ __launch_bounds__(kThreads) void dz_test_k(DzArgs A) {
         const bool has_b = ub0 + lane < ub_end;
         const Box pb = has_b ? load_box(A.pbox, A.cap_u, ub0 + lane) : empty_box();
         uint64_t bm = __ballot(has_b && overlap(pb, gA));
-        bool mb = false;
+        uint64_t hit = 0;  // b pieces that some a piece overlaps
         while (bm) {
           const int kk = __builtin_ctzll(bm);
           bm &= bm - 1;
-          const Box bk = shfl_box(pb, kk);
+          const Box bk = readlane_box(pb, kk);
           const bool ov = has_a && overlap(pa, bk);
           ma |= ov;
-          if (__ballot(ov) != 0 && lane == kk) mb = true;
+          if (__ballot(ov) != 0) hit |= 1ull << kk;
         }
-        if (mb) A.mark[A.uidx_cur[ub0 + lane]] = 1u;
+        if ((hit >> lane) & 1ull) A.mark[ub0 + lane] = 1u;
       }
     }
-    if (ma) A.mark[A.uidx_cur[ua0 + lane]] = 1u;
+    if (ma) A.mark[ua0 + lane] = 1u;
   }
 }
 
@@ -468,10 +509,11 @@ __device__ __forceinline__ uint64_t split_value(const DzArgs& A, int64_t q, bool
   *marked = false;
   *flagged = false;
   if (q >= A.n) return 0;
-  if ((A.cur.state[q] & 1u) || A.mark[q] == 0u) return 1ull << 32;
+  const uint32_t st = A.cur.state[q];
+  if (st == kDzFinal || A.mark[st] == 0u) return 1ull << 32;
   *marked = true;
   double x[4][3];
-  load_piece(A.cur, q, x);
+  load_open(A.ubz_cur, A.cap_o, st, x);
   split_half(x, A.kind == 1, l, r);
   const double lim2 = A.lim2[0];
   *flagged = diag2(l) < lim2 || diag2(r) < lim2;
@@ -499,18 +541,19 @@ __global__ __launch_bounds__(kThreads) void dz_split_apply_k(DzArgs A) {
   const int64_t np = (int64_t)(e >> 32), nu = (int64_t)(e & 0xffffffffull);
   const int32_t loop = A.cur.loop[q];
   if (!mk) {
-    double x[4][3];
-    load_piece(A.cur, q, x);
-    store_piece(A.nxt, np, x, loop, 1u);
+    double x0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x0[c] = A.cur.start[c * A.cur.cap + q];
+    store_piece(A.nxt, np, x0, loop, kDzFinal);
     return;
   }
-  store_piece(A.nxt, np, l, loop, fl ? 1u : 0u);
-  store_piece(A.nxt, np + 1, r, loop, fl ? 1u : 0u);
+  store_piece(A.nxt, np, l[0], loop, fl ? kDzFinal : (uint32_t)nu);
+  store_piece(A.nxt, np + 1, r[0], loop, fl ? kDzFinal : (uint32_t)(nu + 1));
   if (fl) {
     atomicOr(&A.lflags[loop], kFlagIntersect);
   } else {
-    A.uidx_nxt[nu] = (int32_t)np;
-    A.uidx_nxt[nu + 1] = (int32_t)(np + 1);
+    store_open(A.ubz_nxt, A.cap_on, nu, l);
+    store_open(A.ubz_nxt, A.cap_on, nu + 1, r);
   }
 }
 
@@ -525,8 +568,8 @@ __global__ __launch_bounds__(kThreads) void dz_offsets_k(DzArgs A) {
 
 // ---------------------------------------------------------------- finish
 __global__ __launch_bounds__(kThreads) void dz_leftover_k(DzArgs A) {
-  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (u < A.n_u) atomicOr(&A.lflags[A.cur.loop[A.uidx_cur[u]]], kFlagIntersect);
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (q < A.n && A.cur.state[q] != kDzFinal) atomicOr(&A.lflags[A.cur.loop[q]], kFlagIntersect);
 }
 
 __global__ __launch_bounds__(kThreads) void dz_output_k(DzArgs A, double* xyz, int64_t capacity,
@@ -534,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void dz_output_k(DzArgs A, double* xyz, i
   const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (v < A.n && A.n <= capacity) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xyz[3 * v + q] = A.cur.bz[q * A.cur.cap + v];
+    for (int q = 0; q < 3; ++q) xyz[3 * v + q] = A.cur.start[q * A.cur.cap + v];
   }
   if (v <= A.n_loops) off[v] = A.aoff_cur[v];
   if (flags && v < A.n_loops) flags[v] = A.lflags[v];
@@ -561,7 +604,7 @@ hipError_t launch_dz_pass(const DzArgs& a, int n_cu, hipStream_t s) {
     dz_items_reduce_k<<<(unsigned)pb, kThreads, 0, s>>>(a);
     dz_scan_part_k<<<1, 1024, 0, s>>>(a.part, pb, nullptr, a.pair_pre + a.n_pairs);
     dz_items_apply_k<<<(unsigned)pb, kThreads, 0, s>>>(a);
-    dz_test_k<<<(unsigned)(8 * n_cu), kThreads, 0, s>>>(a);
+    dz_test_k<<<(unsigned)(32 * n_cu), kThreads, 0, s>>>(a);
   }
   const int64_t qb = blocks_for(a.n);
   dz_split_reduce_k<<<(unsigned)qb, kThreads, 0, s>>>(a);
@@ -573,7 +616,7 @@ hipError_t launch_dz_pass(const DzArgs& a, int n_cu, hipStream_t s) {
 
 hipError_t launch_dz_finish(const DzArgs& a, double* xyz_out, int64_t capacity, int64_t* off_out,
                             uint32_t* flags_out, hipStream_t s) {
-  if (a.n_u > 0) dz_leftover_k<<<(unsigned)blocks_for(a.n_u), kThreads, 0, s>>>(a);
+  if (a.n_u > 0) dz_leftover_k<<<(unsigned)blocks_for(a.n), kThreads, 0, s>>>(a);
   const int64_t m = (a.n > a.n_loops + 1 ? a.n : a.n_loops + 1);
   dz_output_k<<<(unsigned)blocks_for(m), kThreads, 0, s>>>(a, xyz_out, capacity, off_out,
                                                             flags_out);

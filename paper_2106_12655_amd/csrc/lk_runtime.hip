@@ -70,7 +70,8 @@ struct lk_ctx {
   // discretization: two piece arrays and two unprocessed lists (swapped every
   // pass), piece and group boxes, marks, split prefixes, per-pair item
   // prefixes, scan partials, and the small per-loop arrays
-  DevBuf dz_piece[2], dz_list[2], dz_pbox, dz_gbox, dz_mark, dz_pre, dz_pair_pre, dz_part, dz_loops;
+  DevBuf dz_piece[2], dz_list[2], dz_pbox, dz_gbox, dz_mark, dz_pre, dz_pair_pre, dz_pair_ab,
+      dz_part, dz_loops;
   int dz_max_passes = 64;
   double bh_beta = 4.0;
   int bh_order = 2;
@@ -592,7 +593,8 @@ void lk_destroy(lk_ctx* ctx) {
                     &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
                     &ctx->bh_counts,  &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
                     &ctx->dz_list[1], &ctx->dz_pbox, &ctx->dz_gbox, &ctx->dz_mark,
-                    &ctx->dz_pre,     &ctx->dz_pair_pre, &ctx->dz_part, &ctx->dz_loops};
+                    &ctx->dz_pre,     &ctx->dz_pair_pre, &ctx->dz_pair_ab, &ctx->dz_part,
+                    &ctx->dz_loops};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
@@ -972,35 +974,44 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
   const size_t o_tot = o_off + 4 * 8 * (L + 1), o_lim = o_tot + 32;
   if ((st = ensure(ctx, ctx->dz_loops, o_lim + 8)) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->dz_pair_pre, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  if ((st = ensure(ctx, ctx->dz_pair_ab, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
   auto piece_cap = [](const DevBuf& b) { return (int64_t)(b.bytes / lk::kDzBytesPerPiece); };
+  auto open_cap = [](const DevBuf& b) { return (int64_t)(b.bytes / lk::kDzBytesPerOpen); };
   auto pieces_of = [&](const DevBuf& b) {
     lk::DzPieces P;
     P.cap = piece_cap(b);
-    P.bz = (double*)b.p;
-    P.loop = (int32_t*)((char*)b.p + 96 * (size_t)P.cap);
-    P.state = (uint32_t*)((char*)b.p + 100 * (size_t)P.cap);
+    P.start = (double*)b.p;
+    P.loop = (int32_t*)((char*)b.p + 24 * (size_t)P.cap);
+    P.state = (uint32_t*)((char*)b.p + 28 * (size_t)P.cap);
     return P;
   };
   // sizes the buffers of a pass over n pieces of which nu are unprocessed
+  // (the current arrays already hold them; the next ones are written whole)
   auto size_pass = [&](int64_t n, int64_t nu, int cur) -> lk_status {
     lk_status r;
     const size_t want = (size_t)(n + nu > 0 ? n + nu : 1);
     if ((size_t)piece_cap(ctx->dz_piece[cur ^ 1]) < want &&
         (r = ensure(ctx, ctx->dz_piece[cur ^ 1], lk::kDzBytesPerPiece * want)) != LK_OK)
       return r;
-    if ((r = ensure(ctx, ctx->dz_list[cur ^ 1], 4 * (size_t)(2 * nu + 1))) != LK_OK) return r;
+    if ((size_t)open_cap(ctx->dz_list[cur ^ 1]) < (size_t)(2 * nu + 1) &&
+        (r = ensure(ctx, ctx->dz_list[cur ^ 1], lk::kDzBytesPerOpen * (size_t)(2 * nu + 1))) !=
+            LK_OK)
+      return r;
     if ((r = ensure(ctx, ctx->dz_pbox, 48 * (size_t)(nu + 1))) != LK_OK) return r;
     if ((r = ensure(ctx, ctx->dz_gbox, 48 * (size_t)(nu / lk::kDzGroup + L + 1))) != LK_OK)
       return r;
-    if ((r = ensure(ctx, ctx->dz_mark, 4 * (size_t)(n + 1))) != LK_OK) return r;
+    if ((r = ensure(ctx, ctx->dz_mark, 4 * (size_t)(nu + 1))) != LK_OK) return r;
     if ((r = ensure(ctx, ctx->dz_pre, 8 * (size_t)(n + 1))) != LK_OK) return r;
     const int64_t nb = (std::max(n, n_pairs) + lk::kDzScanBlock - 1) / lk::kDzScanBlock + 1;
     return ensure(ctx, ctx->dz_part, 8 * (size_t)nb);
   };
   int cur = 0;
-  if ((st = ensure(ctx, ctx->dz_piece[0], lk::kDzBytesPerPiece * (size_t)(N > 0 ? N : 1))) != LK_OK)
+  if ((size_t)piece_cap(ctx->dz_piece[0]) < (size_t)(N > 0 ? N : 1) &&
+      (st = ensure(ctx, ctx->dz_piece[0], lk::kDzBytesPerPiece * (size_t)(N > 0 ? N : 1))) != LK_OK)
     return st;
-  if ((st = ensure(ctx, ctx->dz_list[0], 4 * (size_t)(N + 1))) != LK_OK) return st;
+  if ((size_t)open_cap(ctx->dz_list[0]) < (size_t)(N + 1) &&
+      (st = ensure(ctx, ctx->dz_list[0], lk::kDzBytesPerOpen * (size_t)(N + 1))) != LK_OK)
+    return st;
   if ((st = size_pass(N, N, cur)) != LK_OK) return st;
   // every buffer is final for this pass; the pointers are taken after sizing
   auto args = [&](int c, int64_t n, int64_t nu) {
@@ -1015,8 +1026,10 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
     a.eps = 2.220446049250313e-16;  // FP64 machine epsilon (2^-52)
     a.cur = pieces_of(ctx->dz_piece[c]);
     a.nxt = pieces_of(ctx->dz_piece[c ^ 1]);
-    a.uidx_cur = (int32_t*)ctx->dz_list[c].p;
-    a.uidx_nxt = (int32_t*)ctx->dz_list[c ^ 1].p;
+    a.ubz_cur = (double*)ctx->dz_list[c].p;
+    a.ubz_nxt = (double*)ctx->dz_list[c ^ 1].p;
+    a.cap_o = open_cap(ctx->dz_list[c]);
+    a.cap_on = open_cap(ctx->dz_list[c ^ 1]);
     char* lb = (char*)ctx->dz_loops.p;
     a.lflags = (uint32_t*)lb;
     a.lsum = (double*)(lb + o_lsum);
@@ -1034,6 +1047,7 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
     a.mark = (uint32_t*)ctx->dz_mark.p;
     a.pre = (uint64_t*)ctx->dz_pre.p;
     a.pair_pre = (int64_t*)ctx->dz_pair_pre.p;
+    a.pair_ab = (int32_t*)ctx->dz_pair_ab.p;
     a.part = (uint64_t*)ctx->dz_part.p;
     a.n = n;
     a.n_u = nu;
