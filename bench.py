@@ -65,7 +65,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 KERNEL_SOURCES = ("lk_ds.hip", "lk_internal.h", "atan_poly.h")
 TRAFFIC = {
     ("chainmail", "mixed"): {
-        "sources": "ae0c33d4516939ba",
+        "sources": "a08de439717e641a",
         "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "small_batch": 2,
                    "waves_per_cu": 0, "atan_form": 2},
         "fetch_kib": 23241.8, "write_kib": 2494.1, "fetch_scale": 2.000, "write_scale": 1.000,

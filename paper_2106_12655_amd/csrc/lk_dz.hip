@@ -23,7 +23,7 @@
 // The host reads the new counts after each pass (one synchronisation) and
 // sizes the next launches from them.  Arithmetic is FP64 without fused
 // multiply-adds, so every piece is bitwise the one the plain definition gives.
-#include "lk_internal.h"
+#include "lk_dz.h"
 
 #pragma clang fp contract(off)
 

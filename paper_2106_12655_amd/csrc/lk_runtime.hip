@@ -27,6 +27,7 @@
 
 #include "../../include/lk.h"
 #include "lk_internal.h"
+#include "lk_dz.h"
 
 namespace {
 
