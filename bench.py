@@ -60,12 +60,13 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 # of the chainmail command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
 # averaged over the timed dispatches), each scaled by what the same counter read
 # for one 256 MiB device copy in that run (fetch x2.000, write x1.000).  A
-# record only holds for the kernel sources it was taken on and the tuned launch
-# configuration: anything else reports traffic as null.
-KERNEL_SOURCES = ("lk_ds.hip", "lk_internal.h", "atan_poly.h")
+# record only holds for the machine code it was taken on (the fingerprint of
+# the kernel's gfx950 assembly that the build writes to liblk.kernels.json)
+# and for the tuned launch configuration: anything else reports traffic as null.
 TRAFFIC = {
     ("chainmail", "mixed"): {
-        "sources": "a08de439717e641a",
+        "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4EEEvNS_6DsArgsE",
+        "isa": "f19f906333a9a1db",
         "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "small_batch": 2,
                    "waves_per_cu": 0, "atan_form": 2},
         "fetch_kib": 23241.8, "write_kib": 2494.1, "fetch_scale": 2.000, "write_scale": 1.000,
@@ -82,20 +83,20 @@ WORKLOADS = {
 }
 
 
-def kernel_digest() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2106_12655_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_isa(symbol: str):
+    """Fingerprint of a kernel's assembly in the built library, or None."""
+    try:
+        with open(os.path.join(ROOT, "paper_2106_12655_amd", "liblk.kernels.json")) as fh:
+            return json.load(fh)["kernels"].get(symbol)
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def measured_traffic(config: str, mode: str, tuned):
     """HBM bytes per launch from the recorded counters, or None when the record
-    does not match the kernel sources or the launch configuration."""
+    does not match the kernel's machine code or the launch configuration."""
     rec = TRAFFIC.get((config, mode))
-    if rec is None or tuned is None or rec["sources"] != kernel_digest():
+    if rec is None or tuned is None or kernel_isa(rec["kernel"]) != rec["isa"]:
         return None
     if any(tuned.get(k) != v for k, v in rec["config"].items()):
         return None

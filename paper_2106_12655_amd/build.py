@@ -31,12 +31,73 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+# The direct-sum kernels' assembly is kept (-save-temps) and fingerprinted, so
+# that measurements recorded for one build of a kernel can be matched to the
+# exact machine code they were taken on.
+ISA_SOURCE = "lk_ds.hip"
+ISA_FILE = os.path.join(HERE, "liblk.kernels.json")
+ISA_KERNELS = "ds_persistent"
+
+
 def _compile(src: str, obj: str) -> None:
     cmd = [_hipcc(), *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if src == ISA_SOURCE:
+        cmd.append("-save-temps=obj")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed on %s" % src)
+
+
+def kernel_isa_digests(asm_text: str, match: str = ISA_KERNELS) -> dict:
+    """SHA-256 (16 hex digits) of each kernel's gfx950 assembly whose symbol
+    contains ``match``: the function body from its label to its end marker
+    plus its .amdhsa_kernel descriptor (registers, LDS, scratch), without
+    comments.  Local labels are renumbered by first appearance, so code added
+    elsewhere in the file does not change a kernel's digest."""
+    import hashlib
+    import re
+    lines = asm_text.splitlines()
+    out = {}
+    label = re.compile(r"\.L[A-Za-z_]*\d+(?:_\d+)?")
+    for i, line in enumerate(lines):
+        m = re.match(r"^(_Z\w+):", line)
+        if not m or match not in m.group(1):
+            continue
+        sym = m.group(1)
+        body = []
+        for ln in lines[i + 1:]:
+            if re.match(r"^\.Lfunc_end\d+:", ln):
+                break
+            body.append(ln)
+        desc, inside = [], False
+        for ln in lines:
+            t = ln.strip()
+            if t == ".amdhsa_kernel " + sym:
+                inside = True
+            if inside:
+                desc.append(t)
+                if t == ".end_amdhsa_kernel":
+                    break
+        names = {}
+
+        def ren(mm):
+            return ".L%d" % names.setdefault(mm.group(0), len(names))
+        code = [ln.split(";", 1)[0].strip() for ln in body + desc]  # comments vary by build mode
+        text = "\n".join(label.sub(ren, ln) for ln in code if ln)
+        out[sym] = hashlib.sha256(text.encode()).hexdigest()[:16]
+    return out
+
+
+def _write_isa_digests(objdir: str) -> None:
+    import json
+    asm = os.path.join(objdir, ISA_SOURCE.replace(".hip", "") + "-hip-amdgcn-amd-amdhsa-%s.s" % ARCH)
+    with open(asm) as fh:
+        dig = kernel_isa_digests(fh.read())
+    tmp = ISA_FILE + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump({"arch": ARCH, "kernels": dig}, fh, indent=1, sort_keys=True)
+    os.replace(tmp, ISA_FILE)
 
 
 def build(verbose: bool = False) -> str:
@@ -53,6 +114,7 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of liblk.so failed")
     os.replace(tmp, LIB)
+    _write_isa_digests(objdir)
     if verbose:
         print("built", LIB)
     return LIB
