@@ -226,6 +226,21 @@ def bh_pair(L, K, beta: float, order: int = 2, leaf: int = 64, arity: int = 8):
     return v, err.value
 
 
+def bh_pair_adaptive(L, K, beta_init: float = 2.0, beta_max: float = 10.0, target: float = 0.2,
+                     order: int = 2, leaf: int = 64, arity: int = 8):
+    """The adaptive beta of Sec. 3.4.4: Barnes-Hut at beta_init; from its
+    next-order error estimate E, beta_t = (E / target)^(1/4) beta_init; if
+    beta_t > beta_init, evaluate again at min(beta_t, beta_max).  Returns
+    ``(value, first_estimate, beta_used)``."""
+    v, e = bh_pair(L, K, beta_init, order, leaf, arity)
+    bt = (e / target) ** 0.25 * beta_init
+    if bt > beta_init:
+        beta = min(bt, beta_max)
+        v, _ = bh_pair(L, K, beta, order, leaf, arity)
+        return v, e, beta
+    return v, e, beta_init
+
+
 def bh_node_moments(P, a: int, b: int):
     """Centre, R and moments (c_M, C_D, C_Q) of the node covering segments
     [a, b) of loop P, computed directly from its segments."""

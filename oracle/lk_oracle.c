@@ -49,7 +49,7 @@
  * A global mutation switch (lko_set_mutation) plants deliberate mistakes for
  * the tests that prove the pins catch them; it is 0 (off) by default
  * (1-6: the Eq. 4 term and the pair sum; 7, 8: the Barnes-Hut expansion;
- * 9-12: the discretization of Alg. 3).
+ * 9-12: the discretization of Alg. 3; 13: the Barnes-Hut error estimate).
  */
 #include <math.h>
 #include <pthread.h>
@@ -670,7 +670,8 @@ static double bh_far(const bh_node* u, const bh_node* v, int order, double* err)
   if (err) {
     const double nM1 = norm3(u->M), nM2 = norm3(v->M);
     const double nD1 = fro(u->D, 9), nD2 = fro(v->D, 9), nQ1 = fro(u->Q, 27), nQ2 = fro(v->Q, 27);
-    *err += f / d5 * (u->R * nM2 * nQ1 + v->R * nM1 * nQ2 + 3.0 * (nD1 * nQ2 + nQ1 * nD2));
+    const double cross = (g_mutation == 13) ? 0.0 : 3.0 * (nD1 * nQ2 + nQ1 * nD2); /* mutation 13 */
+    *err += f / d5 * (u->R * nM2 * nQ1 + v->R * nM1 * nQ2 + cross);
   }
   return -(t1 + t2 + t3);
 }

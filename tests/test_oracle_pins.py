@@ -414,11 +414,52 @@ def pin_dz_termination():
     return None
 
 
+def pin_bh_estimate():
+    """The next-order error estimate of Sec. 3.4.4 (k = 1/(4 pi)): at least
+    the actual error of the quadrupole expansion, falling as beta grows (by
+    16x or more from beta 2 to 8), symmetric in the two loops, unchanged
+    (bitwise) when every coordinate is scaled by 2^k, and not blind to two
+    far closed loops, whose monopole moments vanish (their dipole-quadrupole
+    coupling remains); the adaptive beta it drives meets the error target."""
+    lp = I.long_pairs(7, n_pairs=1, n_min=2000, n_max=3000)
+    for ls in (lp,):
+        A, B = ls.loop(0), ls.loop(1)
+        ex = oracle.pair(A, B)
+        es = []
+        for beta in (2.0, 4.0, 8.0):
+            v, e = oracle.bh_pair(A, B, beta, 2, 64, 8)
+            if not e >= abs(v - ex):
+                return "estimate %.3g below the error %.3g at beta %g" % (e, abs(v - ex), beta)
+            es.append(e)
+        if not (es[0] > es[1] > es[2] and es[0] >= 16.0 * es[2]):
+            return "estimate does not fall with beta: %s" % es
+        _, e1 = oracle.bh_pair(A, B, 3.0, 2, 64, 8)
+        _, e2 = oracle.bh_pair(B, A, 3.0, 2, 64, 8)
+        _, e3 = oracle.bh_pair(A * 8.0, B * 8.0, 3.0, 2, 64, 8)
+        if abs(e1 - e2) > 1e-9 * e1:
+            return "estimate not symmetric in the loops"
+        if e3 != e1:
+            return "estimate changes under scaling by 8"
+    rng = np.random.default_rng(11)
+    ca = _smooth_loop(rng, 64, np.zeros(3))
+    cb = _smooth_loop(rng, 64, np.array([20.0, 3.0, 1.0]))
+    v, e = oracle.bh_pair(ca, cb, 2.0, 2, 64, 8)
+    if not (abs(v) < 1e-9 and e > 1e-6):
+        return "far closed loops: value %.3g, estimate %.3g" % (v, e)
+    A, B = lp.loop(0), lp.loop(1)
+    ex = oracle.pair(A, B)
+    v, e, beta = oracle.bh_pair_adaptive(A, B, 2.0, 10.0, 0.002)
+    if not (beta > 2.0 and abs(v - ex) <= 0.002):
+        return "adaptive beta %.2f left error %.3g" % (beta, abs(v - ex))
+    return None
+
+
 def run_pins():
     fails = []
     for f in (pin_segment_terms, pin_hopf, pin_torus, pin_crossings, pin_integer_and_refinement,
               pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
-              pin_bh_expansion_order, pin_bh_accuracy, pin_dz_on_curve, pin_dz_separated,
+              pin_bh_expansion_order, pin_bh_accuracy, pin_bh_estimate, pin_dz_on_curve,
+              pin_dz_separated,
               pin_dz_unrefined, pin_dz_homotopy, pin_dz_termination):
         r = f()
         if r:
@@ -587,14 +628,14 @@ def test_loop_flags():
     assert f[1] & oracle.FLAG_NONFINITE
 
 
-@pytest.mark.parametrize("mutation", list(range(1, 13)))
+@pytest.mark.parametrize("mutation", list(range(1, 14)))
 def test_planted_mistakes_are_caught(mutation):
     """A dropped term, a wrong sign, a wrong index, a transposed operand, an
     open loop, a wrong normalisation, a wrong sign of the Barnes-Hut dipole
     term, a dropped part of the segment quadrupole moment, a discretization
     that refines only one loop of a pair, a wrong de Casteljau midpoint, a
-    wrong B-spline end point or halves out of order each break at least one
-    pin."""
+    wrong B-spline end point, halves out of order or a dropped term of the
+    Barnes-Hut error estimate each break at least one pin."""
     oracle.set_mutation(mutation)
     try:
         fails = run_pins()
@@ -606,7 +647,7 @@ def test_planted_mistakes_are_caught(mutation):
 
 def test_bh_pins():
     for f in (pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
-              pin_bh_expansion_order, pin_bh_accuracy):
+              pin_bh_expansion_order, pin_bh_accuracy, pin_bh_estimate):
         assert f() is None, f.__name__
 
 
