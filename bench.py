@@ -27,7 +27,8 @@ Prints ONE JSON line.  Options:
   --mode mixed|plain|crossings|barnes_hut
                          mode of the headline value (default mixed); with mixed,
                          plain FP64, the crossing count (Alg. 4) and Barnes-Hut
-                         (Alg. 6) are timed on the same input and reported beside it
+                         (Alg. 6: beta 4, and the adaptive beta from 2) are timed
+                         on the same input and reported beside it
   --no-plain, --no-crossings, --no-bh, --no-dz   skip those companion legs
                          (dz: the discretization of Alg. 3, timed on the knit
                          workload's B-spline control points, 314k spans)
@@ -189,6 +190,7 @@ def time_mode(ctx, xyz, off, pairs, mode, steps, warmup, lkmod):
         "refit_kernel_ms": st["refit_kernel_ms"],
         "refits": int(np.sum(flags.view(np.uint32) & 1)),
         "refits_direct_sum": int(st.get("refits_direct_sum", 0)),
+        "bh_reruns": int(st.get("bh_reruns", 0)),
         "real": real,
         "lk": lk,
         "flags": flags.view(np.uint32),
@@ -253,9 +255,15 @@ def main():
                                                      args.tune_cache)
         other = time_mode(ctx, xyz, off, pairs, "plain", max(args.steps // 2, 1),
                           min(args.warmup, 1), lk)
-    bh = None
+    bh, bha = None, None
     if not args.no_bh and args.mode == "mixed":
         bh = time_mode(ctx, xyz, off, pairs, "barnes_hut", args.steps, args.warmup, lk)
+        # the adaptive beta of Sec. 3.4.4 with the paper's CPU settings
+        ctx.set_option(lk._lib.OPT_BH_BETA_MILLI, 2000)
+        ctx.set_option(lk._lib.OPT_BH_ADAPTIVE, 1)
+        bha = time_mode(ctx, xyz, off, pairs, "barnes_hut", args.steps, args.warmup, lk)
+        ctx.set_option(lk._lib.OPT_BH_ADAPTIVE, 0)
+        ctx.set_option(lk._lib.OPT_BH_BETA_MILLI, 4000)
     cc, tuned_cc = None, None
     if not args.no_crossings and args.mode == "mixed":
         tuned_cc = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "crossings", lk,
@@ -355,6 +363,17 @@ def main():
             "int_mismatch_vs_mixed": int(np.sum(bh["lk"] != res["lk"])),
             "int_mismatch_vs_construction": int(np.sum(bh["lk"] != exp)),
         }
+        if bha is not None:
+            line["barnes_hut"]["adaptive"] = {
+                "beta_init": 2.0, "beta_max": 10.0, "target": 0.2,
+                "value": T / (bha["ms_per_step"] * 1e-3),
+                "ms_per_step": bha["ms_per_step"],
+                "kernel_ms": bha["kernel_ms"],
+                "pairs_evaluated_again": bha["bh_reruns"],
+                "refits": bha["refits"],
+                "max_abs_diff_vs_mixed": float(np.max(np.abs(bha["real"] - res["real"]))) if len(pr) else 0.0,
+                "int_mismatch_vs_construction": int(np.sum(bha["lk"] != exp)),
+            }
     if not args.no_cpu_baseline:
         line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)

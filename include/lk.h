@@ -259,8 +259,18 @@ enum {
                                      (default 4000) */
   LK_OPT_BH_ORDER = 14,           /* BARNES_HUT: 1 = monopole and dipole terms, 2 = also the
                                      quadrupole term (default) */
-  LK_OPT_DZ_MAX_PASSES = 15       /* lk_discretize: most refinement passes, 1..1000 (default 64;
+  LK_OPT_DZ_MAX_PASSES = 15,      /* lk_discretize: most refinement passes, 1..1000 (default 64;
                                      pieces left unprocessed flag their loop INTERSECT) */
+  LK_OPT_BH_ADAPTIVE = 16,        /* BARNES_HUT: 1 = adaptive beta (Sec. 3.4.4): the first
+                                     traversal at beta (LK_OPT_BH_BETA_MILLI, as beta_init) sums
+                                     each pair's next-order error estimate E (constant
+                                     k = 1/(4 pi)); a pair with beta_t = (E / E_target)^(1/4) beta
+                                     above beta is evaluated again at min(beta_t, beta_max).
+                                     0 = one traversal at beta (default) */
+  LK_OPT_BH_BETA_MAX_MILLI = 17,  /* BARNES_HUT adaptive: beta_max x 1000, 500..1e6 (default
+                                     10000) */
+  LK_OPT_BH_TARGET_PPM = 18       /* BARNES_HUT adaptive: E_target in millionths, 1..1e6
+                                     (default 200000 = 0.2) */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */
@@ -289,6 +299,8 @@ typedef struct {
   int64_t bh_near_pairs;     /* BARNES_HUT: leaf pairs summed directly */
   int64_t bh_list_cap;       /* BARNES_HUT: capacity of a step's list (pairs beyond it are
                                 refitted) */
+  int64_t bh_reruns;         /* BARNES_HUT with adaptive beta: pairs evaluated again at a
+                                larger beta */
 } lk_stats;
 
 /* ------------------------------------------------------------ autotuner */

@@ -26,6 +26,7 @@ OPT_REFIT_THRESHOLD_PPM, OPT_GRAPH, OPT_TIMING, OPT_TILE_A, OPT_CHUNK_A = 1, 2, 
 OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 9
 OPT_SMALL_BATCH, OPT_CROSSING_TOL, OPT_CROSSING_CULL = 10, 11, 12
 OPT_BH_BETA_MILLI, OPT_BH_ORDER, OPT_DZ_MAX_PASSES = 13, 14, 15
+OPT_BH_ADAPTIVE, OPT_BH_BETA_MAX_MILLI, OPT_BH_TARGET_PPM = 16, 17, 18
 FLAG_INTERSECT = 64
 DZ_BSPLINE, DZ_POLYLINE = 0, 1
 DZ_KINDS = {"bspline": DZ_BSPLINE, "polyline": DZ_POLYLINE}
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("chunk_a", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("atan_form", ctypes.c_int32), ("segs_per_lane", ctypes.c_int32),
                 ("refits_direct_sum", ctypes.c_int64), ("bh_list_peak", ctypes.c_int64),
-                ("bh_near_pairs", ctypes.c_int64), ("bh_list_cap", ctypes.c_int64)]
+                ("bh_near_pairs", ctypes.c_int64), ("bh_list_cap", ctypes.c_int64),
+                ("bh_reruns", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):

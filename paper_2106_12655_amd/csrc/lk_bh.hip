@@ -64,7 +64,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (a minimum of non-negative doubles is a minimum of their bit patterns).
 template <typename Tin>
 __global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
-  if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 2) A.counts[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 3) A.counts[threadIdx.x] = 0;
   const Tin* X = static_cast<const Tin*>(A.xyz);
   const int lane = threadIdx.x & 63;
   const int64_t n_slots = level_slots(A, 0);
@@ -205,8 +205,13 @@ __global__ __launch_bounds__(256) void bh_roots_k(BhArgs A, int64_t n_pairs) {
     bool push = false;
     BhPair root{0, 0, 0, 0};
     if (p < n_pairs) {
+      if (A.est) {
+        A.est[2 * p] = 0ull;
+        A.est[2 * p + 1] = 0ull;
+      }
       const int32_t i = A.pairs[2 * p], j = A.pairs[2 * p + 1];
-      const bool valid = i >= 0 && j >= 0 && i < A.n_loops && j < A.n_loops && i != j;
+      const bool valid = i >= 0 && j >= 0 && i < A.n_loops && j < A.n_loops && i != j &&
+                         (!A.beta_p || A.beta_p[p] > 0.0);
       const int64_t na = valid ? A.off[i + 1] - A.off[i] : 0, nb = valid ? A.off[j + 1] - A.off[j] : 0;
       // pairs without work were finalised by the plan
       if (valid && na >= 1 && nb >= 1 && na <= 0x7fffffffLL && nb <= 0x7fffffffLL) {
@@ -278,6 +283,33 @@ __device__ double far_field(const BhNode& u, const BhNode& v, int order) {
   return -(t1 + t2 + t3);
 }
 
+__device__ __forceinline__ double node_radius(const BhNode& n) {
+  return sqrt(n.e[0] * n.e[0] + n.e[1] * n.e[1] + n.e[2] * n.e[2]);
+}
+
+__device__ __forceinline__ double frob(const double* x, int n) {
+  double s = 0.0;
+  for (int q = 0; q < n; ++q) s += x[q] * x[q];
+  return sqrt(s);
+}
+
+// The next-order error estimate of one far node pair (Sec. 3.4.4, with the
+// constant k = 1/(4 pi)):
+//   |r|^-5 (R_A |c_M,B| ||C_Q,A|| + R_B |c_M,A| ||C_Q,B||
+//           + 3 (||C_D,A|| ||C_Q,B|| + ||C_Q,A|| ||C_D,B||)),
+// norms Euclidean / Frobenius, R the half box diagonals.
+__device__ double far_estimate(const BhNode& u, const BhNode& v) {
+  double r[3];
+  for (int q = 0; q < 3; ++q) r[q] = v.c[q] - u.c[q];
+  const double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const double d = sqrt(d2), d5 = d2 * d * d2;
+  const double f = 0.07957747154594766788;  // 1 / (4 pi)
+  const double nM1 = frob(u.M, 3), nM2 = frob(v.M, 3);
+  const double nD1 = frob(u.D, 9), nD2 = frob(v.D, 9), nQ1 = frob(u.Q, 27), nQ2 = frob(v.Q, 27);
+  return f / d5 *
+         (node_radius(u) * nM2 * nQ1 + node_radius(v) * nM1 * nQ2 + 3.0 * (nD1 * nQ2 + nQ1 * nD2));
+}
+
 // ------------------------------------------------------------ traversal
 // Wave-collective append of `n` entries per lane to a list: returns the
 // lane's first position (one atomic per wave).
@@ -302,17 +334,13 @@ __device__ __forceinline__ int64_t checked_slot(const BhArgs& A, int32_t loop, i
   return s - A.level_base[h] < A.level_cap[h] ? s : -1;
 }
 
-__device__ __forceinline__ double node_radius(const BhNode& n) {
-  return sqrt(n.e[0] * n.e[0] + n.e[1] * n.e[1] + n.e[2] * n.e[2]);
-}
-
-__device__ __forceinline__ bool is_far(const BhArgs& A, const BhNode& u, const BhNode& v) {
+__device__ __forceinline__ bool is_far(double beta, const BhNode& u, const BhNode& v) {
   double d2 = 0.0;
   for (int q = 0; q < 3; ++q) {
     const double dq = v.c[q] - u.c[q];
     d2 += dq * dq;
   }
-  return sqrt(d2) > A.beta * (node_radius(u) + node_radius(v));
+  return sqrt(d2) > beta * (node_radius(u) + node_radius(v));
 }
 
 // One breadth-first step over the node pairs of iteration `it`.  A pair that
@@ -333,8 +361,9 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
     const int64_t e = base + threadIdx.x;
     const bool has = e < n_in;
     const BhPair w = has ? in[e] : BhPair{-1, 0, 0, 0};
-    double val = 0.0;
+    double val = 0.0, err = 0.0;
     bool fail = false;
+    const double beta = has && A.beta_p ? A.beta_p[w.p] : A.beta;
     // classification of the pair itself (roots arrive unclassified), then of
     // its children: bit c of near_m / next_m marks child c for that list
     int self = 0;  // 0 none, 1 near, 2 split
@@ -350,8 +379,9 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
       } else {
         const BhNode& u = A.nodes[sa];
         const BhNode& v = A.nodes[sb];
-        if (is_far(A, u, v)) {
+        if (is_far(beta, u, v)) {
           val = far_field(u, v, A.order);
+          if (A.est) err = far_estimate(u, v);
         } else if (ha == 0 && hb == 0) {
           self = 1;
         } else {
@@ -370,9 +400,10 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
               break;
             }
             const BhNode& ch = A.nodes[sc];
-            const bool far = split_a ? is_far(A, ch, v) : is_far(A, u, ch);
+            const bool far = split_a ? is_far(beta, ch, v) : is_far(beta, u, ch);
             if (far) {
               val += split_a ? far_field(ch, v, A.order) : far_field(u, ch, A.order);
+              if (A.est) err += split_a ? far_estimate(ch, v) : far_estimate(u, ch);
             } else if (hc == 0 && (split_a ? hb : ha) == 0) {
               near_m |= 1u << c;
             } else {
@@ -383,19 +414,23 @@ __global__ __launch_bounds__(256) void bh_expand_k(BhArgs A, int it) {
       }
     }
     if (fail) atomicOr(&A.out.flags[w.p], kFlagNonfinite);  // refitted
-    // far-field values: one fixed-point add per pair present in the wave
-    unsigned long long rem = __ballot(val != 0.0 && !fail);
+    // far-field values (and estimates): one fixed-point add per pair present
+    // in the wave
+    const bool add = (val != 0.0 || err != 0.0) && !fail;
+    unsigned long long rem = __ballot(add);
     while (rem) {
       const int leader = __ffsll((long long)rem) - 1;
       const int32_t pl = __shfl(w.p, leader);
-      const bool mine = val != 0.0 && !fail && w.p == pl;
+      const bool mine = add && w.p == pl;
       const unsigned long long m = __ballot(mine);
       const double sum = wave_sum(mine ? val : 0.0);
+      const double esum = A.est ? wave_sum(mine ? err : 0.0) : 0.0;
       if (lane == leader) {
         if (fabs(sum) < 1.0e14)
           fixed_add(&A.acc[2 * (int64_t)pl], sum);
         else
           atomicOr(&A.out.flags[pl], kFlagNonfinite);  // NaN or absurd: refitted
+        if (A.est && esum < 1.0e14) fixed_add(&A.est[2 * (int64_t)pl], esum);
       }
       rem &= ~m;
     }
@@ -462,6 +497,29 @@ __global__ __launch_bounds__(256) void bh_finalize_k(BhArgs A, int64_t n_pairs) 
   }
 }
 
+// -------------------------------------------------------- adaptive beta
+__global__ __launch_bounds__(256) void bh_adapt_k(BhArgs A, int64_t n_pairs, double target,
+                                                  double beta_max) {
+  // the second traversal's lists and leaf list start empty (the count of
+  // pairs evaluated again, at kBhMaxIters + 2, was cleared by the leaf kernel)
+  if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 2) A.counts[threadIdx.x] = 0;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n_pairs;
+       p += (int64_t)gridDim.x * 256) {
+    double b = 0.0;
+    if (!(A.out.flags[p] & kFlagNonfinite)) {  // a failed pair is refitted anyway
+      const double E = from_fixed(A.est[2 * p], A.est[2 * p + 1]);
+      const double bt = pow(E / target, 0.25) * A.beta;
+      if (bt > A.beta) {
+        b = fmin(bt, beta_max);
+        A.acc[2 * p] = 0ull;
+        A.acc[2 * p + 1] = 0ull;
+        atomicAdd(&A.counts[kBhMaxIters + 2], 1);
+      }
+    }
+    A.beta_p[p] = b;
+  }
+}
+
 inline int grid_for(int64_t n, int per_block, int cap) {
   int64_t g = (n + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -492,6 +550,12 @@ hipError_t launch_bh_roots(const BhArgs& a, int64_t n_pairs, hipStream_t s) {
 
 hipError_t launch_bh_expand(const BhArgs& a, int it, hipStream_t s) {
   bh_expand_k<<<2048, 256, 0, s>>>(a, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_bh_adapt(const BhArgs& a, int64_t n_pairs, double target, double beta_max,
+                           hipStream_t s) {
+  bh_adapt_k<<<grid_for(n_pairs, 256, 1024), 256, 0, s>>>(a, n_pairs, target, beta_max);
   return hipGetLastError();
 }
 

@@ -267,8 +267,15 @@ struct BhArgs {
   BhPair* list[2];                   // ping-pong node-pair lists
   BhPair* near;                      // leaf pairs for the direct sum
   int64_t list_cap, near_cap;
-  int32_t* counts;                   // [kBhMaxIters + 2]: list entries per iteration, then near
+  int32_t* counts;                   // [kBhMaxIters + 3]: list entries per iteration, near
+                                     // pairs, pairs evaluated again at a larger beta
   unsigned long long* acc;           // per-pair fixed point [n_pairs][2]
+  // adaptive beta (Sec. 3.4.4): the first traversal sums each pair's
+  // next-order error estimate into est (fixed point [n_pairs][2]); the second
+  // traverses only the pairs with beta_p[p] > 0, at that beta.  Both NULL for
+  // a fixed beta.
+  unsigned long long* est;
+  double* beta_p;
   uint32_t* lf;                      // per-loop validation, folded in by the leaf kernel
   double* minseg2;                   //   (the preparation kernel only initialises it)
   double beta;
@@ -298,6 +305,11 @@ hipError_t launch_bh_expand(const BhArgs& a, int it, hipStream_t s);
 hipError_t launch_bh_near(const BhArgs& a, bool in_f64, hipStream_t s);
 // Round and flag every pair that has work (refit list as in the mixed mode).
 hipError_t launch_bh_finalize(const BhArgs& a, int64_t n_pairs, hipStream_t s);
+// Adaptive beta, between the two traversals: beta_t = (E / target)^(1/4) beta
+// per pair; pairs with beta_t > beta get beta_p = min(beta_t, beta_max) and a
+// cleared accumulator, the others beta_p = 0; the lists start empty again.
+hipError_t launch_bh_adapt(const BhArgs& a, int64_t n_pairs, double target, double beta_max,
+                           hipStream_t s);
 
 // --- lk_ds.hip
 // in_f64: input dtype; compute_f64: arithmetic (true = plain FP64 / refit);

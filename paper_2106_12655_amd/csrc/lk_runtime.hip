@@ -68,6 +68,7 @@ struct lk_ctx {
   DevBuf boxes, vcounts, vprefix;
   DevBuf cc_blk, cc_sup;  // crossing count: projected block and superblock boxes
   DevBuf bh_nodes, bh_lists, bh_counts;  // Barnes-Hut trees, node-pair lists, counts
+  DevBuf bh_adapt;  // adaptive beta: per-pair error estimate (fixed point) and beta
   // discretization: two piece arrays and two unprocessed lists (swapped every
   // pass), piece and group boxes, marks, split prefixes, per-pair item
   // prefixes, scan partials, and the small per-loop arrays
@@ -76,6 +77,9 @@ struct lk_ctx {
   int dz_max_passes = 64;
   double bh_beta = 4.0;
   int bh_order = 2;
+  bool bh_adaptive = false;      // Sec. 3.4.4's second evaluation at a larger beta
+  double bh_beta_max = 10.0;
+  double bh_target = 0.2;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
   // graphs
   struct Cached {
@@ -381,6 +385,8 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     H.beta = ctx->bh_beta;
     H.order = ctx->bh_order;
     H.out = out;
+    const bool adaptive = ctx->bh_adaptive && ctx->bh_adapt.bytes >= 24 * (size_t)n_pairs;
+    if (adaptive) H.est = (unsigned long long*)ctx->bh_adapt.p;
     if (timed) LK_HIP(hipEventRecord(ev[0], s));
     // the leaf kernel also validates the loops, so the plan follows it
     LK_HIP(launch_bh_leaves(H, P.in_f64, s));
@@ -390,6 +396,16 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     LK_HIP(launch_bh_roots(H, n_pairs, s));
     for (int it = 0; it < 2 * (Y.levels - 1) + 1; ++it) LK_HIP(launch_bh_expand(H, it, s));
     LK_HIP(launch_bh_near(H, P.in_f64, s));
+    if (adaptive) {
+      // pairs whose error estimate asks for a larger beta are evaluated again
+      // from their roots at that beta (their first values are discarded)
+      H.beta_p = (double*)((char*)ctx->bh_adapt.p + 16 * (size_t)n_pairs);
+      LK_HIP(launch_bh_adapt(H, n_pairs, ctx->bh_target, ctx->bh_beta_max, s));
+      H.est = nullptr;
+      LK_HIP(launch_bh_roots(H, n_pairs, s));
+      for (int it = 0; it < 2 * (Y.levels - 1) + 1; ++it) LK_HIP(launch_bh_expand(H, it, s));
+      LK_HIP(launch_bh_near(H, P.in_f64, s));
+    }
     if (timed) LK_HIP(hipEventRecord(ev[1], s));
     LK_HIP(launch_bh_finalize(H, n_pairs, s));
   } else {
@@ -541,7 +557,8 @@ lk_status bh_prepare(lk_ctx* ctx, const int64_t* off, int32_t n_loops, int64_t n
   if ((st = ensure(ctx, ctx->bh_lists,
                    sizeof(lk::BhPair) * (size_t)(2 * Y.list_cap + Y.near_cap))) != LK_OK)
     return st;
-  return ensure(ctx, ctx->bh_counts, 4 * (size_t)(lk::kBhMaxIters + 2));
+  if ((st = ensure(ctx, ctx->bh_adapt, 24 * (size_t)(n_pairs + 1))) != LK_OK) return st;
+  return ensure(ctx, ctx->bh_counts, 4 * (size_t)(lk::kBhMaxIters + 3));
 }
 
 bool check_dtype(int d) { return d == LK_F32 || d == LK_F64; }
@@ -592,7 +609,7 @@ void lk_destroy(lk_ctx* ctx) {
                     &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
                     &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix,
                     &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
-                    &ctx->bh_counts,  &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
+                    &ctx->bh_counts,  &ctx->bh_adapt, &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
                     &ctx->dz_list[1], &ctx->dz_pbox, &ctx->dz_gbox, &ctx->dz_mark,
                     &ctx->dz_pre,     &ctx->dz_pair_pre, &ctx->dz_pair_ab, &ctx->dz_part,
                     &ctx->dz_loops};
@@ -669,6 +686,20 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
       if (v < 500 || v > 1000000)
         return ctx->fail(LK_EINVAL, "Barnes-Hut beta (x 1000) must be in [500, 1e6]");
       ctx->bh_beta = (double)v * 1e-3;
+      break;
+    case LK_OPT_BH_ADAPTIVE:
+      if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "adaptive beta must be 0 or 1");
+      ctx->bh_adaptive = v != 0;
+      break;
+    case LK_OPT_BH_BETA_MAX_MILLI:
+      if (v < 500 || v > 1000000)
+        return ctx->fail(LK_EINVAL, "Barnes-Hut beta_max (x 1000) must be in [500, 1e6]");
+      ctx->bh_beta_max = (double)v * 1e-3;
+      break;
+    case LK_OPT_BH_TARGET_PPM:
+      if (v < 1 || v > 1000000)
+        return ctx->fail(LK_EINVAL, "Barnes-Hut error target (ppm) must be in [1, 1e6]");
+      ctx->bh_target = (double)v * 1e-6;
       break;
     case LK_OPT_BH_ORDER:
       if (v != 1 && v != 2) return ctx->fail(LK_EINVAL, "Barnes-Hut order must be 1 or 2");
@@ -871,13 +902,14 @@ lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
     ctx->stats.refits = rn;
     ctx->stats.refits_direct_sum = rn2;
     if (ctx->last_bh && ctx->bh_counts.p) {
-      int32_t c[lk::kBhMaxIters + 2];
+      int32_t c[lk::kBhMaxIters + 3];
       LK_HIP(hipMemcpy(c, ctx->bh_counts.p, sizeof(c), hipMemcpyDeviceToHost));
       int64_t peak = 0;
       for (int k = 0; k <= lk::kBhMaxIters; ++k) peak = std::max<int64_t>(peak, c[k]);
       ctx->stats.bh_list_peak = peak;
       ctx->stats.bh_near_pairs = c[lk::kBhMaxIters + 1];
       ctx->stats.bh_list_cap = ctx->last_bh_list_cap;
+      ctx->stats.bh_reruns = ctx->bh_adaptive ? c[lk::kBhMaxIters + 2] : 0;
     }
   }
   if (ctx->timing && ctx->ring_count > 0) {

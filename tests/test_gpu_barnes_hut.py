@@ -70,6 +70,44 @@ def test_matches_oracle_barnes_hut(bctx, beta, order):
         _set(bctx, 4.0, 2)
 
 
+def _adaptive(c, on, beta_max=10.0, target=0.2):
+    import paper_2106_12655_amd as lk
+    c.set_option(lk._lib.OPT_BH_ADAPTIVE, 1 if on else 0)
+    c.set_option(lk._lib.OPT_BH_BETA_MAX_MILLI, int(round(beta_max * 1000)))
+    c.set_option(lk._lib.OPT_BH_TARGET_PPM, int(round(target * 1e6)))
+
+
+@pytest.mark.parametrize("target", [0.2, 0.002])
+def test_adaptive_beta_matches_oracle(bctx, target):
+    """Adaptive beta (Sec. 3.4.4) from beta_init 2, beta_max 10: the pairs the
+    GPU evaluates again are the ones the oracle's estimate sends to a larger
+    beta, and the values agree with the oracle's adaptive Barnes-Hut."""
+    try:
+        _set(bctx, 2.0, 2)
+        _adaptive(bctx, True, 10.0, target)
+        for ls, pairs, label in _cases():
+            pairs = np.asarray(pairs, np.int32)
+            real, lk_int, flags = _run(bctx, ls, pairs)
+            reruns = bctx.stats()["bh_reruns"]
+            res = [oracle.bh_pair_adaptive(ls.loop(i), ls.loop(j), 2.0, 10.0, target)
+                   for i, j in pairs]
+            ov = np.array([r[0] for r in res])
+            want = sum(r[2] > 2.0 for r in res)
+            olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)[1]
+            err = np.abs(real - ov)
+            print("adaptive target %g %s: betas %s, reruns gpu %d oracle %d, max |gpu - oracle| "
+                  "%.2e, |value - integer| %.2e" % (target, label, [round(r[2], 3) for r in res],
+                                                    reruns, want, err.max(),
+                                                    np.abs(ov - olk).max()), flush=True)
+            refit = (flags & 1) != 0
+            assert reruns == want, label
+            assert err[~refit].max(initial=0.0) <= BH_TOL, label
+            assert np.array_equal(lk_int, olk), label
+    finally:
+        _adaptive(bctx, False)
+        _set(bctx, 4.0, 2)
+
+
 def test_infinite_beta_is_the_direct_sum(bctx):
     """With a huge beta no node pair is far: Barnes-Hut sums every leaf pair,
     which is the mixed direct sum up to FP32 rounding."""
@@ -111,7 +149,9 @@ def test_workloads_integers_and_check(bctx):
 
 def test_options_and_bad_pairs(bctx):
     import paper_2106_12655_amd as lk
-    for key, bad in ((lk._lib.OPT_BH_BETA_MILLI, 100), (lk._lib.OPT_BH_ORDER, 3)):
+    for key, bad in ((lk._lib.OPT_BH_BETA_MILLI, 100), (lk._lib.OPT_BH_ORDER, 3),
+                     (lk._lib.OPT_BH_ADAPTIVE, 2), (lk._lib.OPT_BH_BETA_MAX_MILLI, 10),
+                     (lk._lib.OPT_BH_TARGET_PPM, 0)):
         with pytest.raises(lk.LkError):
             bctx.set_option(key, bad)
     ls = I.hopf(64)
