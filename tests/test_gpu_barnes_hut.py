@@ -108,6 +108,39 @@ def test_adaptive_beta_matches_oracle(bctx, target):
         _set(bctx, 4.0, 2)
 
 
+def test_adaptive_beta_graph_replay(bctx):
+    """The adaptive sequence (two traversals, the per-pair beta kernel in
+    between) is captured once and replayed: replays with eager work between
+    them are bitwise equal to each other and to eager calls."""
+    import torch
+    import paper_2106_12655_amd as lk
+    ls = I.long_pairs(7, n_pairs=2, n_min=20000, n_max=40000)
+    xyz = torch.from_numpy(ls.xyz).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    pr = torch.from_numpy(np.asarray(ls.pairs, np.int32)).cuda()
+    try:
+        _set(bctx, 2.0, 2)
+        _adaptive(bctx, True, 10.0, 0.002)
+        s = torch.cuda.Stream()
+        outs = []
+        with torch.cuda.stream(s):
+            for k in range(4):
+                outs.append([t.cpu().numpy() for t in bctx.direct_sum(xyz, off, pr, "barnes_hut")])
+                torch.randn(1 << 20, device="cuda").sum().item()  # eager work in between
+        replayed = bctx.stats()["graph_replayed"]
+        bctx.set_option(lk._lib.OPT_GRAPH, 0)
+        eager = [t.cpu().numpy() for t in bctx.direct_sum(xyz, off, pr, "barnes_hut")]
+        torch.cuda.synchronize()
+    finally:
+        bctx.set_option(lk._lib.OPT_GRAPH, 1)
+        _adaptive(bctx, False)
+        _set(bctx, 4.0, 2)
+    assert replayed
+    for o in outs[1:] + [eager]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+    assert np.array_equal(outs[0][1], np.asarray(ls.exp_lk))
+
+
 def test_infinite_beta_is_the_direct_sum(bctx):
     """With a huge beta no node pair is far: Barnes-Hut sums every leaf pair,
     which is the mixed direct sum up to FP32 rounding."""

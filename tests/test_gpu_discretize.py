@@ -124,6 +124,23 @@ def test_edge_cases(dctx):
     _compare(dctx, loops[0], [0, len(loops[0])], [], label="one loop")
 
 
+def test_long_loops_many_groups(dctx):
+    """Two loops of 5,000 control points each (79 groups of 64 pieces, so a
+    work item walks the other loop's groups in two chunks of 64), wound
+    around each other three times at a distance close to the control
+    spacing: refined in several passes, bitwise equal to the oracle for
+    both curve kinds, and still linked three times."""
+    r = I.winding_pair(5, 15000, 15000, 3, step=0.03, rho=0.04)
+    a, b = r[0][::3], r[1][::3]
+    ctrl = np.vstack([a, b])
+    off = np.array([0, len(a), len(a) + len(b)], np.int64)
+    for kind in ("bspline", "polyline"):
+        gx, go, gf, info = _compare(dctx, ctrl, off, [[0, 1]], kind=kind,
+                                    label="winding pair 5000 + 5000, %s" % kind)
+        assert go[-1] > len(ctrl) and info["passes"] >= 2
+        assert abs(oracle.pair(gx[go[0]:go[1]], gx[go[1]:go[2]]) - 3.0) < 1e-6
+
+
 def test_pair_order_capacity_and_repeat(dctx):
     import paper_2106_12655_amd as lk
     k, pr = _knit_ctrl(4, 30)
