@@ -7,8 +7,12 @@
  * Summation Methods"; the double sum of Eq. 3 / Alg. 5, Sec. 3.4.2), reduces it
  * to one real number per loop pair and rounds it to the integer linking
  * number.  Around that hot path it offers the potential link search of
- * Alg. 2 (Sec. 3.2) and the before/after comparison with early exit that the
- * method overview (Sec. 3.1, "Fast Verification") describes.
+ * Alg. 2 (Sec. 3.2), the discretization of spline curves into polylines with
+ * the same linking numbers (Alg. 3, Sec. 3.3), the count-crossings and
+ * Barnes-Hut methods as other modes of the same call (Alg. 4 and 6,
+ * Sec. 2.1 and 3.4.4), the before/after comparison with early exit that the
+ * method overview (Sec. 3.1, "Fast Verification") describes, and a
+ * verification server for streams of such checks.
  *
  * Conventions shared by every call
  *   - Geometry: xyz is a contiguous row-major array of V vertices x 3

@@ -37,6 +37,9 @@
  *                     next-order error estimate; lko_bh_node_moments and
  *                     lko_bh_far_pieces expose its moments and far field for
  *                     the pins.
+ *   - lko_discretize: the adaptive discretization of Alg. 3 (Sec. 3.3):
+ *                     B-spline or polyline loops refined into polylines by
+ *                     passes over overlapping piece boxes of paired loops.
  *
  * Readings of the paper used here (also listed in the design notes):
  *   - vertex indices are cyclic: loop of n vertices has n segments, the first

@@ -8,8 +8,9 @@ a built library or a GPU every call raises.
 Functions follow the paper's pipeline (Qu & James 2021, Alg. 1):
 ``build_pairs`` (potential link search, Alg. 2), ``discretize`` (curves to
 polylines with the same linking numbers, Alg. 3), ``direct_sum`` (stage 3 by
-direct summation of Eq. 4, Alg. 5), ``direct_sum_check`` (the same fused with
-the certificate comparison and its early exit, Sec. 3.1) and ``verify`` (the
+direct summation of Eq. 4, Alg. 5; the modes "crossings" and "barnes_hut" run
+Alg. 4 and Alg. 6 instead), ``direct_sum_check`` (the same fused with the
+certificate comparison and its early exit, Sec. 3.1) and ``verify`` (the
 before/after comparison of two sparse matrices, Sec. 3.1).
 """
 from __future__ import annotations

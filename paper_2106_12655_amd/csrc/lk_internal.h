@@ -1,7 +1,9 @@
 // lk_internal.h -- declarations shared by the HIP translation units of liblk.so.
-// Kernels live in lk_ds.hip (the direct-sum hot loop) and lk_aux.hip (planning,
-// scheduling, validation, reduction, pair search, verification);
-// lk_runtime.hip holds the C ABI.
+// Kernels live in lk_ds.hip (the direct-sum and crossing-count hot loop, and
+// the Barnes-Hut leaf pairs), lk_aux.hip (planning, scheduling, validation,
+// reduction, pair search, verification), lk_bh.hip (Barnes-Hut trees and
+// traversal) and lk_dz.hip (discretization, declared in lk_dz.h);
+// lk_runtime.hip holds the C ABI and lk_server.hip the verification server.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -1,5 +1,6 @@
 // lk_runtime.hip -- the C ABI of liblk.so (include/lk.h): contexts, workspace,
-// argument checking, the kernel sequence of each call and its HIP-graph cache.
+// argument checking, the kernel sequence of each call and its HIP-graph cache,
+// the autotuner, and the pass loop of lk_discretize.
 //
 // lk_direct_sum enqueues, on the caller's stream:
 //   preparation (xi partials, per-loop validity) -> plan (items per pair) ->
@@ -8,9 +9,13 @@
 //   pairs split over several items
 //   [MIXED only: plan -> schedule -> FP64 direct-sum -> split pairs, on the
 //   refit list]
-// Every launch has a host-known shape; data-dependent counts live in device
-// memory.  The first call with a given argument set is captured into a HIP
-// graph (when the stream allows capture) and replayed by later identical calls.
+// CROSSINGS replaces the FP32 direct sum by the crossing count (with its FP64
+// count and the FP64 direct sum for undecided pairs); BARNES_HUT by the trees,
+// the breadth-first traversal (twice with the adaptive beta) and the leaf
+// pairs.  Every launch has a host-known shape; data-dependent counts live in
+// device memory.  The first call with a given argument set is captured into a
+// HIP graph (when the stream allows capture) and replayed by later identical
+// calls.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
