@@ -194,19 +194,37 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
 }
 
 // --------------------------------------------------------------- planning
-// Append to a device list from a wavefront: one atomic per wave, then each
-// lane with `pred` gets base + (number of lower lanes with pred).  All active
-// lanes must call it.
-__device__ __forceinline__ int32_t wave_append(int32_t* count, bool pred) {
-  const unsigned long long m = __ballot(pred);
-  const unsigned long long act = __ballot(1);
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)act) - 1;
-  int32_t base = 0;
-  if (lane == leader && m) base = atomicAdd(count, (int32_t)__popcll(m));
-  base = __shfl(base, leader);
+// Workgroup-collective append to two lists at once: one atomic per list per
+// workgroup (instead of one per wavefront), so the plan of tens of thousands
+// of pairs does not queue thousands of atomics on two counters.  Every
+// thread of the workgroup must call it; *pos0 / *pos1 receive the thread's
+// slot in list 0 / 1 when it appends there.
+__device__ __forceinline__ void block_append2(int32_t* count0, bool pred0, int32_t* pos0,
+                                              int32_t* count1, bool pred1, int32_t* pos1) {
+  __shared__ int32_t wn[2][16], base[2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long m0 = __ballot(pred0), m1 = __ballot(pred1);
+  if (lane == 0) {
+    wn[0][w] = (int32_t)__popcll(m0);
+    wn[1][w] = (int32_t)__popcll(m1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int k = threadIdx.x;
+    int32_t t = 0;
+    for (int q = 0; q < nw; ++q) t += wn[k][q];
+    base[k] = t ? atomicAdd(k ? count1 : count0, t) : 0;
+  }
+  __syncthreads();
+  int32_t b0 = base[0], b1 = base[1];
+  for (int q = 0; q < w; ++q) {
+    b0 += wn[0][q];
+    b1 += wn[1][q];
+  }
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-  return base + (int32_t)__popcll(m & below);
+  *pos0 = b0 + (int32_t)__popcll(m0 & below);
+  *pos1 = b1 + (int32_t)__popcll(m1 & below);
+  __syncthreads();  // wn and base are reused by the next call
 }
 
 // Exclusive scan of one value per thread over a 1024-thread workgroup
@@ -305,8 +323,10 @@ __device__ void schedule(const Sched& S, int32_t* zero_next) {
   }
 }
 
-// One thread per list position (1024-thread workgroups: the last one to
-// finish also runs the schedule, which needs a full workgroup scan).
+// One thread per list position, 1024-thread workgroups.  The schedule is a
+// separate single-workgroup launch: handing it to the plan's last workgroup
+// (a fence and a ticket in every workgroup) measured slower on MI355X, where
+// a device-scope fence writes back the XCD's L2.
 __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo li, Sched S,
                                                int refit) {
   // xi = mean |coordinate|: every block reduces the preparation kernel's
@@ -328,7 +348,7 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
     n = nd < n ? nd : n;
   }
   // grid stride with the same trip count in every thread (the appends below
-  // are wavefront-collective)
+  // are workgroup-collective)
   for (int64_t base = (int64_t)blockIdx.x * 1024; base < A.n_list;
        base += (int64_t)gridDim.x * 1024) {
     const int64_t q = base + threadIdx.x;
@@ -403,8 +423,8 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
         A.out.flags[p] = f;
       }
     }
-    const int32_t ps = wave_append(&S.counts[0], small);
-    const int32_t pb = wave_append(&S.counts[1], big);
+    int32_t ps, pb;
+    block_append2(&S.counts[0], small, &ps, &S.counts[1], big, &pb);
     if (small) S.small[ps] = r;
     if (big) S.big_in[pb] = r;
   }
