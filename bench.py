@@ -60,17 +60,20 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 # HBM bytes per launch of the direct-sum kernel, from two rocprofv3 --pmc runs
 # of the chainmail command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
 # averaged over the timed dispatches), each scaled by what the same counter read
-# for one 256 MiB device copy in that run (fetch x2.000, write x1.000).  A
-# record only holds for the machine code it was taken on (the fingerprint of
-# the kernel's gfx950 assembly that the build writes to liblk.kernels.json)
-# and for the tuned launch configuration: anything else reports traffic as null.
+# for one 256 MiB device copy in that run (fetch x2.000, write x1.000), for each
+# of the launch configurations the autotuner picks on this workload.  A record
+# only holds for the machine code it was taken on (the fingerprint of the
+# kernel's gfx950 assembly that the build writes to liblk.kernels.json) and for
+# a recorded launch configuration: anything else reports traffic as null.
 TRAFFIC = {
     ("chainmail", "mixed"): {
         "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4EEEvNS_6DsArgsE",
         "isa": "f19f906333a9a1db",
-        "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "small_batch": 2,
-                   "waves_per_cu": 0, "atan_form": 2},
-        "fetch_kib": 23241.8, "write_kib": 2494.1, "fetch_scale": 2.000, "write_scale": 1.000,
+        "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "atan_form": 2},
+        "fetch_scale": 2.000, "write_scale": 1.000,
+        # (small_batch, waves_per_cu) -> (FETCH_SIZE, WRITE_SIZE) KiB per launch
+        "by_launch": {(2, 0): (21738.0, 2497.8), (4, 0): (21772.2, 2509.6),
+                      (2, 12): (21676.2, 2491.1), (4, 12): (21978.0, 2516.5)},
     },
 }
 
@@ -101,7 +104,10 @@ def measured_traffic(config: str, mode: str, tuned):
         return None
     if any(tuned.get(k) != v for k, v in rec["config"].items()):
         return None
-    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024
+    kib = rec["by_launch"].get((tuned.get("small_batch"), tuned.get("waves_per_cu")))
+    if kib is None:
+        return None
+    return (kib[0] * rec["fetch_scale"] + kib[1] * rec["write_scale"]) * 1024
 
 
 def parse():
