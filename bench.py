@@ -459,7 +459,7 @@ def run_serving(args):
     t0 = time.perf_counter()
     pool = serve.make_pool(args.seed, args.scenes, max_terms=3e11)
     gen_s = time.perf_counter() - t0
-    srv = serve.Server(slots=4)
+    srv = serve.Server(slots=4, mode=args.mode)
     cap = serve.capacity(srv, pool)
     recs = serve.run_stream(srv, pool, args.load * cap, args.requests, args.seed)
     summ = serve.summarize(recs)
@@ -475,11 +475,12 @@ def run_serving(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64" if args.mode == "plain" else ("f32 predicates+f64" if args.mode == "crossings"
+                                                      else "f32+f64"),
         "data": "synthetic",
         "config": {"workload": "serving", "description": WORKLOADS["serving"],
                    "requests": args.requests, "load": args.load, "scenes": args.scenes,
-                   "slots": 4, "seed": args.seed},
+                   "slots": 4, "seed": args.seed, "mode": args.mode},
         "latency": {"p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
                     "mean_ms": summ["mean_ms"], "queue_p50_ms": summ["queue_p50_ms"]},
         "throughput_req_s": summ["throughput_req_s"],

@@ -259,7 +259,7 @@ extern "C" {
 lk_status lk_server_create(lk_server** out, int device, int32_t slots, int64_t mem_budget,
                            int mode, int32_t max_loops, int64_t max_pairs) {
   if (!out || slots < 1 || slots > 8 || mem_budget < 0 || max_loops < 1 || max_pairs < 1 ||
-      (mode != LK_MIXED && mode != LK_PLAIN_F64 && mode != LK_CROSSINGS))
+      (mode != LK_MIXED && mode != LK_PLAIN_F64 && mode != LK_CROSSINGS && mode != LK_BARNES_HUT))
     return LK_EINVAL;
   *out = nullptr;
   if (hipSetDevice(device) != hipSuccess) return LK_EDEVICE;
