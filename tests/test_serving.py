@@ -84,3 +84,16 @@ def test_poisson_stream_reports_pulled_pairs():
     assert summ["exact"] == 24
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
     srv.close()
+
+
+@pytest.mark.parametrize("mode", ["crossings", "barnes_hut", "plain"])
+def test_stream_in_other_modes(mode):
+    """The server runs any mode of the direct-sum call: every request of a
+    short stream reports exactly its pulled-through pairs."""
+    pool = _pool(steps=2)
+    srv = serve.Server(slots=4, mode=mode)
+    recs = serve.run_stream(srv, pool, rate=200.0, n_requests=16, seed=5)
+    summ = serve.summarize(recs)
+    print("stream (%s):" % mode, summ, flush=True)
+    assert summ["exact"] == 16
+    srv.close()
