@@ -128,8 +128,13 @@ const char* lk_last_error(const lk_ctx* ctx);
  * (vertex min/max per loop) overlap on all three axes, in lexicographic order,
  * written to pairs_out [capacity][2].  Synchronises the stream (the count is
  * needed on the host).  *n_pairs (host) receives the number of pairs; if it
- * exceeds `capacity` nothing beyond capacity is written and LK_ECAPACITY is
- * returned with *n_pairs = required size.  Loops with no vertex get no pair. */
+ * exceeds `capacity`, nothing is written and LK_ECAPACITY is returned with
+ * *n_pairs = required size.  Loops with no vertex get no pair.  The search
+ * stands in for the paper's box tree: from 2,048 loops on (LK_OPT_PAIR_SEARCH)
+ * the boxes are binned on a hashed grid by their min corners, and each box is
+ * tested only against the boxes of its 27 neighbouring cells (large or
+ * non-finite boxes against all); below that, all L (L - 1) / 2 box pairs are
+ * tested.  Both give exactly the same pairs. */
 lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* loop_offsets,
                          int32_t n_loops, int32_t* pairs_out, int64_t capacity,
                          int64_t* n_pairs /* host */, void* stream);
@@ -273,8 +278,10 @@ enum {
                                      0 = one traversal at beta (default) */
   LK_OPT_BH_BETA_MAX_MILLI = 17,  /* BARNES_HUT adaptive: beta_max x 1000, 500..1e6 (default
                                      10000) */
-  LK_OPT_BH_TARGET_PPM = 18       /* BARNES_HUT adaptive: E_target in millionths, 1..1e6
+  LK_OPT_BH_TARGET_PPM = 18,      /* BARNES_HUT adaptive: E_target in millionths, 1..1e6
                                      (default 200000 = 0.2) */
+  LK_OPT_PAIR_SEARCH = 19         /* lk_build_pairs: 0 = grid from 2,048 loops on (default),
+                                     1 = test all box pairs, 2 = grid always */
 };
 
 /* Set an option; returns LK_EINVAL for an unknown key or a bad value. */

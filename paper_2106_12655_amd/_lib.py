@@ -27,6 +27,7 @@ OPT_WAVES_PER_CU, OPT_ATAN, OPT_SEGS_PER_LANE, OPT_SEGS_PER_LANE_F64 = 6, 7, 8, 
 OPT_SMALL_BATCH, OPT_CROSSING_TOL, OPT_CROSSING_CULL = 10, 11, 12
 OPT_BH_BETA_MILLI, OPT_BH_ORDER, OPT_DZ_MAX_PASSES = 13, 14, 15
 OPT_BH_ADAPTIVE, OPT_BH_BETA_MAX_MILLI, OPT_BH_TARGET_PPM = 16, 17, 18
+OPT_PAIR_SEARCH = 19
 FLAG_INTERSECT = 64
 DZ_BSPLINE, DZ_POLYLINE = 0, 1
 DZ_KINDS = {"bspline": DZ_BSPLINE, "polyline": DZ_POLYLINE}

@@ -525,6 +525,204 @@ __global__ __launch_bounds__(256) void pair_scan_k(const double* box, int32_t L,
   if (!WRITE && i < L) counts[i] = cnt;
 }
 
+// ------------------------------------- potential link search on a hashed grid
+// A box is "regular" when it is finite and no side is longer than half the
+// cell size h; regular boxes are binned by the cell of their min corner.  Two
+// overlapping regular boxes have min corners at most h/2 apart on every
+// axis, so their cells differ by at most one: a regular box only meets the
+// regular boxes of the 27 cells around its own.  Cells are hashed into a
+// table of buckets, so the scene's extent does not matter; boxes of other
+// cells that share a bucket are candidates the box test rejects.  Every
+// other box (large, empty or non-finite) is tested against all boxes with
+// the same predicate as the brute-force scan, so both give exactly the same
+// pairs.  Each pair is found once, from its smaller index; a row's pairs are
+// sorted by j afterwards, so the output is lexicographic.
+__device__ __forceinline__ bool box_regular(const double* b, double h) {
+  bool ok = true;
+  for (int q = 0; q < 3; ++q) {
+    const double e = b[3 + q] - b[q];
+    ok = ok && isfinite(b[q]) && isfinite(b[3 + q]) && e >= 0.0 && e <= 0.5 * h;
+  }
+  return ok;
+}
+
+__device__ __forceinline__ int64_t grid_coord(const GridParams& g, const double* b, int q) {
+  // far beyond any real scene the coordinate saturates (a shared cell only
+  // adds candidates; boxes that far apart do not overlap a nearer one)
+  const double c = floor((b[q] - g.lo[q]) / g.h);
+  return c < 4.0e18 ? (int64_t)c : (int64_t)4000000000000000000ll;
+}
+
+__device__ __forceinline__ int64_t grid_bucket(const GridParams& g, int64_t x, int64_t y,
+                                               int64_t z) {
+  const uint64_t k = ((uint64_t)x * 73856093ull) ^ ((uint64_t)y * 19349663ull) ^
+                     ((uint64_t)z * 83492791ull);
+  return (int64_t)(k % (uint64_t)g.buckets);
+}
+
+// One workgroup: h = 4 x the mean box size (the largest side per box), the
+// origin at the regular boxes' least min corner; zeroes the bucket counts and
+// the large-box count.
+__global__ __launch_bounds__(1024) void grid_params_k(const double* box, int32_t L,
+                                                      int64_t buckets, GridParams* gp,
+                                                      unsigned long long* cell_count,
+                                                      int32_t* n_over) {
+  __shared__ double rs[1024], rc[1024], rmin[3][1024];
+  __shared__ double h_s;
+  const int t = threadIdx.x;
+  double s = 0.0, c = 0.0;
+  for (int64_t i = t; i < L; i += 1024) {
+    const double* b = box + 6 * i;
+    double e = -1.0;
+    for (int q = 0; q < 3; ++q) e = fmax(e, b[3 + q] - b[q]);
+    if (isfinite(e) && e >= 0.0) {
+      s += e;
+      c += 1.0;
+    }
+  }
+  rs[t] = s;
+  rc[t] = c;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      rs[t] += rs[t + w];
+      rc[t] += rc[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double mean = rc[0] > 0.0 ? rs[0] / rc[0] : 0.0;
+    h_s = mean > 0.0 ? 4.0 * mean : 1.0;
+  }
+  __syncthreads();
+  const double h = h_s;
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  for (int64_t i = t; i < L; i += 1024) {
+    const double* b = box + 6 * i;
+    if (!box_regular(b, h)) continue;
+    for (int q = 0; q < 3; ++q) mn[q] = fmin(mn[q], b[q]);
+  }
+  for (int q = 0; q < 3; ++q) rmin[q][t] = mn[q];
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w)
+      for (int q = 0; q < 3; ++q) rmin[q][t] = fmin(rmin[q][t], rmin[q][t + w]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    GridParams g;
+    g.h = h;
+    for (int q = 0; q < 3; ++q) g.lo[q] = isfinite(rmin[q][0]) ? rmin[q][0] : 0.0;
+    g.buckets = buckets;
+    *gp = g;
+    *n_over = 0;
+  }
+  for (int64_t k = t; k < buckets; k += 1024) cell_count[k] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void grid_bin_k(const double* box, int32_t L,
+                                                  const GridParams* gp,
+                                                  unsigned long long* cell_count,
+                                                  int64_t* cell_of, int32_t* over,
+                                                  int32_t* n_over) {
+  const GridParams g = *gp;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
+    const double* b = box + 6 * i;
+    if (box_regular(b, g.h)) {
+      const int64_t c =
+          grid_bucket(g, grid_coord(g, b, 0), grid_coord(g, b, 1), grid_coord(g, b, 2));
+      cell_of[i] = c;
+      atomicAdd(&cell_count[c], 1ull);
+    } else {
+      cell_of[i] = -1;
+      over[atomicAdd(n_over, 1)] = (int32_t)i;
+    }
+  }
+}
+
+// cell_count still holds the counts: each box takes a slot by counting down.
+__global__ __launch_bounds__(256) void grid_scatter_k(int32_t L, const int64_t* cell_of,
+                                                      const int64_t* cell_start,
+                                                      unsigned long long* cell_count,
+                                                      int32_t* cell_items) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
+    const int64_t c = cell_of[i];
+    if (c < 0) continue;
+    const unsigned long long k = atomicAdd(&cell_count[c], ~0ull);  // - 1
+    cell_items[cell_start[c] + (int64_t)k - 1] = (int32_t)i;
+  }
+}
+
+// Row i: the pairs (i, j > i).  WRITE = 0 counts, 1 fills (unsorted for a
+// regular box, ascending j for the others).
+template <int WRITE>
+__global__ __launch_bounds__(256) void grid_rows_k(const double* box, int32_t L,
+                                                   const GridParams* gp, const int64_t* cell_of,
+                                                   const int64_t* cell_start,
+                                                   const int32_t* cell_items, const int32_t* over,
+                                                   const int32_t* n_over, int64_t* counts,
+                                                   const int64_t* row_start, int32_t* out) {
+  const GridParams g = *gp;
+  const int32_t no = *n_over;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
+    double me[6];
+    for (int q = 0; q < 6; ++q) me[q] = box[6 * i + q];
+    int64_t cnt = 0;
+    int64_t pos = WRITE ? row_start[i] : 0;
+    auto emit = [&](int64_t j) {
+      if (WRITE) {
+        out[2 * pos] = (int32_t)i;
+        out[2 * pos + 1] = (int32_t)j;
+        ++pos;
+      } else {
+        ++cnt;
+      }
+    };
+    if (cell_of[i] >= 0) {
+      const int64_t c0 = grid_coord(g, me, 0), c1 = grid_coord(g, me, 1), c2 = grid_coord(g, me, 2);
+      for (int t = 0; t < 27; ++t) {
+        const int64_t c = grid_bucket(g, c0 + t % 3 - 1, c1 + (t / 3) % 3 - 1, c2 + t / 9 - 1);
+        // two neighbour cells in one bucket: visit it once (hashes recomputed,
+        // so nothing is kept in memory)
+        bool dup = false;
+        for (int u = 0; u < t; ++u)
+          dup = dup || grid_bucket(g, c0 + u % 3 - 1, c1 + (u / 3) % 3 - 1, c2 + u / 9 - 1) == c;
+        if (dup) continue;
+        for (int64_t k = cell_start[c]; k < cell_start[c + 1]; ++k) {
+          const int32_t j = cell_items[k];
+          if (j > i && overlap(me, box + 6 * (int64_t)j)) emit(j);
+        }
+      }
+      for (int32_t k = 0; k < no; ++k) {
+        const int32_t j = over[k];
+        if (j > i && overlap(me, box + 6 * (int64_t)j)) emit(j);
+      }
+    } else {
+      for (int64_t j = i + 1; j < L; ++j)
+        if (overlap(me, box + 6 * j)) emit(j);
+    }
+    if (!WRITE) counts[i] = cnt;
+  }
+}
+
+// Rows of regular boxes were filled in cell order: sort each by j.
+__global__ __launch_bounds__(256) void grid_sort_rows_k(int32_t L, const int64_t* cell_of,
+                                                        const int64_t* row_start, int32_t* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
+    if (cell_of[i] < 0) continue;
+    const int64_t a = row_start[i], b = row_start[i + 1];
+    for (int64_t k = a + 1; k < b; ++k) {
+      const int32_t v = out[2 * k + 1];
+      int64_t m = k - 1;
+      while (m >= a && out[2 * m + 1] > v) {
+        out[2 * (m + 1) + 1] = out[2 * m + 1];
+        --m;
+      }
+      out[2 * (m + 1) + 1] = v;
+    }
+  }
+}
+
 // ------------------------------------------------------------ verification
 __device__ __forceinline__ long long key_of(const int32_t* pr, int64_t k) {
   return ((long long)pr[2 * k] << 32) | (unsigned int)pr[2 * k + 1];
@@ -696,6 +894,33 @@ hipError_t launch_pair_fill(const double* boxes, int32_t n_loops, const int64_t*
                             int32_t* pairs_out, int64_t capacity, hipStream_t s) {
   pair_scan_k<1><<<blocks_for(n_loops, 256), 256, 0, s>>>(boxes, n_loops, nullptr, row_start,
                                                           pairs_out, capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBufs& b, int pass,
+                             const int64_t* row_start, int32_t* pairs_out, hipStream_t s) {
+  const int g = blocks_for(n_loops, 256, 4096);
+  switch (pass) {
+    case 0:  // grid, binning and the per-cell scan
+      grid_params_k<<<1, 1024, 0, s>>>(boxes, n_loops, b.buckets, b.params, b.cell_count,
+                                       b.n_over);
+      grid_bin_k<<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_count, b.cell_of, b.over,
+                                   b.n_over);
+      scan_k<<<1, 1024, 0, s>>>(reinterpret_cast<const int64_t*>(b.cell_count), b.buckets,
+                                b.cell_start);
+      grid_scatter_k<<<g, 256, 0, s>>>(n_loops, b.cell_of, b.cell_start, b.cell_count,
+                                       b.cell_items);
+      grid_rows_k<0><<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
+                                       b.cell_items, b.over, b.n_over, b.row_counts, nullptr,
+                                       nullptr);
+      break;
+    default:  // fill and sort the rows
+      grid_rows_k<1><<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
+                                       b.cell_items, b.over, b.n_over, nullptr, row_start,
+                                       pairs_out);
+      grid_sort_rows_k<<<g, 256, 0, s>>>(n_loops, b.cell_of, row_start, pairs_out);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -377,6 +377,30 @@ hipError_t launch_pair_count(const double* boxes, int32_t n_loops, int64_t* coun
 hipError_t launch_pair_fill(const double* boxes, int32_t n_loops, const int64_t* row_start,
                             int32_t* pairs_out, int64_t capacity, hipStream_t s);
 
+// Potential link search on a hashed grid of the boxes' min corners (see
+// grid_params_k): the same pairs as launch_pair_count / launch_pair_fill in
+// about L x (boxes in 27 buckets) tests instead of L^2 / 2.
+struct GridParams {
+  double h;         // cell size; boxes with every side at most h / 2 are binned
+  double lo[3];     // grid origin
+  int64_t buckets;  // hash table size
+};
+struct GridBufs {
+  GridParams* params;
+  unsigned long long* cell_count;  // [buckets] (int64 counts)
+  int64_t* cell_start;             // [buckets + 1]
+  int64_t* cell_of;                // [L] bucket, -1 for a box tested against all
+  int32_t* cell_items;             // [L]
+  int32_t* over;                   // [L]
+  int32_t* n_over;
+  int64_t* row_counts;             // [L]
+  int64_t buckets;
+};
+// pass 0: grid, binning, per-row counts into row_counts; pass 1 (after the
+// caller's scan of the counts into row_start): fill and sort the rows.
+hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBufs& b, int pass,
+                             const int64_t* row_start, int32_t* pairs_out, hipStream_t s);
+
 // Verification: per merged position, mismatch flags, then a scan and a scatter.
 hipError_t launch_verify(const int32_t* pairs, const int32_t* lk, int64_t n,
                          const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp,

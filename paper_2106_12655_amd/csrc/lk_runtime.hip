@@ -74,6 +74,8 @@ struct lk_ctx {
   DevBuf cc_blk, cc_sup;  // crossing count: projected block and superblock boxes
   DevBuf bh_nodes, bh_lists, bh_counts;  // Barnes-Hut trees, node-pair lists, counts
   DevBuf bh_adapt;  // adaptive beta: per-pair error estimate (fixed point) and beta
+  DevBuf pls_grid;  // grid pair search: parameters, cell counts and starts, bins
+  int pair_search = 0;  // 0 auto, 1 all pairs, 2 grid
   // discretization: two piece arrays and two unprocessed lists (swapped every
   // pass), piece and group boxes, marks, split prefixes, per-pair item
   // prefixes, scan partials, and the small per-loop arrays
@@ -614,7 +616,7 @@ void lk_destroy(lk_ctx* ctx) {
                     &ctx->big_prefix, &ctx->meta,    &ctx->acc,     &ctx->flags,
                     &ctx->refit_list, &ctx->boxes,   &ctx->vcounts, &ctx->vprefix,
                     &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
-                    &ctx->bh_counts,  &ctx->bh_adapt, &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
+                    &ctx->bh_counts,  &ctx->bh_adapt, &ctx->pls_grid, &ctx->dz_piece[0], &ctx->dz_piece[1], &ctx->dz_list[0],
                     &ctx->dz_list[1], &ctx->dz_pbox, &ctx->dz_gbox, &ctx->dz_mark,
                     &ctx->dz_pre,     &ctx->dz_pair_pre, &ctx->dz_pair_ab, &ctx->dz_part,
                     &ctx->dz_loops};
@@ -692,6 +694,10 @@ lk_status lk_set_option(lk_ctx* ctx, int key, int64_t v) {
         return ctx->fail(LK_EINVAL, "Barnes-Hut beta (x 1000) must be in [500, 1e6]");
       ctx->bh_beta = (double)v * 1e-3;
       break;
+    case LK_OPT_PAIR_SEARCH:
+      if (v < 0 || v > 2) return ctx->fail(LK_EINVAL, "pair search must be 0, 1 or 2");
+      ctx->pair_search = (int)v;
+      return LK_OK;  // no captured graph depends on it
     case LK_OPT_BH_ADAPTIVE:
       if (v != 0 && v != 1) return ctx->fail(LK_EINVAL, "adaptive beta must be 0 or 1");
       ctx->bh_adaptive = v != 0;
@@ -956,15 +962,41 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
   double* boxes = (double*)ctx->boxes.p;
   int64_t* cnt = (int64_t*)ctx->vcounts.p;
   int64_t* pre = (int64_t*)ctx->vprefix.p;
+  // the grid pays off beyond a few thousand loops; both give the same pairs
+  const bool grid = ctx->pair_search == 2 || (ctx->pair_search == 0 && n_loops >= 2048);
+  lk::GridBufs G{};
+  if (grid) {
+    const size_t L = (size_t)n_loops;
+    G.buckets = 4 * (int64_t)n_loops + 64;
+    const size_t mc = (size_t)G.buckets;
+    const size_t o_cnt = 64, o_start = o_cnt + 8 * mc, o_of = o_start + 8 * (mc + 1);
+    const size_t o_items = o_of + 8 * L, o_over = o_items + 4 * L, o_nover = o_over + 4 * L;
+    if ((st = ensure(ctx, ctx->pls_grid, o_nover + 8)) != LK_OK) return st;
+    char* gb = (char*)ctx->pls_grid.p;
+    G.params = (lk::GridParams*)gb;
+    G.cell_count = (unsigned long long*)(gb + o_cnt);
+    G.cell_start = (int64_t*)(gb + o_start);
+    G.cell_of = (int64_t*)(gb + o_of);
+    G.cell_items = (int32_t*)(gb + o_items);
+    G.over = (int32_t*)(gb + o_over);
+    G.n_over = (int32_t*)(gb + o_nover);
+    G.row_counts = cnt;
+  }
   LK_HIP(lk::launch_boxes(xyz, dtype == LK_F64, off, n_loops, boxes, s));
-  LK_HIP(lk::launch_pair_count(boxes, n_loops, cnt, s));
+  if (grid)
+    LK_HIP(lk::launch_grid_pairs(boxes, n_loops, G, 0, nullptr, nullptr, s));
+  else
+    LK_HIP(lk::launch_pair_count(boxes, n_loops, cnt, s));
   LK_HIP(lk::launch_scan(cnt, n_loops, pre, s));
   int64_t total = 0;
   LK_HIP(hipMemcpyAsync(&total, pre + n_loops, 8, hipMemcpyDeviceToHost, s));
   LK_HIP(hipStreamSynchronize(s));
   *n_pairs = total;
-  if (total > 0 && capacity > 0) {
-    LK_HIP(lk::launch_pair_fill(boxes, n_loops, pre, pairs_out, capacity, s));
+  if (total > 0 && total <= capacity) {
+    if (grid)
+      LK_HIP(lk::launch_grid_pairs(boxes, n_loops, G, 1, pre, pairs_out, s));
+    else
+      LK_HIP(lk::launch_pair_fill(boxes, n_loops, pre, pairs_out, capacity, s));
     LK_HIP(hipStreamSynchronize(s));
   }
   if (total > capacity)

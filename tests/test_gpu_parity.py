@@ -205,6 +205,41 @@ def test_build_pairs_matches_oracle(ctx):
     assert ei.value.status == lk_mod._lib.ECAPACITY
 
 
+def test_grid_pair_search_matches_all_pairs(ctx):
+    """The grid search (LK_OPT_PAIR_SEARCH 2) returns exactly the pairs of the
+    all-pairs scan and of the oracle: chainmail and knit sheets, and a set
+    with an empty loop, one loop around everything, a loop with a NaN and an
+    infinite coordinate, many coincident loops (one crowded cell) and far
+    outliers."""
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    from paper_2106_12655_amd.inputs import _pack
+    rng = np.random.default_rng(4)
+    ring = I.circle(16)
+    loops = [ring * 0.3 + rng.uniform(0, 20, 3) for _ in range(3000)]
+    loops += [ring * 0.3 + np.array([5.0, 5.0, 5.0]) for _ in range(200)]  # one crowded cell
+    loops += [ring * 15.0 + 10.0, ring[:0], ring * 0.3 + 1e6]
+    bad = ring * 0.3 + 3.0
+    bad[2, 1] = np.nan
+    bad[5, 0] = np.inf
+    loops.append(bad)
+    odd = _pack(loops, np.float64, {}, "odd", 0)
+    cases = [I.chainmail(0, rows=60, cols=70), I.knit(2, n_loops=3000, cp_max=64, per_span=2), odd]
+    try:
+        for ls in cases:
+            xyz, off = _dev(ls)
+            res = []
+            for mode in (1, 2, 0):
+                ctx.set_option(lk_mod._lib.OPT_PAIR_SEARCH, mode)
+                res.append(ctx.build_pairs(xyz, off).cpu().numpy())
+            want = oracle.aabb_pairs(ls.xyz, ls.offsets)
+            print("%s: %d loops, %d pairs" % (ls.name, ls.n_loops, len(want)), flush=True)
+            for r in res:
+                assert np.array_equal(r, want), ls.name
+    finally:
+        ctx.set_option(lk_mod._lib.OPT_PAIR_SEARCH, 0)
+
+
 def _verify_reference(pairs, lk, ep, elk):
     cur = {tuple(p): v for p, v in zip(pairs.tolist(), lk.tolist())}
     exp = {tuple(p): v for p, v in zip(ep.tolist(), elk.tolist())}
