@@ -18,7 +18,10 @@
  *   - Geometry: xyz is a contiguous row-major array of V vertices x 3
  *     coordinates (float32 or float64, see lk_dtype).  Loop l owns vertices
  *     loop_offsets[l] .. loop_offsets[l+1]-1 (int64, n_loops+1 entries,
- *     non-decreasing).  A loop of n vertices is closed: segment s joins vertex
+ *     non-decreasing; calls that size buffers from the offsets -- the
+ *     CROSSINGS and BARNES_HUT modes and lk_discretize -- check this and
+ *     return LK_EINVAL, the direct sum treats a loop of negative size as an
+ *     invalid loop).  A loop of n vertices is closed: segment s joins vertex
  *     s to vertex (s+1) mod n; the first vertex is not repeated.
  *   - Pairs: int32 [n][2] row-major loop indices.  For pair (i, j) loop i plays
  *     gamma_1 of Eq. 4 (vertices l, index j) and loop j plays gamma_2

@@ -55,6 +55,8 @@ struct DzArgs {
   int64_t n, n_u;          // pieces and unprocessed pieces of cur (host copies)
 };
 
+// *bad (device int32, set to 0 by the caller) becomes 1 if the offsets decrease.
+hipError_t launch_dz_check(const int64_t* off, int32_t n_loops, int32_t* bad, hipStream_t s);
 hipError_t launch_dz_setup(const DzArgs& a, int64_t n_points, hipStream_t s);
 hipError_t launch_dz_pass(const DzArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_dz_finish(const DzArgs& a, double* xyz_out, int64_t capacity,

@@ -276,6 +276,15 @@ __global__ __launch_bounds__(kThreads) void dz_loops_k(DzArgs A) {
   }
 }
 
+// Offsets that decrease anywhere: *bad = 1 (the host rejects the call
+// before any kernel indexes with them).
+__global__ __launch_bounds__(kThreads) void dz_check_offsets_k(const int64_t* off, int32_t L,
+                                                               int32_t* bad) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < L;
+       i += (int64_t)gridDim.x * kThreads)
+    if (off[i + 1] < off[i]) *bad = 1;
+}
+
 // xi = mean over the points of (|x| + |y| + |z|) / 3; lim2 = (eps * xi)^2.
 __global__ __launch_bounds__(1024) void dz_xi_k(DzArgs A) {
   __shared__ double red[1024];
@@ -586,6 +595,12 @@ __global__ __launch_bounds__(kThreads) void dz_output_k(DzArgs A, double* xyz, i
 int64_t blocks_for(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 }  // namespace
+
+hipError_t launch_dz_check(const int64_t* off, int32_t n_loops, int32_t* bad, hipStream_t s) {
+  const int64_t b = blocks_for(n_loops);
+  dz_check_offsets_k<<<(unsigned)(b < 4096 ? b : 4096), kThreads, 0, s>>>(off, n_loops, bad);
+  return hipGetLastError();
+}
 
 hipError_t launch_dz_setup(const DzArgs& a, int64_t n_points, hipStream_t s) {
   const int64_t lb = (a.n_loops + 3) / 4;

@@ -184,7 +184,8 @@ constexpr size_t kMetaCountsRefit2 = 64; // int32[2]
 constexpr size_t kMetaRefitN2 = 72;      // int32 (follows the above)
 constexpr size_t kMetaBigTotalRefit2 = 80;
 constexpr size_t kMetaCounterRefit2 = 88;
-constexpr size_t kMetaBytes = 96;
+constexpr size_t kMetaOffsetsBad = 96;  // int32: offsets that decrease (set by a check)
+constexpr size_t kMetaBytes = 104;
 
 // Fused certificate check of a call (lk_direct_sum_check); empty for
 // lk_direct_sum.
@@ -532,10 +533,18 @@ lk_status ensure_workspace(lk_ctx* ctx, int32_t n_loops, int64_t n_pairs) {
 lk_status read_vertices(lk_ctx* ctx, const int64_t* off, int32_t n_loops, hipStream_t s,
                         bool can_sync, int64_t* v) {
   if (can_sync && (ctx->cc_off_key != off || ctx->cc_loops_key != n_loops)) {
+    // the block and node slots are computed from the offsets, so offsets that
+    // decrease are rejected here, in the same synchronisation
     int64_t ends[2] = {0, 0};
+    int32_t bad = 0;
+    int32_t* bad_d = meta_at<int32_t>(ctx, kMetaOffsetsBad);
+    LK_HIP(hipMemsetAsync(bad_d, 0, 4, s));
+    LK_HIP(lk::launch_dz_check(off, n_loops, bad_d, s));
+    LK_HIP(hipMemcpyAsync(&bad, bad_d, 4, hipMemcpyDeviceToHost, s));
     LK_HIP(hipMemcpyAsync(&ends[0], off, 8, hipMemcpyDeviceToHost, s));
     LK_HIP(hipMemcpyAsync(&ends[1], off + n_loops, 8, hipMemcpyDeviceToHost, s));
     LK_HIP(hipStreamSynchronize(s));
+    if (bad) return ctx->fail(LK_EINVAL, "loop offsets decrease");
     ctx->cc_off_key = off;
     ctx->cc_loops_key = n_loops;
     ctx->cc_vertices = ends[1] - ends[0] > 0 ? ends[1] - ends[0] : 0;
@@ -1027,22 +1036,28 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
       return ctx->fail(LK_EBUSY, "lk_discretize synchronises and cannot be captured");
   }
-  // the point count sizes every buffer: read it (one synchronisation)
+  // the point count sizes every buffer: read it, and whether the offsets
+  // ever decrease (one synchronisation)
+  const size_t L = (size_t)n_loops;
+  const size_t o_lsum = (4 * L + 7) / 8 * 8, o_off = o_lsum + 8 * L;
+  const size_t o_tot = o_off + 4 * 8 * (L + 1), o_lim = o_tot + 32;
+  if ((st = ensure(ctx, ctx->dz_loops, o_lim + 8)) != LK_OK) return st;
+  int32_t* bad_d = (int32_t*)((char*)ctx->dz_loops.p + o_tot);  // the totals slot, free until the passes
   int64_t ends[2] = {0, 0};
+  int32_t bad = 0;
+  LK_HIP(hipMemsetAsync(bad_d, 0, 4, s));
+  LK_HIP(lk::launch_dz_check(ctrl_offsets, n_loops, bad_d, s));
+  LK_HIP(hipMemcpyAsync(&bad, bad_d, 4, hipMemcpyDeviceToHost, s));
   LK_HIP(hipMemcpyAsync(&ends[0], ctrl_offsets, 8, hipMemcpyDeviceToHost, s));
   LK_HIP(hipMemcpyAsync(&ends[1], ctrl_offsets + n_loops, 8, hipMemcpyDeviceToHost, s));
   LK_HIP(hipStreamSynchronize(s));
   const int64_t N = ends[1] - ends[0];
-  if (N < 0) return ctx->fail(LK_EINVAL, "offsets decrease");
+  if (bad || N < 0) return ctx->fail(LK_EINVAL, "offsets decrease");
   // piece indices are int32 and the split packs two 32-bit counts
   const int64_t kMaxPieces = (int64_t)1 << 30;
   if (N > kMaxPieces) return ctx->fail(LK_EINVAL, "more than 2^30 input spans");
-  const size_t L = (size_t)n_loops;
-  // per-loop block: lflags [L] u32 | lsum [L] f64 | 4 offset arrays [L+1] i64 |
-  // totals [4] u64 | lim2 f64
-  const size_t o_lsum = (4 * L + 7) / 8 * 8, o_off = o_lsum + 8 * L;
-  const size_t o_tot = o_off + 4 * 8 * (L + 1), o_lim = o_tot + 32;
-  if ((st = ensure(ctx, ctx->dz_loops, o_lim + 8)) != LK_OK) return st;
+  // per-loop block (sized above): lflags [L] u32 | lsum [L] f64 | 4 offset
+  // arrays [L+1] i64 | totals [4] u64 | lim2 f64
   if ((st = ensure(ctx, ctx->dz_pair_pre, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
   if ((st = ensure(ctx, ctx->dz_pair_ab, 8 * (size_t)(n_pairs + 1))) != LK_OK) return st;
   auto piece_cap = [](const DevBuf& b) { return (int64_t)(b.bytes / lk::kDzBytesPerPiece); };

@@ -156,6 +156,12 @@ def test_pair_order_capacity_and_repeat(dctx):
     with pytest.raises(lk.LkError) as e:
         _gpu(dctx, k.xyz, k.offsets, pr, capacity=10)
     assert e.value.status == lk._lib.ECAPACITY
+    # offsets that decrease are rejected before any kernel uses them
+    bad = k.offsets.copy()
+    bad[3] = bad[5]
+    with pytest.raises(lk.LkError) as e:
+        _gpu(dctx, k.xyz, bad, pr)
+    assert e.value.status == lk._lib.EINVAL
 
 
 def test_full_knit_properties(dctx):

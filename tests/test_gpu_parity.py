@@ -378,3 +378,26 @@ def test_arctangent_forms_and_lane_blocking():
             segs, np.abs(got[0] - got[2]).max(), np.abs(got[1] - oreal).max()), flush=True)
         assert np.array_equal(got[0], got[2]), segs
     tctx.close()
+
+
+def test_decreasing_offsets(ctx):
+    """Offsets must not decrease.  The modes whose slots are computed from the
+    offsets (crossings, Barnes-Hut) check this when they read the vertex count
+    and reject the call; the direct sum treats such a loop as empty (invalid)
+    and never indexes with a negative size."""
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    ls = I.ring_grid(0)
+    xyz, off = _dev(ls)
+    bad = off.clone()
+    bad[5] = bad[7]
+    pr = torch.tensor([[0, 1], [4, 5], [8, 9]], dtype=torch.int32, device="cuda")
+    for mode in ("crossings", "barnes_hut"):
+        with pytest.raises(lk_mod.LkError) as ei:
+            ctx.direct_sum(xyz, bad, pr, mode)
+        assert ei.value.status == lk_mod._lib.EINVAL
+    real, lk, flags = ctx.direct_sum(xyz, bad, pr, "mixed")
+    torch.cuda.synchronize()
+    f = flags.cpu().numpy().view(np.uint32)
+    assert f[1] & lk_mod.FLAG_BADLOOP and f[0] == 0 and f[2] == 0
+    assert int(lk[0].item()) == int(ls.expected_for(np.array([[0, 1]]))[0])
