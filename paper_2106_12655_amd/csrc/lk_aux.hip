@@ -186,7 +186,9 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
     if (lane == 0) {
       if (slot < n_sup) sup[slot] = acc;
       if (f) atomicOr(&lf[lo], f);
-      if (mn < INFINITY)
+      // the entry only decreases, so a plain read that is not above mn
+      // makes the atomic unnecessary (thousands of blocks share one loop)
+      if (mn < INFINITY && mn < minseg2[lo])
         atomicMin(reinterpret_cast<unsigned long long*>(&minseg2[lo]),
                   (unsigned long long)__double_as_longlong(mn));
     }

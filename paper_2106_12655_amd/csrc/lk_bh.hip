@@ -55,26 +55,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // --------------------------------------------------------------- leaves
-// One wavefront per leaf slot: lane t holds segment t of the leaf.  The box
-// covers the leaf's vertices (with the one closing its last segment); a
-// segment with vector s and midpoint offset d from the centre adds s, s d^T
-// and s (x) d (x) d + s (x) s (x) s / 12 (its exact moments).  The same pass
-// validates the loops in parallel over their leaves (non-finite coordinates,
-// shortest squared segment), folding into the per-loop entries with atomics
-// (a minimum of non-negative doubles is a minimum of their bit patterns).
+// One wavefront (one workgroup) per leaf slot: lane t holds segment t of the
+// leaf.  The box covers the leaf's vertices (with the one closing its last
+// segment); a segment with vector s and midpoint offset d from the centre
+// adds s, s d^T and s (x) d (x) d + s (x) s (x) s / 12 (its exact moments).
+// The lanes stage s and d in LDS, and lane j < 39 then sums moment j over
+// the segments in order, so the 45 values of the node are written by 45
+// lanes at once.  The same pass validates the loops in parallel over their
+// leaves (non-finite coordinates, shortest squared segment), folding into the
+// per-loop entries with atomics (a minimum of non-negative doubles is a
+// minimum of their bit patterns).
+static_assert(sizeof(BhNode) == 45 * sizeof(double), "BhNode is c, e, M, D, Q back to back");
+
 template <typename Tin>
-__global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
+__global__ __launch_bounds__(64) void bh_leaves_k(BhArgs A) {
+  __shared__ double sd[kBhLeaf][8];  // per segment: s[3], d[3]
   if (blockIdx.x == 0 && threadIdx.x < kBhMaxIters + 3) A.counts[threadIdx.x] = 0;
   const Tin* X = static_cast<const Tin*>(A.xyz);
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x;
   const int64_t n_slots = level_slots(A, 0);
-  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
-  for (int64_t slot = wave; slot < n_slots; slot += nwaves) {
+  // moment j of this lane: c_M[p] (j < 3), C_D[p][b] (j < 12), C_Q[p][b][c]
+  const int j = lane - 6;
+  const int jq = j - 12, jd = j - 3;
+  const int mp = j < 3 ? j : (j < 12 ? jd / 3 : jq / 9);
+  const int mb = j < 12 ? jd % 3 : (jq / 3) % 3;
+  const int mc = jq % 3;
+  for (int64_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
     const int32_t i = find_loop(A.off, A.n_loops, slot, kBhLeaf);
     const int64_t oi = A.off[i], n = A.off[i + 1] - oi;
     const int64_t k = slot - ((oi - A.off[0]) / kBhLeaf + i);
-    if (k >= bh_count(n, 0)) continue;  // uniform over the wave
+    if (k >= bh_count(n, 0)) continue;  // uniform over the workgroup
     const int64_t a = k * kBhLeaf;
     const int m = (int)((n - a) < kBhLeaf ? (n - a) : kBhLeaf);
     double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0};
@@ -103,7 +113,9 @@ __global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
       }
       if (lane == 0) {
         if (f) atomicOr(&A.lf[i], f);
-        if (mn < INFINITY)
+        // the entry only decreases, so a plain read that is not above mn
+        // makes the atomic unnecessary (thousands of leaves share one loop)
+        if (mn < INFINITY && mn < A.minseg2[i])
           atomicMin(reinterpret_cast<unsigned long long*>(&A.minseg2[i]),
                     (unsigned long long)__double_as_longlong(mn));
       }
@@ -113,28 +125,46 @@ __global__ __launch_bounds__(256) void bh_leaves_k(BhArgs A) {
         lo[q] = fmin(lo[q], __shfl_xor(lo[q], o));
         hi[q] = fmax(hi[q], __shfl_xor(hi[q], o));
       }
-    BhNode nd;
+    double c[3], e[3];
     for (int q = 0; q < 3; ++q) {
-      nd.c[q] = 0.5 * (lo[q] + hi[q]);
-      nd.e[q] = 0.5 * (hi[q] - lo[q]);
+      c[q] = 0.5 * (lo[q] + hi[q]);
+      e[q] = 0.5 * (hi[q] - lo[q]);
     }
-    double s[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+    __syncthreads();  // the previous slot's reads of sd are done
     if (lane < m)
       for (int q = 0; q < 3; ++q) {
-        s[q] = x1[q] - x0[q];
-        d[q] = 0.5 * (x0[q] + x1[q]) - nd.c[q];
+        sd[lane][q] = x1[q] - x0[q];
+        sd[lane][3 + q] = 0.5 * (x0[q] + x1[q]) - c[q];
       }
-    for (int p = 0; p < 3; ++p) {
-      nd.M[p] = wave_sum(s[p]);
-      for (int b = 0; b < 3; ++b) {
-        nd.D[3 * p + b] = wave_sum(s[p] * d[b]);
-        for (int c = 0; c < 3; ++c)
-          nd.Q[9 * p + 3 * b + c] =
-              wave_sum(s[p] * d[b] * d[c] + s[p] * s[b] * s[c] * (1.0 / 12.0));
+    __syncthreads();
+    double v = 0.0;
+    if (j >= 0 && j < 39)
+      for (int r = 0; r < m; ++r) {
+        const double s0 = sd[r][0], s1 = sd[r][1], s2 = sd[r][2];
+        const double d0 = sd[r][3], d1 = sd[r][4], d2 = sd[r][5];
+        const double sp = mp == 0 ? s0 : (mp == 1 ? s1 : s2);
+        if (j < 3) {
+          v += sp;
+        } else {
+          const double db = mb == 0 ? d0 : (mb == 1 ? d1 : d2);
+          if (j < 12) {
+            v += sp * db;
+          } else {
+            const double dc = mc == 0 ? d0 : (mc == 1 ? d1 : d2);
+            const double sb = mb == 0 ? s0 : (mb == 1 ? s1 : s2);
+            const double sc = mc == 0 ? s0 : (mc == 1 ? s1 : s2);
+            v += sp * db * dc + sp * sb * sc * (1.0 / 12.0);
+          }
+        }
       }
-    }
+    // node layout: c[3], e[3], M[3], D[9], Q[27] -- 45 doubles, one per lane
     const int64_t dst = A.level_base[0] + slot;
-    if (lane == 0 && slot < A.level_cap[0]) A.nodes[dst] = nd;
+    if (lane < 45 && slot < A.level_cap[0]) {
+      const int q = lane % 3;
+      const double cq = q == 0 ? c[0] : (q == 1 ? c[1] : c[2]);
+      const double eq = q == 0 ? e[0] : (q == 1 ? e[1] : e[2]);
+      reinterpret_cast<double*>(&A.nodes[dst])[lane] = lane < 3 ? cq : (lane < 6 ? eq : v);
+    }
   }
 }
 
@@ -530,11 +560,11 @@ inline int grid_for(int64_t n, int per_block, int cap) {
 }  // namespace
 
 hipError_t launch_bh_leaves(const BhArgs& a, bool in_f64, hipStream_t s) {
-  const int g = grid_for(a.level_cap[0], 4, 16384);
+  const int g = grid_for(a.level_cap[0], 1, 65536);
   if (in_f64)
-    bh_leaves_k<double><<<g, 256, 0, s>>>(a);
+    bh_leaves_k<double><<<g, 64, 0, s>>>(a);
   else
-    bh_leaves_k<float><<<g, 256, 0, s>>>(a);
+    bh_leaves_k<float><<<g, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
