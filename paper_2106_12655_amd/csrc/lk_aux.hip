@@ -555,16 +555,18 @@ __device__ __forceinline__ int64_t grid_coord(const GridParams& g, const double*
   return c < 4.0e18 ? (int64_t)c : (int64_t)4000000000000000000ll;
 }
 
+// buckets is a power of two, so the hash is masked rather than divided
 __device__ __forceinline__ int64_t grid_bucket(const GridParams& g, int64_t x, int64_t y,
                                                int64_t z) {
   const uint64_t k = ((uint64_t)x * 73856093ull) ^ ((uint64_t)y * 19349663ull) ^
                      ((uint64_t)z * 83492791ull);
-  return (int64_t)(k % (uint64_t)g.buckets);
+  return (int64_t)((k ^ (k >> 29)) & (uint64_t)(g.buckets - 1));
 }
 
-// One workgroup: h = 4 x the mean box size (the largest side per box), the
-// origin at the regular boxes' least min corner; zeroes the bucket counts and
-// the large-box count.
+// One workgroup: h = 2 x the largest box size (the largest side per box)
+// among the boxes no larger than 4 x the mean size, so those are all regular
+// and the cells stay small; the origin at the regular boxes' least min
+// corner; zeroes the bucket counts and the large-box count.
 __global__ __launch_bounds__(1024) void grid_params_k(const double* box, int32_t L,
                                                       int64_t buckets, GridParams* gp,
                                                       unsigned long long* cell_count,
@@ -592,10 +594,24 @@ __global__ __launch_bounds__(1024) void grid_params_k(const double* box, int32_t
     }
     __syncthreads();
   }
-  if (t == 0) {
-    const double mean = rc[0] > 0.0 ? rs[0] / rc[0] : 0.0;
-    h_s = mean > 0.0 ? 4.0 * mean : 1.0;
+  if (t == 0) h_s = rc[0] > 0.0 ? rs[0] / rc[0] : 0.0;  // the mean size
+  __syncthreads();
+  const double cap = 4.0 * h_s;
+  double em = 0.0;
+  for (int64_t i = t; i < L; i += 1024) {
+    const double* b = box + 6 * i;
+    double e = -1.0;
+    for (int q = 0; q < 3; ++q) e = fmax(e, b[3 + q] - b[q]);
+    if (isfinite(e) && e <= cap) em = fmax(em, e);
   }
+  __syncthreads();
+  rs[t] = em;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) rs[t] = fmax(rs[t], rs[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) h_s = rs[0] > 0.0 ? 2.0 * rs[0] : 1.0;
   __syncthreads();
   const double h = h_s;
   double mn[3] = {INFINITY, INFINITY, INFINITY};
@@ -642,68 +658,89 @@ __global__ __launch_bounds__(256) void grid_bin_k(const double* box, int32_t L,
   }
 }
 
-// cell_count still holds the counts: each box takes a slot by counting down.
-__global__ __launch_bounds__(256) void grid_scatter_k(int32_t L, const int64_t* cell_of,
+// cell_count still holds the counts: each box takes a slot by counting down;
+// a copy of the box goes with it, so a bucket's boxes are read contiguously.
+__global__ __launch_bounds__(256) void grid_scatter_k(const double* box, int32_t L,
+                                                      const int64_t* cell_of,
                                                       const int64_t* cell_start,
                                                       unsigned long long* cell_count,
-                                                      int32_t* cell_items) {
+                                                      int32_t* cell_items, double* cell_box) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
     const int64_t c = cell_of[i];
     if (c < 0) continue;
     const unsigned long long k = atomicAdd(&cell_count[c], ~0ull);  // - 1
-    cell_items[cell_start[c] + (int64_t)k - 1] = (int32_t)i;
+    const int64_t pos = cell_start[c] + (int64_t)k - 1;
+    cell_items[pos] = (int32_t)i;
+    for (int q = 0; q < 6; ++q) cell_box[6 * pos + q] = box[6 * i + q];
   }
 }
 
-// Row i: the pairs (i, j > i).  WRITE = 0 counts, 1 fills (unsorted for a
-// regular box, ascending j for the others).
+// Row i: the pairs (i, j > i), one wavefront per row, the lanes testing
+// candidates side by side.  WRITE = 0 counts, 1 fills (in bucket order for a
+// regular box; ascending j for the others, since each chunk of 64 is emitted
+// in lane order).
 template <int WRITE>
 __global__ __launch_bounds__(256) void grid_rows_k(const double* box, int32_t L,
                                                    const GridParams* gp, const int64_t* cell_of,
                                                    const int64_t* cell_start,
-                                                   const int32_t* cell_items, const int32_t* over,
+                                                   const int32_t* cell_items,
+                                                   const double* cell_box, const int32_t* over,
                                                    const int32_t* n_over, int64_t* counts,
                                                    const int64_t* row_start, int32_t* out) {
   const GridParams g = *gp;
   const int32_t no = *n_over;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+  for (int64_t i = wave; i < L; i += nwaves) {
     double me[6];
     for (int q = 0; q < 6; ++q) me[q] = box[6 * i + q];
-    int64_t cnt = 0;
-    int64_t pos = WRITE ? row_start[i] : 0;
-    auto emit = [&](int64_t j) {
-      if (WRITE) {
-        out[2 * pos] = (int32_t)i;
-        out[2 * pos + 1] = (int32_t)j;
-        ++pos;
-      } else {
-        ++cnt;
+    int64_t pos = WRITE ? row_start[i] : 0;  // uniform over the wave
+    // all lanes call it; lane with `hit` writes (i, j) in lane order
+    auto emit = [&](bool hit, int64_t j) {
+      const unsigned long long m = __ballot(hit);
+      if (WRITE && hit) {
+        const int64_t at = pos + __popcll(m & below);
+        out[2 * at] = (int32_t)i;
+        out[2 * at + 1] = (int32_t)j;
       }
+      pos += __popcll(m);
     };
     if (cell_of[i] >= 0) {
       const int64_t c0 = grid_coord(g, me, 0), c1 = grid_coord(g, me, 1), c2 = grid_coord(g, me, 2);
+      // lane t < 27 hashes neighbour cell t; a bucket reached by two
+      // neighbour cells is visited once (at its first lane)
+      const int tl = lane < 27 ? lane : 0;
+      const int64_t mine = grid_bucket(g, c0 + tl % 3 - 1, c1 + (tl / 3) % 3 - 1, c2 + tl / 9 - 1);
+      bool dup = false;
+      for (int u = 0; u < 27; ++u) {
+        const int64_t bu = __shfl(mine, u);
+        dup = dup || (u < lane && bu == mine);
+      }
+      const unsigned long long visit = __ballot(lane < 27 && !dup);
       for (int t = 0; t < 27; ++t) {
-        const int64_t c = grid_bucket(g, c0 + t % 3 - 1, c1 + (t / 3) % 3 - 1, c2 + t / 9 - 1);
-        // two neighbour cells in one bucket: visit it once (hashes recomputed,
-        // so nothing is kept in memory)
-        bool dup = false;
-        for (int u = 0; u < t; ++u)
-          dup = dup || grid_bucket(g, c0 + u % 3 - 1, c1 + (u / 3) % 3 - 1, c2 + u / 9 - 1) == c;
-        if (dup) continue;
-        for (int64_t k = cell_start[c]; k < cell_start[c + 1]; ++k) {
-          const int32_t j = cell_items[k];
-          if (j > i && overlap(me, box + 6 * (int64_t)j)) emit(j);
+        if (!((visit >> t) & 1ull)) continue;
+        const int64_t c = __shfl(mine, t);
+        for (int64_t k0 = cell_start[c]; k0 < cell_start[c + 1]; k0 += 64) {
+          const int64_t k = k0 + lane;
+          const bool in = k < cell_start[c + 1];
+          const int32_t j = in ? cell_items[k] : -1;
+          emit(in && j > i && overlap(me, cell_box + 6 * k), j);
         }
       }
-      for (int32_t k = 0; k < no; ++k) {
-        const int32_t j = over[k];
-        if (j > i && overlap(me, box + 6 * (int64_t)j)) emit(j);
+      for (int32_t k0 = 0; k0 < no; k0 += 64) {
+        const int32_t k = k0 + lane;
+        const int32_t j = k < no ? over[k] : -1;
+        emit(k < no && j > i && overlap(me, box + 6 * (int64_t)j), j);
       }
     } else {
-      for (int64_t j = i + 1; j < L; ++j)
-        if (overlap(me, box + 6 * j)) emit(j);
+      for (int64_t j0 = i + 1; j0 < L; j0 += 64) {
+        const int64_t j = j0 + lane;
+        emit(j < L && overlap(me, box + 6 * (j < L ? j : 0)), j);
+      }
     }
-    if (!WRITE) counts[i] = cnt;
+    if (!WRITE && lane == 0) counts[i] = pos;
   }
 }
 
@@ -902,6 +939,7 @@ hipError_t launch_pair_fill(const double* boxes, int32_t n_loops, const int64_t*
 hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBufs& b, int pass,
                              const int64_t* row_start, int32_t* pairs_out, hipStream_t s) {
   const int g = blocks_for(n_loops, 256, 4096);
+  const int gw = blocks_for((int64_t)n_loops * 64, 256, 16384);  // one wavefront per row
   switch (pass) {
     case 0:  // grid, binning and the per-cell scan
       grid_params_k<<<1, 1024, 0, s>>>(boxes, n_loops, b.buckets, b.params, b.cell_count,
@@ -910,16 +948,16 @@ hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBuf
                                    b.n_over);
       scan_k<<<1, 1024, 0, s>>>(reinterpret_cast<const int64_t*>(b.cell_count), b.buckets,
                                 b.cell_start);
-      grid_scatter_k<<<g, 256, 0, s>>>(n_loops, b.cell_of, b.cell_start, b.cell_count,
-                                       b.cell_items);
-      grid_rows_k<0><<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
-                                       b.cell_items, b.over, b.n_over, b.row_counts, nullptr,
-                                       nullptr);
+      grid_scatter_k<<<g, 256, 0, s>>>(boxes, n_loops, b.cell_of, b.cell_start, b.cell_count,
+                                       b.cell_items, b.cell_box);
+      grid_rows_k<0><<<gw, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
+                                       b.cell_items, b.cell_box, b.over, b.n_over, b.row_counts,
+                                       nullptr, nullptr);
       break;
     default:  // fill and sort the rows
-      grid_rows_k<1><<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
-                                       b.cell_items, b.over, b.n_over, nullptr, row_start,
-                                       pairs_out);
+      grid_rows_k<1><<<gw, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
+                                       b.cell_items, b.cell_box, b.over, b.n_over, nullptr,
+                                       row_start, pairs_out);
       grid_sort_rows_k<<<g, 256, 0, s>>>(n_loops, b.cell_of, row_start, pairs_out);
       break;
   }

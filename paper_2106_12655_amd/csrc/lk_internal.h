@@ -383,7 +383,7 @@ hipError_t launch_pair_fill(const double* boxes, int32_t n_loops, const int64_t*
 struct GridParams {
   double h;         // cell size; boxes with every side at most h / 2 are binned
   double lo[3];     // grid origin
-  int64_t buckets;  // hash table size
+  int64_t buckets;  // hash table size (a power of two)
 };
 struct GridBufs {
   GridParams* params;
@@ -391,6 +391,7 @@ struct GridBufs {
   int64_t* cell_start;             // [buckets + 1]
   int64_t* cell_of;                // [L] bucket, -1 for a box tested against all
   int32_t* cell_items;             // [L]
+  double* cell_box;                // [L][6] the boxes in bucket order
   int32_t* over;                   // [L]
   int32_t* n_over;
   int64_t* row_counts;             // [L]

@@ -976,10 +976,12 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
   lk::GridBufs G{};
   if (grid) {
     const size_t L = (size_t)n_loops;
-    G.buckets = 4 * (int64_t)n_loops + 64;
+    G.buckets = 64;  // a power of two of at least 4 buckets per loop
+    while (G.buckets < 4 * (int64_t)n_loops) G.buckets *= 2;
     const size_t mc = (size_t)G.buckets;
     const size_t o_cnt = 64, o_start = o_cnt + 8 * mc, o_of = o_start + 8 * (mc + 1);
-    const size_t o_items = o_of + 8 * L, o_over = o_items + 4 * L, o_nover = o_over + 4 * L;
+    const size_t o_cbox = o_of + 8 * L, o_items = o_cbox + 48 * L;
+    const size_t o_over = o_items + 4 * L, o_nover = o_over + 4 * L;
     if ((st = ensure(ctx, ctx->pls_grid, o_nover + 8)) != LK_OK) return st;
     char* gb = (char*)ctx->pls_grid.p;
     G.params = (lk::GridParams*)gb;
@@ -987,6 +989,7 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
     G.cell_start = (int64_t*)(gb + o_start);
     G.cell_of = (int64_t*)(gb + o_of);
     G.cell_items = (int32_t*)(gb + o_items);
+    G.cell_box = (double*)(gb + o_cbox);
     G.over = (int32_t*)(gb + o_over);
     G.n_over = (int32_t*)(gb + o_nover);
     G.row_counts = cnt;
