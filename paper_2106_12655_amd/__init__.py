@@ -116,7 +116,9 @@ class Context:
         self._dev(offsets, torch.int64, "offsets")
         L = offsets.numel() - 1
         n = ctypes.c_int64(0)
-        cap = int(capacity) if capacity is not None else 0
+        # a first guess of 8 pairs per loop; the exact count comes back with
+        # LK_ECAPACITY when it is too small, and the search runs again
+        cap = int(capacity) if capacity is not None else 8 * max(L, 0) + 1024
         out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=xyz.device)
         st = self.lib.lk_build_pairs(self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), L,
                                      _ptr(out) if cap > 0 else ctypes.c_void_p(0), cap,
