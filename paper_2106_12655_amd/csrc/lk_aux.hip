@@ -563,87 +563,151 @@ __device__ __forceinline__ int64_t grid_bucket(const GridParams& g, int64_t x, i
   return (int64_t)((k ^ (k >> 29)) & (uint64_t)(g.buckets - 1));
 }
 
-// One workgroup: h = 2 x the largest box size (the largest side per box)
-// among the boxes no larger than 4 x the mean size, so those are all regular
-// and the cells stay small; the origin at the regular boxes' least min
-// corner; zeroes the bucket counts and the large-box count.
-__global__ __launch_bounds__(1024) void grid_params_k(const double* box, int32_t L,
-                                                      int64_t buckets, GridParams* gp,
-                                                      unsigned long long* cell_count,
-                                                      int32_t* n_over) {
-  __shared__ double rs[1024], rc[1024], rmin[3][1024];
-  __shared__ double h_s;
-  const int t = threadIdx.x;
+// The grid parameters in three passes over the boxes; grid_bin_k finishes
+// them from the partials.  Every reduction runs in a fixed order (64 workgroup
+// partials, each a tree in LDS), so the cell size does not depend on
+// scheduling.  Pass 0 sums the box sizes (the largest side per box) and
+// clears the bucket counts; pass 1 takes the largest size not above 4 x their
+// mean; pass 2 takes the least min corner of the boxes regular at h = 2 x that
+// largest size.  A box's size and regularity use the same tests everywhere.
+__device__ __forceinline__ double grid_box_size(const double* b) {
+  double e = -1.0;
+  for (int q = 0; q < 3; ++q) e = fmax(e, b[3 + q] - b[q]);
+  return e;
+}
+
+// every thread of every workgroup reduces the partials the same way
+__device__ __forceinline__ double grid_size_cap(const double* part) {
   double s = 0.0, c = 0.0;
-  for (int64_t i = t; i < L; i += 1024) {
-    const double* b = box + 6 * i;
-    double e = -1.0;
-    for (int q = 0; q < 3; ++q) e = fmax(e, b[3 + q] - b[q]);
-    if (isfinite(e) && e >= 0.0) {
-      s += e;
-      c += 1.0;
-    }
+  for (int k = 0; k < kGridStatBlocks; ++k) {
+    s += part[k];
+    c += part[kGridStatBlocks + k];
   }
-  rs[t] = s;
-  rc[t] = c;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) {
-      rs[t] += rs[t + w];
-      rc[t] += rc[t + w];
-    }
-    __syncthreads();
-  }
-  if (t == 0) h_s = rc[0] > 0.0 ? rs[0] / rc[0] : 0.0;  // the mean size
-  __syncthreads();
-  const double cap = 4.0 * h_s;
+  return 4.0 * (c > 0.0 ? s / c : 0.0);
+}
+__device__ __forceinline__ double grid_cell_size(const double* part) {
   double em = 0.0;
-  for (int64_t i = t; i < L; i += 1024) {
+  for (int k = 0; k < kGridStatBlocks; ++k) em = fmax(em, part[2 * kGridStatBlocks + k]);
+  return em > 0.0 ? 2.0 * em : 1.0;
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void grid_stats_k(const double* box, int32_t L,
+                                                    int64_t buckets, double* part,
+                                                    unsigned long long* cell_count,
+                                                    int32_t* n_over) {
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
+  const double cap = PASS == 1 ? grid_size_cap(part) : 0.0;
+  const double h = PASS == 2 ? grid_cell_size(part) : 0.0;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (PASS == 2) v[0] = v[1] = v[2] = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < L; i += kGridStatBlocks * 256) {
     const double* b = box + 6 * i;
-    double e = -1.0;
-    for (int q = 0; q < 3; ++q) e = fmax(e, b[3 + q] - b[q]);
-    if (isfinite(e) && e <= cap) em = fmax(em, e);
+    if (PASS == 0) {
+      const double e = grid_box_size(b);
+      if (isfinite(e) && e >= 0.0) {
+        v[0] += e;
+        v[1] += 1.0;
+      }
+    } else if (PASS == 1) {
+      const double e = grid_box_size(b);
+      if (isfinite(e) && e <= cap) v[0] = fmax(v[0], e);
+    } else if (box_regular(b, h)) {
+      for (int q = 0; q < 3; ++q) v[q] = fmin(v[q], b[q]);
+    }
   }
-  __syncthreads();
-  rs[t] = em;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) rs[t] = fmax(rs[t], rs[t + w]);
-    __syncthreads();
+  if (PASS == 0) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + t; k < buckets; k += kGridStatBlocks * 256)
+      cell_count[k] = 0ull;
+    if (blockIdx.x == 0 && t == 0) *n_over = 0;
   }
-  if (t == 0) h_s = rs[0] > 0.0 ? 2.0 * rs[0] : 1.0;
+  for (int q = 0; q < 3; ++q) red[q][t] = v[q];
   __syncthreads();
-  const double h = h_s;
-  double mn[3] = {INFINITY, INFINITY, INFINITY};
-  for (int64_t i = t; i < L; i += 1024) {
-    const double* b = box + 6 * i;
-    if (!box_regular(b, h)) continue;
-    for (int q = 0; q < 3; ++q) mn[q] = fmin(mn[q], b[q]);
-  }
-  for (int q = 0; q < 3; ++q) rmin[q][t] = mn[q];
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w)
-      for (int q = 0; q < 3; ++q) rmin[q][t] = fmin(rmin[q][t], rmin[q][t + w]);
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      if (PASS == 0) {
+        red[0][t] += red[0][t + w];
+        red[1][t] += red[1][t + w];
+      } else if (PASS == 1) {
+        red[0][t] = fmax(red[0][t], red[0][t + w]);
+      } else {
+        for (int q = 0; q < 3; ++q) red[q][t] = fmin(red[q][t], red[q][t + w]);
+      }
+    }
     __syncthreads();
   }
   if (t == 0) {
-    GridParams g;
-    g.h = h;
-    for (int q = 0; q < 3; ++q) g.lo[q] = isfinite(rmin[q][0]) ? rmin[q][0] : 0.0;
-    g.buckets = buckets;
-    *gp = g;
-    *n_over = 0;
+    if (PASS == 0) {
+      part[blockIdx.x] = red[0][0];
+      part[kGridStatBlocks + blockIdx.x] = red[1][0];
+    } else if (PASS == 1) {
+      part[2 * kGridStatBlocks + blockIdx.x] = red[0][0];
+    } else {
+      for (int q = 0; q < 3; ++q) part[(3 + q) * kGridStatBlocks + blockIdx.x] = red[q][0];
+    }
   }
-  for (int64_t k = t; k < buckets; k += 1024) cell_count[k] = 0ull;
 }
 
+__device__ GridParams grid_params_of(const double* part, int64_t buckets) {
+  GridParams g;
+  g.h = grid_cell_size(part);
+  for (int q = 0; q < 3; ++q) {
+    double m = INFINITY;
+    for (int k = 0; k < kGridStatBlocks; ++k) m = fmin(m, part[(3 + q) * kGridStatBlocks + k]);
+    g.lo[q] = isfinite(m) ? m : 0.0;
+  }
+  g.buckets = buckets;
+  return g;
+}
+
+// Exclusive scan across workgroups of 4096 entries: the tiles' totals, a
+// single-workgroup scan of those into tile offsets (whose last entry is the
+// grand total), then each tile's scan from its offset.
+__global__ __launch_bounds__(1024) void tile_sums_k(const int64_t* counts, int64_t n,
+                                                    int64_t* tile_sum) {
+  __shared__ int64_t wsum[16];
+  const int64_t k0 = (int64_t)blockIdx.x * 4096 + 4 * (int64_t)threadIdx.x;
+  int64_t v = 0;
+  for (int i = 0; i < 4; ++i) v += (k0 + i < n) ? counts[k0 + i] : 0;
+  int64_t tot = 0;
+  block_excl_scan(v, wsum, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void tile_scan_k(const int64_t* counts, int64_t n,
+                                                    const int64_t* tile_off, int64_t* prefix) {
+  __shared__ int64_t wsum[16];
+  const int64_t k0 = (int64_t)blockIdx.x * 4096 + 4 * (int64_t)threadIdx.x;
+  int64_t v[4], sum = 0;
+  for (int i = 0; i < 4; ++i) {
+    v[i] = (k0 + i < n) ? counts[k0 + i] : 0;
+    sum += v[i];
+  }
+  int64_t tot = 0;
+  int64_t run = tile_off[blockIdx.x] + block_excl_scan(sum, wsum, &tot);
+  for (int i = 0; i < 4; ++i) {
+    if (k0 + i < n) prefix[k0 + i] = run;
+    run += v[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) prefix[n] = tile_off[gridDim.x];
+}
+
+// Each workgroup finishes the grid parameters from the partials (the same
+// fixed order everywhere); the first one stores them for the later kernels.
 __global__ __launch_bounds__(256) void grid_bin_k(const double* box, int32_t L,
-                                                  const GridParams* gp,
+                                                  const double* part, int64_t buckets,
+                                                  GridParams* gp,
                                                   unsigned long long* cell_count,
                                                   int64_t* cell_of, int32_t* over,
                                                   int32_t* n_over) {
-  const GridParams g = *gp;
+  __shared__ GridParams gs;
+  if (threadIdx.x == 0) {
+    gs = grid_params_of(part, buckets);
+    if (blockIdx.x == 0) *gp = gs;
+  }
+  __syncthreads();
+  const GridParams g = gs;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < L; i += (int64_t)gridDim.x * 256) {
     const double* b = box + 6 * i;
     if (box_regular(b, g.h)) {
@@ -941,19 +1005,28 @@ hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBuf
   const int g = blocks_for(n_loops, 256, 4096);
   const int gw = blocks_for((int64_t)n_loops * 64, 256, 16384);  // one wavefront per row
   switch (pass) {
-    case 0:  // grid, binning and the per-cell scan
-      grid_params_k<<<1, 1024, 0, s>>>(boxes, n_loops, b.buckets, b.params, b.cell_count,
-                                       b.n_over);
-      grid_bin_k<<<g, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_count, b.cell_of, b.over,
-                                   b.n_over);
-      scan_k<<<1, 1024, 0, s>>>(reinterpret_cast<const int64_t*>(b.cell_count), b.buckets,
-                                b.cell_start);
+    case 0: {  // grid, binning and the per-cell scan
+      grid_stats_k<0><<<kGridStatBlocks, 256, 0, s>>>(boxes, n_loops, b.buckets, b.part,
+                                                      b.cell_count, b.n_over);
+      grid_stats_k<1><<<kGridStatBlocks, 256, 0, s>>>(boxes, n_loops, b.buckets, b.part,
+                                                      nullptr, nullptr);
+      grid_stats_k<2><<<kGridStatBlocks, 256, 0, s>>>(boxes, n_loops, b.buckets, b.part,
+                                                      nullptr, nullptr);
+      grid_bin_k<<<g, 256, 0, s>>>(boxes, n_loops, b.part, b.buckets, b.params, b.cell_count,
+                                   b.cell_of, b.over, b.n_over);
+      const int64_t nt = (b.buckets + 4095) / 4096;
+      const int64_t* counts = reinterpret_cast<const int64_t*>(b.cell_count);
+      tile_sums_k<<<(unsigned)nt, 1024, 0, s>>>(counts, b.buckets, b.tiles);
+      scan_k<<<1, 1024, 0, s>>>(b.tiles, nt, b.tiles + nt + 1);
+      tile_scan_k<<<(unsigned)nt, 1024, 0, s>>>(counts, b.buckets, b.tiles + nt + 1,
+                                                b.cell_start);
       grid_scatter_k<<<g, 256, 0, s>>>(boxes, n_loops, b.cell_of, b.cell_start, b.cell_count,
                                        b.cell_items, b.cell_box);
       grid_rows_k<0><<<gw, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
                                        b.cell_items, b.cell_box, b.over, b.n_over, b.row_counts,
                                        nullptr, nullptr);
       break;
+    }
     default:  // fill and sort the rows
       grid_rows_k<1><<<gw, 256, 0, s>>>(boxes, n_loops, b.params, b.cell_of, b.cell_start,
                                        b.cell_items, b.cell_box, b.over, b.n_over, nullptr,

@@ -378,7 +378,7 @@ hipError_t launch_pair_fill(const double* boxes, int32_t n_loops, const int64_t*
                             int32_t* pairs_out, int64_t capacity, hipStream_t s);
 
 // Potential link search on a hashed grid of the boxes' min corners (see
-// grid_params_k): the same pairs as launch_pair_count / launch_pair_fill in
+// grid_stats_k): the same pairs as launch_pair_count / launch_pair_fill in
 // about L x (boxes in 27 buckets) tests instead of L^2 / 2.
 struct GridParams {
   double h;         // cell size; boxes with every side at most h / 2 are binned
@@ -395,8 +395,11 @@ struct GridBufs {
   int32_t* over;                   // [L]
   int32_t* n_over;
   int64_t* row_counts;             // [L]
+  double* part;                    // [kGridStatBlocks][6] per-workgroup partials
+  int64_t* tiles;                  // [2 (buckets / 4096 + 2)] tile sums and offsets
   int64_t buckets;
 };
+constexpr int kGridStatBlocks = 64;
 // pass 0: grid, binning, per-row counts into row_counts; pass 1 (after the
 // caller's scan of the counts into row_start): fill and sort the rows.
 hipError_t launch_grid_pairs(const double* boxes, int32_t n_loops, const GridBufs& b, int pass,

@@ -982,7 +982,9 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
     const size_t o_cnt = 64, o_start = o_cnt + 8 * mc, o_of = o_start + 8 * (mc + 1);
     const size_t o_cbox = o_of + 8 * L, o_items = o_cbox + 48 * L;
     const size_t o_over = o_items + 4 * L, o_nover = o_over + 4 * L;
-    if ((st = ensure(ctx, ctx->pls_grid, o_nover + 8)) != LK_OK) return st;
+    const size_t o_part = o_nover + 64, o_tiles = o_part + 8 * 6 * lk::kGridStatBlocks;
+    const size_t n_tiles = (mc + 4095) / 4096;
+    if ((st = ensure(ctx, ctx->pls_grid, o_tiles + 8 * 2 * (n_tiles + 2))) != LK_OK) return st;
     char* gb = (char*)ctx->pls_grid.p;
     G.params = (lk::GridParams*)gb;
     G.cell_count = (unsigned long long*)(gb + o_cnt);
@@ -992,6 +994,8 @@ lk_status lk_build_pairs(lk_ctx* ctx, const void* xyz, int dtype, const int64_t*
     G.cell_box = (double*)(gb + o_cbox);
     G.over = (int32_t*)(gb + o_over);
     G.n_over = (int32_t*)(gb + o_nover);
+    G.part = (double*)(gb + o_part);
+    G.tiles = (int64_t*)(gb + o_tiles);
     G.row_counts = cnt;
   }
   LK_HIP(lk::launch_boxes(xyz, dtype == LK_F64, off, n_loops, boxes, s));
