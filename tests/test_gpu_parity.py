@@ -240,6 +240,28 @@ def test_grid_pair_search_matches_all_pairs(ctx):
         ctx.set_option(lk_mod._lib.OPT_PAIR_SEARCH, 0)
 
 
+def test_build_pairs_more_than_first_guess(ctx):
+    """The binding's first output buffer holds 8 pairs per loop (+1,024);
+    120 nearly coincident rings give 7,140 pairs, so the search reports
+    LK_ECAPACITY with the exact count and runs again: the result is the
+    oracle's list, for both search methods."""
+    import paper_2106_12655_amd as lk_mod
+    from paper_2106_12655_amd.inputs import _pack
+    ring = I.circle(16)
+    loops = [ring * 0.5 + np.array([0.001 * k, 0.0, 0.0]) for k in range(120)]
+    ls = _pack(loops, np.float64, {}, "coincident", 0)
+    want = oracle.aabb_pairs(ls.xyz, ls.offsets)
+    assert len(want) == 120 * 119 // 2 > 8 * 120 + 1024
+    xyz, off = _dev(ls)
+    try:
+        for mode in (1, 2):
+            ctx.set_option(lk_mod._lib.OPT_PAIR_SEARCH, mode)
+            got = ctx.build_pairs(xyz, off).cpu().numpy()
+            assert np.array_equal(got, want), mode
+    finally:
+        ctx.set_option(lk_mod._lib.OPT_PAIR_SEARCH, 0)
+
+
 def _verify_reference(pairs, lk, ep, elk):
     cur = {tuple(p): v for p, v in zip(pairs.tolist(), lk.tolist())}
     exp = {tuple(p): v for p, v in zip(ep.tolist(), elk.tolist())}
