@@ -22,12 +22,26 @@ inline int blocks_for(int64_t n, int threads, int cap = 65535 * 8) {
 }
 
 // ------------------------------------------------------------- validation
-// xi partial sums over a flat grid stride (one per block), the per-loop bits
-// that do not depend on xi (fewer than 3 vertices, non-finite coordinates) and
-// each loop's shortest squared segment (one wavefront per loop).  The zero-
-// length test of Alg. 3 (segment shorter than eps * xi) is applied by the plan,
-// which reduces the partials to xi itself.  Block 0 also zeroes the main
-// pass's schedule counts.
+// Sum of one value per thread of a 256-thread workgroup (a fixed-order tree),
+// stored at part[blockIdx.x].
+__device__ __forceinline__ void block_sum_to(double v, double* red, double* part) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// One wavefront per loop: the per-loop bits that do not depend on xi (fewer
+// than 3 vertices, non-finite coordinates), each loop's shortest squared
+// segment, and one xi partial sum of |coordinate| per workgroup over the
+// vertices of its loops.  The zero-length test of Alg. 3 (segment shorter
+// than eps * xi) is applied by the plan, which reduces the partials to xi
+// itself.  When the crossing count's box kernel does the per-loop scan, this
+// kernel sums xi over a flat grid stride and only initialises the per-loop
+// entries.  Block 0 also zeroes the main pass's schedule counts.
 template <typename Tin>
 __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, int32_t L,
                                               double* part, uint32_t* lf, double* minseg2,
@@ -40,20 +54,14 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
     *zero_mismatch = 0ull;
     *zero_stop = 0;
   }
-  const int64_t v0 = off[0], v1 = off[L];
-  const int64_t n3 = 3 * (v1 - v0);
   double s = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n3; k += (int64_t)gridDim.x * 256)
-    s += fabs((double)X[3 * v0 + k]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-
   if (!scan_loops) {
+    const int64_t v0 = off[0], v1 = off[L];
+    const int64_t n3 = 3 * (v1 - v0);
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n3;
+         k += (int64_t)gridDim.x * 256)
+      s += fabs((double)X[3 * v0 + k]);
+    block_sum_to(s, red, part);
     // the crossing count's box kernel scans the vertices (in parallel over
     // blocks of long loops) and folds its results into these with atomics
     for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
@@ -62,6 +70,8 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
     }
     return;
   }
+  // one pass over the loops: each vertex adds |x| + |y| + |z| to the xi
+  // partial of the workgroup that scans its loop
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
@@ -76,6 +86,7 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
       const double x1 = (double)X[3 * (o + t)], y1 = (double)X[3 * (o + t) + 1],
                    z1 = (double)X[3 * (o + t) + 2];
       if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0)) f |= kFlagNonfinite | kFlagBadloop;
+      s += fabs(x0) + fabs(y0) + fabs(z0);
       const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
       mn = fmin(mn, dx * dx + dy * dy + dz * dz);
     }
@@ -88,6 +99,7 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
       minseg2[l] = mn;
     }
   }
+  block_sum_to(s, red, part);
 }
 
 // ------------------------------------------------- crossing-count boxes
