@@ -505,7 +505,7 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
   P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, mixed ? default_tile(true) : P.tile,
                                  ctx->n_cu, ctx->opt_waves);
   // refits are rare: a small persistent grid keeps the empty refit pass cheap
-  P.grid_refit = 2 * ctx->n_cu < P.grid64 ? 2 * ctx->n_cu : P.grid64;
+  P.grid_refit = ctx->n_cu < P.grid64 ? ctx->n_cu : P.grid64;
   P.grid_cc64 = P.crossings ? lk::direct_sum_grid(in_f64, true, kFormCrossings, P.segs64,
                                                   default_tile(true), ctx->n_cu, 0)
                             : 0;
