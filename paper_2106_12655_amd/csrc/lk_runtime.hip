@@ -1389,6 +1389,11 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     if ((st = sweep(&lk_tuning::atan_form, {0, 2})) != LK_OK) return st;
     if ((st = sweep(&lk_tuning::segs_per_lane, {1, 2, 4})) != LK_OK) return st;
   } else {
+    // FP64: at two segments per lane a batch of one small pair is slow while
+    // one segment per lane barely depends on it, so a start from batch 1
+    // (left by an FP32 tuning) would settle on one segment: sweep the batch
+    // first
+    if (n_small > 0 && (st = sweep(&lk_tuning::small_batch, {1, 2, 4, 8})) != LK_OK) return st;
     if ((st = sweep(&lk_tuning::segs_per_lane_f64, {1, 2})) != LK_OK) return st;
   }
   if (n_small > 0 && (st = sweep(&lk_tuning::small_batch, {1, 2, 4, 8, 16, 32})) != LK_OK) return st;
