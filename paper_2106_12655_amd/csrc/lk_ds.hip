@@ -33,11 +33,19 @@
 // with one cross product per step shared by the lane's R segments and a
 // per-lane constant s_r x delta_r; both pieces are built from short vectors,
 // which keeps FP32 accurate for distant pairs.  The two arctangents are merged
-// into one: (d1 + i p)(d2 + i p) has the angle atan2(p, d1) + atan2(p, d2),
-// which stays inside (-pi, pi) because the pair's parallelogram subtends less
-// than a hemisphere, so
-//   theta = atan2(p (d1 + d2), d1 d2 - p^2),  term = theta / (2 pi)
-// (the angle-addition idea of the appendix, Alg. 7, applied per term).
+// into one: (d1 + i p)(d2 + i p) has the angle atan2(p, d1) + atan2(p, d2)
+// (the angle-addition idea of the appendix, Alg. 7, applied per term).  Every
+// difference vector l(s) - k(t) of the two segments has the same component p
+// along s_j x s_r, so the pair's quadrilateral lies in one open hemisphere:
+// the angle stays inside (-pi, pi) and has the sign of p, which makes
+// d1 + d2 > 0 in exact arithmetic.  Near contact with the crossing close to
+// the diagonal a-c both d1 and d2 shrink and their FP32 sum carries no sign,
+// so the sign is taken from p (which stays accurate there) and only the
+// magnitude from the merged form:
+//   theta = atan2(p |d1 + d2|, d1 d2 - p^2),  term = theta / (2 pi)
+// The magnitude's error near contact grows like eps |s| / h (h the distance
+// of the segments); it stays below 0.5 per term and is caught by the refit
+// rule long before h reaches the resolution of the coordinates.
 #include "lk_internal.h"
 #include "atan_poly.h"
 
@@ -61,6 +69,8 @@ __device__ __forceinline__ V3<T> cross(const V3<T>& a, const V3<T>& b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
+__device__ __forceinline__ float fabs_t(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double fabs_t(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -237,7 +247,7 @@ __device__ __forceinline__ T walk_step(Walk<T, R>& w, const V3<T>& l1, const Seg
     const T f = nd * nc + (n2[r] - gr);
     const T d1 = nc * w.E[r] + vert[r + 1] * na + ca * nb;
     const T d2 = na * f + vert[r] * nc + ca * nd;
-    Y[r] = p * (d1 + d2);
+    Y[r] = p * fabs_t(d1 + d2);  // |.| is a free source modifier
     X[r] = d1 * d2 - p * p;
     w.E[r] = f;
     w.G[r] = gr;

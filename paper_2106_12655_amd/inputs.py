@@ -154,6 +154,107 @@ def torus_link(m: int, n: int, N: int = 400, dtype=np.float64) -> LoopSet:
                   np.array([[0, 1]], np.int32))
 
 
+# ---------------------------------------------- near the singularities of Eq. 4
+def _ngon(n: int, radius: float) -> np.ndarray:
+    """Regular n-gon in the xy plane with vertices at angles (2k + 1) pi / n,
+    so that its last segment (vertex n-1 -> vertex 0) is parallel to +y at
+    x = radius cos(pi / n) and crosses the x axis at its midpoint."""
+    t = np.pi * (2 * np.arange(n) + 1) / n
+    return np.stack([radius * np.cos(t), radius * np.sin(t), np.zeros(n)], axis=1)
+
+
+def near_contact(h_rel, t_a, t_b, seed: int = 0, offset: float = 0.0, n_a: int = 32,
+                 n_b: int = 24, r_b: float = 0.6, rotate: bool = True, spacing: float = 10.0,
+                 dtype=np.float64) -> LoopSet:
+    """Loop pairs that pass within a prescribed distance of each other (Sec. 4.1:
+    Eq. 4 is singular only where two segments touch).
+
+    Case k (one entry of each of ``h_rel``, ``t_a``, ``t_b``): A is a unit
+    n_a-gon in the xy plane, shifted along y so that its last segment (length
+    s_a, parallel to +y) crosses the x axis at fraction t_a of its length; B is
+    an n_b-gon of radius r_b in the xz plane, centred on the x axis and shifted
+    along z so that its last segment (parallel to +z) crosses the x axis at
+    fraction t_b, at distance h = h_rel[k] * s_a beyond A's segment.  The two
+    segments are perpendicular and their closest points are h apart; no other
+    segments come near.  B's opposite side crosses A's plane inside A, so for
+    h > 0 B passes once through A's disk (linking number -1 for these
+    orientations, as in :func:`hopf`) and for h < 0 twice in opposite
+    directions (0).  Each case gets its own seeded rotation (``rotate``), is
+    moved ``spacing`` along x from the previous one (0: all cases share one
+    centre; the pair list keeps them apart) and the whole set by ``offset``
+    along (1, 1, 1)/sqrt(3).  ``pairs`` lists (2k, 2k + 1); ``meta["h"]`` the
+    distances h before rounding to ``dtype``.
+    """
+    h_rel, t_a, t_b = (np.atleast_1d(np.asarray(v, dtype=np.float64)) for v in (h_rel, t_a, t_b))
+    h_rel, t_a, t_b = np.broadcast_arrays(h_rel, t_a, t_b)
+    rng = np.random.default_rng(seed)
+    A0 = _ngon(n_a, 1.0)
+    s_a = 2.0 * np.sin(np.pi / n_a)
+    x_a = np.cos(np.pi / n_a)
+    B0 = _ngon(n_b, r_b)[:, [0, 2, 1]]  # into the xz plane, last segment along +z
+    s_b = 2.0 * r_b * np.sin(np.pi / n_b)
+    x_b = r_b * np.cos(np.pi / n_b)
+    shift = offset * np.ones(3) / np.sqrt(3.0)
+    loops, exp, hs = [], {}, []
+    for k in range(h_rel.shape[0]):
+        h = float(h_rel[k]) * s_a
+        A = A0 + np.array([0.0, s_a * (0.5 - t_a[k]), 0.0])
+        B = B0 + np.array([x_a + h - x_b, 0.0, s_b * (0.5 - t_b[k])])
+        R = random_rotation(rng) if rotate else np.eye(3)
+        c = np.array([spacing * k, 0.0, 0.0]) + shift
+        loops += [A @ R.T + c, B @ R.T + c]
+        if h > 0:
+            exp[(2 * k, 2 * k + 1)] = -1
+        hs.append(h)
+    pairs = np.array([[2 * k, 2 * k + 1] for k in range(h_rel.shape[0])], np.int32).reshape(-1, 2)
+    return _pack(loops, dtype, exp, "near_contact", seed, pairs,
+                 meta={"h": np.array(hs), "s_a": s_a})
+
+
+def near_parallel(h_rel, alpha, seed: int = 0, offset: float = 0.0, per_edge: int = 8,
+                  rotate: bool = True, spacing: float = 10.0, dtype=np.float64) -> LoopSet:
+    """Linked square loops with a pair of long, nearly parallel sides close
+    together (the other end of Sec. 4.1's conditioning: segment pairs whose
+    s_j x s_i nearly vanishes next to a near contact).
+
+    Case k, with h = h_rel[k] (in units of the side): A is the unit square
+    [0, 1]^2 in the xy plane; B is a 1 x 1 square in the plane y = h, spanning
+    x in [-0.5, 0.5] and z in [-1 + h, h], turned by alpha[k] radians about
+    the z axis through (0, h, h) (alpha[k] > -2 h keeps B's side x = 0.5 above
+    y = 0).  B's top side then runs over A's side y = 0
+    at distance about h sqrt(2), nearly parallel to it over half its length,
+    and B's side x = 0.5 crosses A's plane inside A at distance about h from
+    that side.  B's side x = -0.5 crosses A's plane outside A, so the pair
+    links once (-1 for these orientations).  Each side has ``per_edge``
+    segments.  Rotation, spacing and ``offset`` as in :func:`near_contact`.
+    """
+    h_rel, alpha = (np.atleast_1d(np.asarray(v, dtype=np.float64)) for v in (h_rel, alpha))
+    h_rel, alpha = np.broadcast_arrays(h_rel, alpha)
+    rng = np.random.default_rng(seed)
+    u = np.arange(per_edge) / per_edge
+
+    def square(p0, e1, e2):
+        pts = [p0 + np.outer(u, e1), p0 + e1 + np.outer(u, e2), p0 + e1 + e2 - np.outer(u, e1),
+               p0 + e2 - np.outer(u, e2)]
+        return np.concatenate(pts, axis=0)
+
+    ex, ey, ez = np.eye(3)
+    A0 = square(np.zeros(3), ex, ey)
+    shift = offset * np.ones(3) / np.sqrt(3.0)
+    loops, exp = [], {}
+    for k in range(h_rel.shape[0]):
+        h = float(h_rel[k])
+        piv = np.array([0.0, h, h])
+        B = square(np.array([-0.5, h, h]), ex, -ez)
+        B = (B - piv) @ rot_z(float(alpha[k])).T + piv
+        R = random_rotation(rng) if rotate else np.eye(3)
+        c = np.array([spacing * k, 0.0, 0.0]) + shift
+        loops += [A0 @ R.T + c, B @ R.T + c]
+        exp[(2 * k, 2 * k + 1)] = -1
+    pairs = np.array([[2 * k, 2 * k + 1] for k in range(h_rel.shape[0])], np.int32).reshape(-1, 2)
+    return _pack(loops, dtype, exp, "near_parallel", seed, pairs, meta={"h": h_rel.copy()})
+
+
 # ------------------------------------------------------------- ring grid (C1)
 def ring_grid(seed: int = 0, rows: int = 8, cols: int = 8, nseg: int = 32, spacing: float = 1.6,
               jitter: float = 0.02, dtype=np.float64) -> LoopSet:

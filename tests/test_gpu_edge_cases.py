@@ -1,0 +1,156 @@
+"""Parity with the FP64 oracle where Eq. 4 is badly conditioned (Sec. 4.1).
+
+Eq. 4 is singular only when two segments touch (or overlap collinearly, or one
+has zero length); these tests bring segments close to that:
+
+* perpendicular near contacts at h / |s| from 1e-2 down to 1e-6, with the
+  crossing at equal or nearly equal fractions of both segments (the diagonal
+  of the pair's quadrilateral, where the two halves of the merged arctangent
+  both vanish), from both sides;
+* long sides that run nearly parallel at distance about h next to such a
+  contact;
+* the same sets moved 1e3 from the origin, so that FP32 coordinates keep only
+  about 6e-5 of absolute resolution.
+
+Every set runs in both modes from FP32 and from FP64 input.  Rounding the
+input moves each contact by up to a few units in the last place of its
+coordinates, so a pair's closest distance d is measured on the rounded input;
+pairs with d below four units in the last place of their largest coordinate
+are at the resolution limit of the input (they may even touch) and are only
+reported.  The bar for every other pair: the integer equals the oracle's;
+plain-FP64 reals lie within 1e-6 of it; in the mixed mode a pair whose FP32
+value strayed more than 0.05 from an integer carries REFIT and then also lies
+within 1e-6, and every other pair lies within 0.05 (the FP32 term error near
+contact grows like eps |s| / d).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12655_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+PLAIN_TOL = 1e-6
+FLAG_REFIT = 1
+FLAG_BAD = 4 | 8  # NONFINITE | BADPAIR
+
+H_REL = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+T_A = [0.3, 0.5, 0.7]
+DT = [0.0, 1e-5, 1e-3]
+
+
+def _contact_set(offset, dtype):
+    h, ta, tb = [], [], []
+    for hr in H_REL:
+        for sgn in (1.0, -1.0):
+            for a in T_A:
+                for d in DT:
+                    h.append(sgn * hr)
+                    ta.append(a)
+                    tb.append(a + d)
+    return I.near_contact(h, ta, tb, seed=21, offset=offset, spacing=0.0, dtype=dtype)
+
+
+def _parallel_set(offset, dtype):
+    h, al = [], []
+    for hr in H_REL:
+        for a in (0.0, 1e-3 * hr, hr, 1e-3):
+            h.append(hr)
+            al.append(a)
+    return I.near_parallel(h, al, seed=22, offset=offset, spacing=0.0, dtype=dtype)
+
+
+def _segment_distance(A, B):
+    """Smallest distance between the segments of closed polylines A and B
+    (FP64, all pairs, clamped closest points)."""
+    P0, P1 = A, np.roll(A, -1, 0)
+    Q0, Q1 = B, np.roll(B, -1, 0)
+    d1 = (P1 - P0)[:, None, :]
+    d2 = (Q1 - Q0)[None, :, :]
+    r = P0[:, None, :] - Q0[None, :, :]
+    a = (d1 * d1).sum(-1)
+    e = (d2 * d2).sum(-1)
+    b = (d1 * d2).sum(-1)
+    c = (d1 * r).sum(-1)
+    f = (d2 * r).sum(-1)
+    den = a * e - b * b
+    s = np.clip(np.divide(b * f - c * e, den, out=np.zeros_like(den), where=den > 0), 0, 1)
+    t = np.clip((b * s + f) / e, 0, 1)
+    s = np.clip((b * t - c) / a, 0, 1)
+    t = np.clip((b * s + f) / e, 0, 1)
+    v = r + d1 * s[..., None] - d2 * t[..., None]
+    return float(np.sqrt((v * v).sum(-1)).min())
+
+
+def _resolved(ls):
+    """Pairs whose rounded geometry keeps the two loops more than four units
+    in the last place of their coordinates apart."""
+    eps = np.finfo(ls.xyz.dtype).eps
+    out = []
+    for i, j in ls.pairs:
+        A, B = ls.loop(i).astype(np.float64), ls.loop(j).astype(np.float64)
+        scale = max(np.abs(A).max(), np.abs(B).max())
+        out.append(_segment_distance(A, B) > 4 * eps * scale)
+    return np.array(out)
+
+
+def _run(ctx, ls, mode):
+    import torch
+    xyz = torch.from_numpy(np.ascontiguousarray(ls.xyz)).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    pr = torch.from_numpy(ls.pairs).cuda()
+    real, lk, flags = ctx.direct_sum(xyz, off, pr, mode)
+    torch.cuda.synchronize()
+    return real.cpu().numpy(), lk.cpu().numpy(), flags.cpu().numpy().view(np.uint32)
+
+
+def _check(ctx, ls, label):
+    oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, ls.pairs)
+    ok = _resolved(ls)
+    h = np.abs(np.asarray(ls.meta["h"]))
+    print("%s: %d pairs, %d at the resolution limit" % (label, len(ok), int((~ok).sum())), flush=True)
+    for mode in ("plain", "mixed"):
+        real, lk, flags = _run(ctx, ls, mode)
+        err = np.abs(real - oreal)
+        refit = (flags & FLAG_REFIT) != 0
+        for hr in sorted(set(h.tolist()), reverse=True):
+            sel = (h == hr) & ok
+            if np.any(sel):
+                print("  %s h %.0e: max |err| %.3e refits %d/%d" % (
+                    mode, hr, err[sel].max(), int(refit[sel].sum()), int(sel.sum())), flush=True)
+        lim = np.nonzero(~ok)[0]
+        if lim.size:
+            print("  %s at the limit: integers equal %d/%d" % (
+                mode, int(np.sum(lk[lim] == olk[lim])), lim.size), flush=True)
+        assert np.all((flags[ok] & FLAG_BAD) == 0), label
+        bad = np.nonzero((lk != olk) & ok)[0]
+        assert bad.size == 0, (label, mode, bad[:8].tolist(), real[bad[:8]].tolist(),
+                               oreal[bad[:8]].tolist())
+        if mode == "plain":
+            assert err[ok].max() <= PLAIN_TOL, (label, mode)
+        else:
+            assert np.all(err[ok & refit] <= PLAIN_TOL), (label, mode)
+            assert np.all(err[ok & ~refit] <= 0.05), (label, mode)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("offset", [0.0, 1e3], ids=["origin", "far"])
+def test_near_contact(ctx, dtype, offset):
+    ls = _contact_set(offset, dtype)
+    if dtype == np.float64:
+        # the construction's values hold where rounding cannot move a contact
+        # across its partner
+        assert np.array_equal(oracle.direct_sum(ls.xyz, ls.offsets, ls.pairs)[1],
+                              ls.expected_for(ls.pairs))
+    _check(ctx, ls, "near_contact %s %s" % (np.dtype(dtype).name, "far" if offset else "origin"))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("offset", [0.0, 1e3], ids=["origin", "far"])
+def test_near_parallel(ctx, dtype, offset):
+    ls = _parallel_set(offset, dtype)
+    if dtype == np.float64:
+        assert np.array_equal(oracle.direct_sum(ls.xyz, ls.offsets, ls.pairs)[1],
+                              ls.expected_for(ls.pairs))
+    _check(ctx, ls, "near_parallel %s %s" % (np.dtype(dtype).name, "far" if offset else "origin"))

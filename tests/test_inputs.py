@@ -136,3 +136,24 @@ def test_winding_pair_full_length_coarse():
     xyz = np.vstack([C, D])
     real, lk = oracle.direct_sum(xyz, [0, len(C), len(C) + len(D)], [[0, 1]])
     assert lk[0] == v == -4 and abs(real[0] - v) < 1e-8
+
+
+def test_near_contact_construction():
+    # perpendicular segments h apart: -1 when B passes outside A's segment, 0
+    # when it passes inside (both of its crossings of A's plane are in A)
+    h = [1e-1, 1e-2, -1e-2, 1e-4, -1e-4]
+    ls = I.near_contact(h, 0.4, 0.6, seed=3)
+    _check_against_oracle(ls, ls.pairs)
+    assert ls.expected_for(ls.pairs).tolist() == [-1, -1, 0, -1, 0]
+    # the closest points of the two last segments are h apart
+    for k, hk in enumerate(ls.meta["h"]):
+        A, B = ls.loop(2 * k), ls.loop(2 * k + 1)
+        sa, sb = A[0] - A[-1], B[0] - B[-1]
+        n = np.cross(sa, sb)
+        assert abs(abs((B[-1] - A[-1]) @ n) / np.linalg.norm(n) - abs(hk)) < 1e-12
+
+
+def test_near_parallel_construction():
+    ls = I.near_parallel([1e-1, 1e-2, 1e-4, 1e-4], [0.0, 1e-3, 0.0, 1e-4], seed=4)
+    _check_against_oracle(ls, ls.pairs)
+    assert np.all(ls.expected_for(ls.pairs) == -1)
