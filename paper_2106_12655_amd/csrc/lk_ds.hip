@@ -174,6 +174,33 @@ __device__ __forceinline__ V3<Tc> load_vertex(const Tin* X, int64_t v) {
   return {(Tc)X[3 * v], (Tc)X[3 * v + 1], (Tc)X[3 * v + 2]};
 }
 
+// Vertex loads of one work item.  An FP32 pass over FP64 input takes every
+// coordinate relative to an origin inside the item (a vertex of its loop-B
+// block), subtracted in FP64 before the rounding to FP32: the FP32 values
+// then carry relative precision against the item's own extent, not against
+// the distance from the coordinate origin (2^-24 of 1e3 is 6e-5, enough to
+// move a near contact across its partner).  The terms only use differences
+// of vertices, which the shift leaves unchanged in exact arithmetic.  FP32
+// input, and FP64 passes, load the values as stored.
+template <typename Tin, typename Tc>
+struct Frame {
+  static constexpr bool kShift = sizeof(Tin) > sizeof(Tc);
+  Tin ox = 0, oy = 0, oz = 0;
+  __device__ __forceinline__ void set(const Tin* X, int64_t v) {
+    if constexpr (kShift) {
+      ox = X[3 * v];
+      oy = X[3 * v + 1];
+      oz = X[3 * v + 2];
+    }
+  }
+  __device__ __forceinline__ V3<Tc> load(const Tin* X, int64_t v) const {
+    if constexpr (kShift)
+      return {(Tc)(X[3 * v] - ox), (Tc)(X[3 * v + 1] - oy), (Tc)(X[3 * v + 2] - oz)};
+    else
+      return load_vertex<Tc>(X, v);
+  }
+};
+
 // The R consecutive segments of loop B owned by a lane: vertices k_0..k_R,
 // segment vectors s_r = k_{r+1} - k_r and the constants s_r x (k_r - k_0) of
 // the numerator p.  Segments past the end of the item are evaluated on
@@ -324,14 +351,14 @@ __device__ __forceinline__ Layout layout(const WorkRec& r, int64_t local, int ch
 // repeat the last vertex and are masked by Segs::valid).
 template <typename Tin, typename Tc, int R>
 __device__ __forceinline__ void load_b(const Tin* X, const WorkRec& w, const Layout& L,
-                                       V3<Tc>* k) {
+                                       const Frame<Tin, Tc>& F, V3<Tc>* k) {
   const int first = L.bi * R;
 #pragma unroll
   for (int r = 0; r <= R; ++r) {
     int64_t i = L.b0 + first + r;
     if (i >= w.nb) i -= w.nb;
     if (i >= w.nb) i = w.nb - 1;
-    k[r] = load_vertex<Tc>(X, w.ob + i);
+    k[r] = F.load(X, w.ob + i);
   }
 }
 
@@ -536,7 +563,8 @@ __device__ __forceinline__ void walk_tile(const Vtx<Tc>* lds, int t0, int jlo, i
 // is staged (65 vertices) and walked from a fresh start.  The box tests are
 // uniform over the wave.
 template <typename Tin, typename Tc, int R>
-__device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X, Vtx<Tc>* lds,
+__device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X,
+                                               const Frame<Tin, Tc>& F, Vtx<Tc>* lds,
                                                const WorkRec& r, const Layout& L, int lane,
                                                CcWalk<Tc, R>& wk, const CcSegs<Tc, R>& sg,
                                                double& acc) {
@@ -571,7 +599,7 @@ __device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X, Vt
       __syncthreads();
       for (int t = lane; t <= kCcBlock; t += kWave) {
         const int idx = (v0 + t) % r.na;  // the block's vertices, cyclic
-        const V3<Tc> x = load_vertex<Tc>(X, r.oa + idx);
+        const V3<Tc> x = F.load(X, r.oa + idx);
         lds[t] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
       }
       __syncthreads();
@@ -680,8 +708,10 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
       const WorkRec r = A.s.big[lo];
       const uint32_t fpre = r.items == 1 ? A.out.flags[r.p] : 0u;
       const Layout L = layout<R>(r, w - A.s.big_prefix[lo], A.chunk, lane);
+      Frame<Tin, Tc> F;
+      F.set(X, r.ob + L.b0);
       V3<Tc> kv[R + 1];
-      load_b<Tin, Tc, R>(X, r, L, kv);
+      load_b<Tin, Tc, R>(X, r, L, F, kv);
       typename LaneOf<Tc, AT, R>::S sg;
       make_lane<Tc, R>(kv, L, A, sg);
       typename LaneOf<Tc, AT, R>::W wk;
@@ -689,7 +719,7 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
       bool culled = false;
       if constexpr (AT == kCrossings) {
         if (A.cc_blk) {
-          cc_item_culled<Tin, Tc, R>(A, X, lds, r, L, lane, wk, sg, acc);
+          cc_item_culled<Tin, Tc, R>(A, X, F, lds, r, L, lane, wk, sg, acc);
           culled = true;
         }
       }
@@ -700,7 +730,7 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
         for (int v = lane; v <= tl; v += kWave) {
           int64_t idx = L.a0 + t0 + v;
           if (idx >= r.na) idx -= r.na;  // closing vertex of the loop
-          const V3<Tc> x = load_vertex<Tc>(X, r.oa + idx);
+          const V3<Tc> x = F.load(X, r.oa + idx);
           lds[v] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
         }
         __syncthreads();
@@ -736,15 +766,17 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
           for (int t = has ? r0 + seg : r0; t > 0; --t) mm &= mm - 1ull;
           const WorkRec cur = recs[__ffsll((long long)mm) - 1];
           const uint32_t fm = A.out.flags[cur.p];
+          Frame<Tin, Tc> F;
+          F.set(X, cur.ob);
           __syncthreads();
           if (has)
             for (int v = sl; v <= cur.na; v += S) {
-              const V3<Tc> x = load_vertex<Tc>(X, cur.oa + (v < cur.na ? v : 0));
+              const V3<Tc> x = F.load(X, cur.oa + (v < cur.na ? v : 0));
               myl[v] = Vtx<Tc>{x.x, x.y, x.z, (Tc)0};
             }
           const Layout L = layout<R>(cur, 0, A.chunk, sl, S);
           V3<Tc> kv[R + 1];
-          load_b<Tin, Tc, R>(X, cur, L, kv);
+          load_b<Tin, Tc, R>(X, cur, L, F, kv);
           typename LaneOf<Tc, AT, R>::S sg;
           make_lane<Tc, R>(kv, L, A, sg);
           __syncthreads();
@@ -765,10 +797,12 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
         const WorkRec cur = recs[m];
         const uint32_t fm = A.out.flags[cur.p];
         const Layout L = layout<R>(cur, 0, A.chunk, lane);
+        Frame<Tin, Tc> F;
+        F.set(X, cur.ob);
         V3<Tc> kv[R + 1];
-        load_b<Tin, Tc, R>(X, cur, L, kv);
-        const V3<Tc> a_lo = load_vertex<Tc>(X, cur.oa + (lane < cur.na ? lane : 0));
-        const V3<Tc> a_hi = load_vertex<Tc>(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
+        load_b<Tin, Tc, R>(X, cur, L, F, kv);
+        const V3<Tc> a_lo = F.load(X, cur.oa + (lane < cur.na ? lane : 0));
+        const V3<Tc> a_hi = F.load(X, cur.oa + (lane + kWave < cur.na ? lane + kWave : 0));
         __syncthreads();
         if (lane <= cur.na) lds[lane] = Vtx<Tc>{a_lo.x, a_lo.y, a_lo.z, (Tc)0};
         if (lane + kWave <= cur.na) lds[lane + kWave] = Vtx<Tc>{a_hi.x, a_hi.y, a_hi.z, (Tc)0};
@@ -815,11 +849,13 @@ __global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
       const int64_t a0 = (int64_t)w.ka * kBhLeaf, b0 = (int64_t)w.kb * kBhLeaf;
       const int ma = (int)((na - a0) < kBhLeaf ? (na - a0) : kBhLeaf);
       const int mb = (int)((nb - b0) < kBhLeaf ? (nb - b0) : kBhLeaf);
+      Frame<Tin, float> F;
+      F.set(X, ob + b0);
       __syncthreads();
       for (int t = sl; t <= ma; t += S) {
         int64_t idx = a0 + t;
         if (idx >= na) idx -= na;  // closing vertex of the loop
-        const V3<float> x = load_vertex<float>(X, oa + idx);
+        const V3<float> x = F.load(X, oa + idx);
         lds[seg][t] = Vtx<float>{x.x, x.y, x.z, 0.0f};
       }
       Segs<float, R> sg;
@@ -830,7 +866,7 @@ __global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
         for (int r = 0; r <= R; ++r) {
           int64_t ib = b0 + (first + r < mb ? first + r : mb);  // vertex b0 + mb closes the leaf
           if (ib >= nb) ib -= nb;
-          kv[r] = load_vertex<float>(X, ob + ib);
+          kv[r] = F.load(X, ob + ib);
         }
 #pragma unroll
         for (int r = 0; r <= R; ++r) sg.k[r] = kv[r];

@@ -17,7 +17,10 @@ input moves each contact by up to a few units in the last place of its
 coordinates, so a pair's closest distance d is measured on the rounded input;
 pairs with d below four units in the last place of their largest coordinate
 are at the resolution limit of the input (they may even touch) and are only
-reported.  The bar for every other pair: the integer equals the oracle's;
+reported.  The mixed mode's FP32 terms see FP64 input rounded to FP32
+relative to a vertex of the work item (the kernel subtracts it in FP64 first),
+so there the limit is also at least four FP32 units of the pair's extent.
+The bar for every other pair: the integer equals the oracle's;
 plain-FP64 reals lie within 1e-6 of it; in the mixed mode a pair whose FP32
 value strayed more than 0.05 from an integer carries REFIT and then also lies
 within 1e-6, and every other pair lies within 0.05 (the FP32 term error near
@@ -83,15 +86,20 @@ def _segment_distance(A, B):
     return float(np.sqrt((v * v).sum(-1)).min())
 
 
-def _resolved(ls):
+def _resolved(ls, mode):
     """Pairs whose rounded geometry keeps the two loops more than four units
-    in the last place of their coordinates apart."""
+    in the last place of their coordinates apart (in the mixed mode, also
+    more than four FP32 units of the pair's extent)."""
     eps = np.finfo(ls.xyz.dtype).eps
+    eps32 = float(np.finfo(np.float32).eps)
     out = []
     for i, j in ls.pairs:
         A, B = ls.loop(i).astype(np.float64), ls.loop(j).astype(np.float64)
-        scale = max(np.abs(A).max(), np.abs(B).max())
-        out.append(_segment_distance(A, B) > 4 * eps * scale)
+        lim = 4 * eps * max(np.abs(A).max(), np.abs(B).max())
+        if mode == "mixed":
+            AB = np.concatenate([A, B])
+            lim = max(lim, 4 * eps32 * float((AB.max(0) - AB.min(0)).max()))
+        out.append(_segment_distance(A, B) > lim)
     return np.array(out)
 
 
@@ -107,10 +115,11 @@ def _run(ctx, ls, mode):
 
 def _check(ctx, ls, label):
     oreal, olk = oracle.direct_sum(ls.xyz, ls.offsets, ls.pairs)
-    ok = _resolved(ls)
     h = np.abs(np.asarray(ls.meta["h"]))
-    print("%s: %d pairs, %d at the resolution limit" % (label, len(ok), int((~ok).sum())), flush=True)
     for mode in ("plain", "mixed"):
+        ok = _resolved(ls, mode)
+        print("%s %s: %d pairs, %d at the resolution limit" % (
+            label, mode, len(ok), int((~ok).sum())), flush=True)
         real, lk, flags = _run(ctx, ls, mode)
         err = np.abs(real - oreal)
         refit = (flags & FLAG_REFIT) != 0
