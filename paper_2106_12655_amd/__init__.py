@@ -170,11 +170,15 @@ class Context:
         """Eq. 4 summed over every segment pair of every loop pair.
 
         Returns ``(lk_real float64[P], lk_int int32[P], flags int32[P])`` on the
-        device (flags hold the LK_FLAG_* bits).  ``mode`` is ``"mixed"`` (FP32
-        terms, FP64 pair sums and FP64 refit of ambiguous pairs), ``"plain"``
-        (FP64 throughout) or ``"crossings"`` (certified crossing count of a
-        projection, Alg. 4, with the FP64 direct sum for undecided pairs).
-        ``out``: optional preallocated output triple.
+        device.  ``flags`` holds the C call's uint32 LK_FLAG_* words in an
+        int32 tensor (torch has few uint32 operations); every defined bit is
+        below 2^31, so the values read the same.  ``mode`` is ``"mixed"``
+        (FP32 terms, FP64 pair sums and FP64 refit of ambiguous pairs),
+        ``"plain"`` (FP64 throughout), ``"crossings"`` (certified crossing
+        count of a projection, Alg. 4, with the FP64 direct sum for undecided
+        pairs) or ``"barnes_hut"`` (the two-tree method of Alg. 6, with the
+        FP64 refit of pairs far from an integer).  ``out``: optional
+        preallocated output triple.
         """
         torch = _torch()
         self._dev(xyz, None, "xyz")
