@@ -176,6 +176,33 @@ lk_status lk_direct_sum_check(lk_ctx* ctx, const void* xyz, int dtype,
                               double* lk_real, int32_t* lk_int, uint32_t* flags,
                               int64_t* n_mismatch /* device */, void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation and kernels as lk_direct_sum in the PLAIN_F64 and MIXED modes
+ * (bitwise equal results for the same context options), with the call's
+ * workspace in one static device array of the library (about 17.6 MiB, held
+ * by each device the library runs on until the process ends) instead of the
+ * context's buffers.  The call allocates nothing: no hipMalloc, hipFree or
+ * graph instantiation; the kernels are launched eagerly on `stream` (which a
+ * caller may be capturing).  The device's address of the array is looked up
+ * once per device when a context is created on it.
+ *   - Limits: n_loops <= 65536 and n_pairs <= 131072; larger calls return
+ *     LK_ECAPACITY and enqueue nothing.  Other modes return LK_EINVAL.
+ *   - flags may be NULL (the flags then live in the static array).
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents (each call initialises what it reads): calls that
+ *     overlap on one device -- on different streams, from any context or
+ *     thread -- race and give undefined results.  Serialise them (one stream,
+ *     or events).
+ *   - lk_get_stats afterwards reports the configuration used but no refit
+ *     count.
+ * Arguments, layout, ownership and errors are otherwise those of
+ * lk_direct_sum. */
+lk_status lk_direct_sum_noalloc(lk_ctx* ctx, const void* xyz, int dtype,
+                                const int64_t* loop_offsets, int32_t n_loops,
+                                const int32_t* pairs, int64_t n_pairs, int mode, double* lk_real,
+                                int32_t* lk_int, uint32_t* flags, void* stream);
+
 /* --------------------------------------------------------------- verify */
 /* Compare the current sparse linking matrix (pairs, lk)[n] with the expected
  * one (exp_pairs, exp_lk)[n_exp]; both pair lists sorted lexicographically

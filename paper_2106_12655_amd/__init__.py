@@ -199,6 +199,29 @@ class Context:
                                            _ptr(lk), _ptr(flags), _stream(self.device)))
         return real, lk, flags
 
+    def direct_sum_noalloc(self, xyz, offsets, pairs, mode: str = "mixed", out=None):
+        """lk_direct_sum_noalloc: as :meth:`direct_sum` in the ``"mixed"`` and
+        ``"plain"`` modes, with the workspace in the library's static device
+        array (at most 65,536 loops and 131,072 pairs; calls on one device must
+        not overlap).  Pass ``out`` to keep this binding from allocating the
+        outputs; ``out[2]`` (flags) may be None."""
+        torch = _torch()
+        self._dev(xyz, None, "xyz")
+        self._dev(offsets, torch.int64, "offsets")
+        self._dev(pairs, torch.int32, "pairs")
+        P = pairs.shape[0] if pairs.dim() == 2 else 0
+        if pairs.numel() and (pairs.dim() != 2 or pairs.shape[1] != 2):
+            raise ValueError("pairs must be [P, 2]")
+        if out is None:
+            out = (torch.empty(P, dtype=torch.float64, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device),
+                   torch.empty(P, dtype=torch.int32, device=xyz.device))
+        real, lk, flags = out
+        self._check(self.lib.lk_direct_sum_noalloc(
+            self.h, _ptr(xyz), _dtype_code(xyz), _ptr(offsets), offsets.numel() - 1, _ptr(pairs), P,
+            _lib.MODES[mode], _ptr(real), _ptr(lk), _ptr(flags), _stream(self.device)))
+        return real, lk, flags
+
     def direct_sum_check(self, xyz, offsets, pairs, expected, early_exit: bool = False,
                          mode: str = "mixed", out=None):
         """Eq. 4 summed per pair with the fused certificate check

@@ -33,8 +33,9 @@ DZ_BSPLINE, DZ_POLYLINE = 0, 1
 DZ_KINDS = {"bspline": DZ_BSPLINE, "polyline": DZ_POLYLINE}
 
 EXPORTS = ["lk_create", "lk_destroy", "lk_last_error", "lk_build_pairs", "lk_direct_sum",
-           "lk_direct_sum_check", "lk_verify", "lk_set_option", "lk_set_view_direction",
-           "lk_get_view_direction", "lk_get_stats", "lk_autotune", "lk_reserve", "lk_discretize",
+           "lk_direct_sum_check", "lk_direct_sum_noalloc", "lk_verify", "lk_set_option",
+           "lk_set_view_direction", "lk_get_view_direction", "lk_get_stats", "lk_autotune",
+           "lk_reserve", "lk_discretize",
            "lk_server_create", "lk_server_destroy", "lk_server_last_error",
            "lk_server_open_session", "lk_server_close_session", "lk_server_submit",
            "lk_server_wait"]
@@ -113,6 +114,9 @@ def load():
         lib.lk_direct_sum_check.argtypes = [p, p, ctypes.c_int, p, i32, p, i64, p, ctypes.c_int,
                                              ctypes.c_int, p, p, p, p, p]
         lib.lk_direct_sum_check.restype = st
+        lib.lk_direct_sum_noalloc.argtypes = [p, p, ctypes.c_int, p, i32, p, i64, ctypes.c_int, p,
+                                              p, p, p]
+        lib.lk_direct_sum_noalloc.restype = st
         lib.lk_verify.argtypes = [p, p, p, i64, p, p, i64, ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int64), p, i64, p]
         lib.lk_verify.restype = st

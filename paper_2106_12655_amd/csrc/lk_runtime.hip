@@ -200,20 +200,51 @@ T* meta_at(lk_ctx* ctx, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ctx->meta.p) + off);
 }
 
+// Device workspace of one direct-sum call in the PLAIN_F64 and MIXED modes:
+// the context's buffers, or a carve of the no-allocation entry point's static
+// array.  (CROSSINGS and BARNES_HUT also use the context's boxes and trees.)
+struct Ws {
+  uint32_t* loop_flags;     // [L]
+  double* minseg2;          // [L]
+  double* xi;               // [kPrepMaxBlocks + 1]
+  lk::WorkRec* recs;        // [3 P]
+  int64_t* big_prefix;      // [P + 1]
+  char* meta;               // [kMetaBytes]
+  unsigned long long* acc;  // [2 P]
+  int32_t* refit_list;      // [2 P]
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(meta + off);
+  }
+};
+
+Ws ctx_ws(lk_ctx* ctx) {
+  Ws w;
+  w.loop_flags = (uint32_t*)ctx->loop_flags.p;
+  w.minseg2 = (double*)ctx->minseg2.p;
+  w.xi = (double*)ctx->xi.p;
+  w.recs = (lk::WorkRec*)ctx->recs.p;
+  w.big_prefix = (int64_t*)ctx->big_prefix.p;
+  w.meta = (char*)ctx->meta.p;
+  w.acc = (unsigned long long*)ctx->acc.p;
+  w.refit_list = (int32_t*)ctx->refit_list.p;
+  return w;
+}
+
 // pass: 0 main, 1 refit, 2 second refit (CROSSINGS)
-lk::Sched make_sched(lk_ctx* ctx, int64_t n_pairs, int pass) {
+lk::Sched make_sched(const Ws& W, int64_t n_pairs, int pass) {
   lk::Sched S;
-  lk::WorkRec* recs = (lk::WorkRec*)ctx->recs.p;
+  lk::WorkRec* recs = W.recs;
   S.small = recs;
   S.big_in = recs + n_pairs;
   S.big = recs + 2 * n_pairs;
-  S.big_prefix = (int64_t*)ctx->big_prefix.p;
+  S.big_prefix = W.big_prefix;
   const size_t counts[3] = {kMetaCountsMain, kMetaCountsRefit, kMetaCountsRefit2};
   const size_t totals[3] = {kMetaBigTotalMain, kMetaBigTotalRefit, kMetaBigTotalRefit2};
   const size_t counters[3] = {kMetaCounterMain, kMetaCounterRefit, kMetaCounterRefit2};
-  S.counts = meta_at<int32_t>(ctx, counts[pass]);
-  S.big_total = meta_at<int64_t>(ctx, totals[pass]);
-  S.counter = meta_at<unsigned long long>(ctx, counters[pass]);
+  S.counts = W.at<int32_t>(counts[pass]);
+  S.big_total = W.at<int64_t>(totals[pass]);
+  S.counter = W.at<unsigned long long>(counters[pass]);
   return S;
 }
 
@@ -275,21 +306,22 @@ BhLayout bh_layout(int64_t v, int32_t n_loops, int64_t n_pairs) {
 }
 
 // Enqueue the whole direct-sum sequence (no graph logic here).
-lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const int64_t* off,
-                             int32_t n_loops, const int32_t* pairs, int64_t n_pairs,
-                             double* lk_real, int32_t* lk_int, uint32_t* flags, hipStream_t s,
-                             hipEvent_t* ev /* 4 events or NULL */, const Check& ck = Check()) {
+lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void* xyz,
+                             const int64_t* off, int32_t n_loops, const int32_t* pairs,
+                             int64_t n_pairs, double* lk_real, int32_t* lk_int, uint32_t* flags,
+                             hipStream_t s, hipEvent_t* ev /* 4 events or NULL */,
+                             const Check& ck = Check()) {
   const bool timed = ev != nullptr;
   using namespace lk;
-  uint32_t* lf = (uint32_t*)ctx->loop_flags.p;
-  double* xi = (double*)ctx->xi.p;  // [kPrepMaxBlocks] partial sums of |coordinate|
-  int32_t* rlist = (int32_t*)ctx->refit_list.p;
-  int32_t* rn = meta_at<int32_t>(ctx, kMetaRefitN);
-  unsigned long long* acc = (unsigned long long*)ctx->acc.p;
+  uint32_t* lf = W.loop_flags;
+  double* xi = W.xi;  // [kPrepMaxBlocks] partial sums of |coordinate|
+  int32_t* rlist = W.refit_list;
+  int32_t* rn = W.at<int32_t>(kMetaRefitN);
+  unsigned long long* acc = W.acc;
 
   LoopInfo li;
   li.lf = lf;
-  li.minseg2 = (const double*)ctx->minseg2.p;
+  li.minseg2 = W.minseg2;
   li.part = xi;
   // the vertex count is known (and the boxes sized for it) only in CROSSINGS
   const bool cull = P.crossings && ctx->cc_cull;
@@ -309,7 +341,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   out.refit_pass = 0;
   out.expected = ck.expected;
   out.n_mismatch = ck.expected ? (unsigned long long*)ck.n_mismatch : nullptr;
-  out.stop = ck.expected ? meta_at<int32_t>(ctx, kMetaStop) : nullptr;
+  out.stop = ck.expected ? W.at<int32_t>(kMetaStop) : nullptr;
   out.early_exit = ck.expected ? ck.early_exit : 0;
 
   PlanArgs M{};
@@ -326,7 +358,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
   M.out = out;
   DsArgs A{};
   A.xyz = xyz;
-  A.s = make_sched(ctx, n_pairs, 0);
+  A.s = make_sched(W, n_pairs, 0);
   A.acc = acc;
   A.tile = P.tile;
   A.chunk = P.chunk;
@@ -348,12 +380,12 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
 
   // the crossing count's box kernel and the Barnes-Hut leaf kernel validate
   // the loops in parallel; the preparation kernel then only initialises
-  LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, (double*)ctx->minseg2.p, A.s.counts,
+  LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, W.minseg2, A.s.counts,
                      out.n_mismatch, out.stop, !cull && !P.bh, li.n_part, s));
   if (cull)
     LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
                            (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
-                           lf, (double*)ctx->minseg2.p, s));
+                           lf, W.minseg2, s));
   if (P.bh) {
     // Barnes-Hut: the plan validates, flags and zeroes (every pair one item);
     // the trees, the breadth-first traversal and the leaf pairs replace the
@@ -389,7 +421,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     H.counts = (int32_t*)ctx->bh_counts.p;
     H.acc = acc;
     H.lf = lf;
-    H.minseg2 = (double*)ctx->minseg2.p;
+    H.minseg2 = W.minseg2;
     H.beta = ctx->bh_beta;
     H.order = ctx->bh_order;
     H.out = out;
@@ -400,7 +432,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     LK_HIP(launch_bh_leaves(H, P.in_f64, s));
     for (int h = 1; h < Y.levels; ++h) LK_HIP(launch_bh_level(H, h, s));
     LK_HIP(launch_plan(Mb, n_loops, li, A.s, false, s));
-    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
+    LK_HIP(launch_sched(A.s, W.at<int32_t>(kMetaCountsRefit), s));
     LK_HIP(launch_bh_roots(H, n_pairs, s));
     for (int it = 0; it < 2 * (Y.levels - 1) + 1; ++it) LK_HIP(launch_bh_expand(H, it, s));
     LK_HIP(launch_bh_near(H, P.in_f64, s));
@@ -418,7 +450,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     LK_HIP(launch_bh_finalize(H, n_pairs, s));
   } else {
     LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
-    LK_HIP(launch_sched(A.s, meta_at<int32_t>(ctx, kMetaCountsRefit), s));
+    LK_HIP(launch_sched(A.s, W.at<int32_t>(kMetaCountsRefit), s));
     if (timed) LK_HIP(hipEventRecord(ev[0], s));
     LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
                              P.mixed ? P.grid : P.grid64, s));
@@ -429,7 +461,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     // refit: the FP64 direct sum (MIXED), or the FP64 crossing count
     // (CROSSINGS), which queues what it cannot decide for the FP64 direct sum
     int32_t* rlist2 = rlist + n_pairs;
-    int32_t* rn2 = meta_at<int32_t>(ctx, kMetaRefitN2);
+    int32_t* rn2 = W.at<int32_t>(kMetaRefitN2);
     Outs ro = out;
     ro.refit_list = P.crossings ? rlist2 : nullptr;
     ro.refit_n = P.crossings ? rn2 : nullptr;
@@ -445,7 +477,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     if (!P.crossings) B.cc_blk = B.cc_sup = nullptr;
     B.cc_tau = (float)(kCcTau64 * ctx->cc_tol);
     B.cc_tau_p = (float)(kCcTauP64 * ctx->cc_tol);
-    B.s = make_sched(ctx, n_pairs, 1);
+    B.s = make_sched(W, n_pairs, 1);
     B.tile = default_tile(true);
     B.chunk = R.chunk;
     // refits are few and latency-bound: one pair per work index spreads them
@@ -453,7 +485,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
     B.batch = 1;
     B.out = ro;
     LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
-    LK_HIP(launch_sched(B.s, P.crossings ? meta_at<int32_t>(ctx, kMetaCountsRefit2) : nullptr, s));
+    LK_HIP(launch_sched(B.s, P.crossings ? W.at<int32_t>(kMetaCountsRefit2) : nullptr, s));
     if (timed) LK_HIP(hipEventRecord(ev[2], s));
     // the FP64 crossing count gets the whole grid: its pairs are the ones
     // with shallow crossings, often the largest
@@ -473,7 +505,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Plan& P, const void* xyz, const 
       R2.out = r2;
       DsArgs B2 = B;
       B2.cc_blk = B2.cc_sup = nullptr;
-      B2.s = make_sched(ctx, n_pairs, 2);
+      B2.s = make_sched(W, n_pairs, 2);
       B2.chunk = R2.chunk;
       B2.out = r2;
       LK_HIP(launch_plan(R2, n_loops, li, B2.s, true, s));
@@ -587,6 +619,67 @@ lk_status set_device(lk_ctx* ctx) {
   return LK_OK;
 }
 
+// ------------------------------------------------ no-allocation workspace
+// lk_direct_sum_noalloc runs the PLAIN_F64 / MIXED kernel sequence with its
+// workspace carved from one static device array instead of the context's
+// buffers.  Its limits size that array.
+constexpr int32_t kNoallocMaxLoops = 65536;
+constexpr int64_t kNoallocMaxPairs = 131072;
+
+constexpr size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Byte offsets of the workspace arrays for L loops and P pairs (each aligned
+// to 256 bytes; the same arrays and sizes as ensure_workspace, plus flags).
+struct NoallocLayout {
+  size_t lf, minseg2, xi, recs, big_prefix, meta, acc, refit, flags, total;
+};
+
+constexpr NoallocLayout noalloc_layout(size_t L, size_t P) {
+  NoallocLayout y{};
+  y.lf = 0;
+  y.minseg2 = y.lf + al256(4 * L);
+  y.xi = y.minseg2 + al256(8 * L);
+  y.recs = y.xi + al256(8 * (size_t)(lk::kPrepMaxBlocks + 1));
+  y.big_prefix = y.recs + al256(3 * sizeof(lk::WorkRec) * P);
+  y.meta = y.big_prefix + al256(8 * (P + 1));
+  y.acc = y.meta + al256(kMetaBytes);
+  y.refit = y.acc + al256(16 * P);
+  y.flags = y.refit + al256(8 * P);
+  y.total = y.flags + al256(4 * P);
+  return y;
+}
+
+constexpr size_t kNoallocBytes =
+    noalloc_layout((size_t)kNoallocMaxLoops, (size_t)kNoallocMaxPairs).total;
+
+}  // namespace
+
+// The no-allocation entry point's workspace (about 17.6 MiB; each device the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes this name to a kernel: it stands for a host-side shadow, not
+// the device address, which is looked up per device below.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// With `device` current: look up that device's copy of `scratch`, once.
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -607,6 +700,12 @@ lk_status lk_create(lk_ctx** out, int device) {
   }
   ctx->n_cu = prop.multiProcessorCount;
   memset(&ctx->stats, 0, sizeof(ctx->stats));
+  // messages are formatted into at most 512 bytes: with the capacity reserved
+  // here, reporting an error later allocates nothing
+  ctx->err.reserve(512);
+  // the no-allocation entry point's device address of `scratch` on this
+  // device (a failure is reported by that entry point, not here)
+  scratch_setup(device);
   // a generic direction (no coordinate plane or diagonal), exact in FP32
   ctx->view[0] = 0.3671875f;
   ctx->view[1] = -0.6103515625f;
@@ -833,7 +932,7 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
       const int slots = (int)(ctx->ring.size() / 4);
       ev = &ctx->ring[4 * (size_t)(ctx->ring_pos % slots)];
     }
-    st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
+    st = enqueue_direct_sum(ctx, ctx_ws(ctx), P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
                             ev, ck);
     if (timed && st == LK_OK) {
       const int slots = (int)(ctx->ring.size() / 4);
@@ -858,7 +957,7 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
     ctx->graphs.erase(it);
   }
   LK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
+  st = enqueue_direct_sum(ctx, ctx_ws(ctx), P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags, s,
                           nullptr, ck);
   hipGraph_t g = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &g);
@@ -907,6 +1006,66 @@ lk_status lk_direct_sum_check(lk_ctx* ctx, const void* xyz, int dtype, const int
   ck.n_mismatch = n_mismatch;
   return direct_sum_call(ctx, xyz, dtype, off, n_loops, pairs, n_pairs, mode, lk_real, lk_int,
                          flags, stream, ck);
+}
+
+lk_status lk_direct_sum_noalloc(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                                int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                                double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream) {
+  if (!ctx) return LK_EINVAL;
+  ctx->err.clear();
+  if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
+  if (mode != LK_PLAIN_F64 && mode != LK_MIXED)
+    return ctx->fail(LK_EINVAL, "mode %d: the no-allocation direct sum runs PLAIN_F64 and MIXED only",
+                     mode);
+  if (n_loops < 1) return ctx->fail(LK_EINVAL, "n_loops must be >= 1");
+  if (n_pairs < 0) return ctx->fail(LK_EINVAL, "n_pairs must be >= 0");
+  if (n_loops > kNoallocMaxLoops || n_pairs > kNoallocMaxPairs)
+    return ctx->fail(LK_ECAPACITY,
+                     "%d loops and %lld pairs exceed the static workspace (at most %d loops and "
+                     "%lld pairs)",
+                     n_loops, (long long)n_pairs, kNoallocMaxLoops, (long long)kNoallocMaxPairs);
+  if (!xyz || !off || (n_pairs > 0 && (!pairs || !lk_real || !lk_int)))
+    return ctx->fail(LK_EINVAL, "null pointer argument");
+  lk_status st = set_device(ctx);
+  if (st != LK_OK) return st;
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device < kMaxDevices) base = (char*)g_scratch_ptr[ctx->device];
+    if (!base)
+      return ctx->fail(LK_EDEVICE, "static workspace of device %d unavailable: %s", ctx->device,
+                       ctx->device < kMaxDevices && g_scratch_tried[ctx->device]
+                           ? hipGetErrorString(g_scratch_err[ctx->device])
+                           : "not set up");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // lk_get_stats reports this call's configuration, not its refit count
+  ctx->stats = lk_stats{};
+  ctx->last_mixed = ctx->last_crossings = ctx->last_bh = ctx->last_timed = false;
+  if (n_pairs == 0) return LK_OK;
+
+  const NoallocLayout y = noalloc_layout((size_t)n_loops, (size_t)n_pairs);
+  Ws W;
+  W.loop_flags = (uint32_t*)(base + y.lf);
+  W.minseg2 = (double*)(base + y.minseg2);
+  W.xi = (double*)(base + y.xi);
+  W.recs = (lk::WorkRec*)(base + y.recs);
+  W.big_prefix = (int64_t*)(base + y.big_prefix);
+  W.meta = base + y.meta;
+  W.acc = (unsigned long long*)(base + y.acc);
+  W.refit_list = (int32_t*)(base + y.refit);
+  if (!flags) flags = (uint32_t*)(base + y.flags);
+
+  const bool mixed = mode == LK_MIXED;
+  const Plan P = make_plan(ctx, dtype == LK_F64, mode);
+  ctx->stats.tile_a = P.tile;
+  ctx->stats.chunk_a = P.chunk;
+  ctx->stats.waves_per_cu = (mixed ? P.grid : P.grid64) / (ctx->n_cu > 0 ? ctx->n_cu : 1);
+  ctx->stats.atan_form = P.atan_form;
+  ctx->stats.segs_per_lane = mixed ? P.segs : P.segs64;
+  // eager launches only: instantiating a graph would allocate
+  return enqueue_direct_sum(ctx, W, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int, flags,
+                            s, nullptr);
 }
 
 lk_status lk_get_stats(lk_ctx* ctx, lk_stats* out) {
@@ -1344,7 +1503,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     double best = 1e30;
     int reps = 3;
     for (int r = 0; r <= reps; ++r) {
-      lk_status e = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
+      lk_status e = enqueue_direct_sum(ctx, ctx_ws(ctx), P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
                                        flags, s, ev);
       if (e != LK_OK) return e;
       LK_HIP(hipStreamSynchronize(s));
@@ -1420,7 +1579,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   // leave the outputs as a valid result of the chosen configuration
   {
     const Plan P = make_plan(ctx, in_f64, mode);
-    if ((st = enqueue_direct_sum(ctx, P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
+    if ((st = enqueue_direct_sum(ctx, ctx_ws(ctx), P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
                                  flags, s, nullptr)) != LK_OK)
       return st;
     LK_HIP(hipStreamSynchronize(s));
@@ -1436,4 +1595,5 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
 }
 
 }  // extern "C"
+
 
