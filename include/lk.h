@@ -403,16 +403,23 @@ typedef struct {
   int64_t n_flagged;   /* pairs with NONFINITE, BADPAIR, BADLOOP or AMBIGUOUS set */
   int64_t refits;      /* pairs recomputed in FP64 */
   double terms;        /* segment-pair terms evaluated */
-  int64_t bytes;       /* device bytes charged to the budget while it ran */
+  int64_t bytes;       /* device bytes of its own buffers charged while it ran */
   double t_submit;     /* seconds (server clock) when submitted */
   double t_admit;      /* ... when admitted to a slot */
   double t_done;       /* ... when its results were on the host */
 } lk_result;
 
 /* Create a server on `device` with `slots` concurrent slots (1..8), a device
- * memory budget in bytes for request data (0 = 80% of free memory), the
- * direct-sum mode of every request, and per-slot workspace reserved for up to
- * max_loops loops and max_pairs candidate pairs per request. */
+ * memory budget in bytes (0 = 80% of free memory), the direct-sum mode of
+ * every request, and per-slot workspace reserved for up to max_loops loops
+ * and max_pairs candidate pairs per request.  The budget covers sessions,
+ * each running request's buffers (charged for a first guess of its pair
+ * count, corrected once the pairs are counted; a request whose charge grows
+ * waits for memory unless nothing else could free it) and the growth of a
+ * slot's workspace beyond the reservation made here (the Barnes-Hut trees and
+ * lists, about 150 bytes per vertex, and the crossing-count boxes are sized
+ * per request).  A request is admitted over the budget only when nothing else
+ * runs. */
 lk_status lk_server_create(lk_server** out, int device, int32_t slots, int64_t mem_budget,
                            int mode, int32_t max_loops, int64_t max_pairs);
 /* Stop accepting, finish queued and running requests, free everything. */

@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
     const int64_t s = slot - ((oi - o0) / kCcSuper + lo);
     const int64_t nblk = n > 0 ? (n + kCcBlock - 1) / kCcBlock : 0;
     constexpr int64_t kPer = kCcSuper / kCcBlock;
-    if (s * kPer >= nblk) continue;  // slot not used by the loop (uniform over the wave)
+    // slot not used by the loop, or offsets that decrease (uniform over the wave)
+    if (n <= 0 || s < 0 || s * kPer >= nblk) continue;
     const int64_t bbase = (oi - o0) / kCcBlock + lo;
     float4 acc = float4{INFINITY, -INFINITY, INFINITY, -INFINITY};
     uint32_t f = 0u;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void cc_boxes_k(const Tin* X, const int64_t* o
       }
       const float pad = 4.76837158203125e-7f * mag;  // 8 * 2^-24
       const float4 box = float4{a0 - pad, a1 + pad, b0 - pad, b1 + pad};
-      if (lane == 0 && bbase + k < n_blk) blk[bbase + k] = box;
+      if (lane == 0 && (uint64_t)(bbase + k) < (uint64_t)n_blk) blk[bbase + k] = box;
       acc = box_join(acc, box);
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -392,7 +393,8 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
       if (A.cc_sup && valid && !too_big && items > 0 && r.na <= kCcSuper && r.nb <= kCcSuper) {
         const int64_t o0 = A.off[0];
         const int64_t si = (r.oa - o0) / kCcSuper + i, sj = (r.ob - o0) / kCcSuper + j;
-        if (si < A.cc_nsup && sj < A.cc_nsup && boxes_disjoint(A.cc_sup[si], A.cc_sup[sj]))
+        if ((uint64_t)si < (uint64_t)A.cc_nsup && (uint64_t)sj < (uint64_t)A.cc_nsup &&
+            boxes_disjoint(A.cc_sup[si], A.cc_sup[sj]))
           items = 0;
       }
       uint32_t f;

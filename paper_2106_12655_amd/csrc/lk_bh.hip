@@ -84,7 +84,8 @@ __global__ __launch_bounds__(64) void bh_leaves_k(BhArgs A) {
     const int32_t i = find_loop(A.off, A.n_loops, slot, kBhLeaf);
     const int64_t oi = A.off[i], n = A.off[i + 1] - oi;
     const int64_t k = slot - ((oi - A.off[0]) / kBhLeaf + i);
-    if (k >= bh_count(n, 0)) continue;  // uniform over the workgroup
+    // (offsets that decrease make no node: every read stays in the loop)
+    if (n <= 0 || k < 0 || k >= bh_count(n, 0)) continue;  // uniform over the workgroup
     const int64_t a = k * kBhLeaf;
     const int m = (int)((n - a) < kBhLeaf ? (n - a) : kBhLeaf);
     double x0[3] = {0, 0, 0}, x1[3] = {0, 0, 0};
@@ -182,14 +183,14 @@ __global__ __launch_bounds__(256) void bh_level_k(BhArgs A, int h) {
     const int64_t n = A.off[i + 1] - A.off[i];
     const int64_t k = slot - ((A.off[i] - A.off[0]) / span + i);
     const int64_t nch = bh_count(n, h - 1);
-    if (k >= bh_count(n, h) || nch <= 1) continue;  // no such node, or above the root
+    if (n <= 0 || k < 0 || k >= bh_count(n, h) || nch <= 1) continue;  // no such node, or above the root
     if (slot >= A.level_cap[h]) continue;
     const int64_t c0 = k * kBhArity, c1 = (c0 + kBhArity) < nch ? c0 + kBhArity : nch;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool ok = true;
     for (int64_t c = c0; c < c1; ++c) {
       const int64_t cs = node_slot(A, i, h - 1, c);
-      if (cs - A.level_base[h - 1] >= A.level_cap[h - 1]) {
+      if ((uint64_t)(cs - A.level_base[h - 1]) >= (uint64_t)A.level_cap[h - 1]) {
         ok = false;
         break;
       }
@@ -361,7 +362,8 @@ __device__ __forceinline__ int64_t wave_reserve(int32_t* count, int n) {
 // Node (level h, index k) of loop `loop`: its slot, or -1 beyond the buffer.
 __device__ __forceinline__ int64_t checked_slot(const BhArgs& A, int32_t loop, int h, int64_t k) {
   const int64_t s = node_slot(A, loop, h, k);
-  return s - A.level_base[h] < A.level_cap[h] ? s : -1;
+  // unsigned: a slot below the level (offsets that decrease) is refused too
+  return (uint64_t)(s - A.level_base[h]) < (uint64_t)A.level_cap[h] ? s : -1;
 }
 
 __device__ __forceinline__ bool is_far(double beta, const BhNode& u, const BhNode& v) {

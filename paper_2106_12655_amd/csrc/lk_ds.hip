@@ -576,7 +576,7 @@ __device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X,
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     if (L.b0 + (int64_t)c * kCcBlock < r.nb) {
-      if (bslot + c < A.cc_nblk) {
+      if ((uint64_t)(bslot + c) < (uint64_t)A.cc_nblk) {
         const float4 q = A.cc_blk[bslot + c];
         bb = float4{fminf(bb.x, q.x), fmaxf(bb.y, q.y), fminf(bb.z, q.z), fmaxf(bb.w, q.w)};
       } else {
@@ -590,11 +590,13 @@ __device__ __forceinline__ void cc_item_culled(const DsArgs& A, const Tin* X,
   const int a0 = (int)L.a0, a_end = (int)L.a0 + L.nah;
   const int lo_l = a0 + L.js, hi_l = a0 + L.je;  // this lane's segments of A
   for (int sp = a0 / kCcSuper; sp * kCcSuper < a_end; ++sp) {
-    if (asup + sp < A.cc_nsup && boxes_disjoint(A.cc_sup[asup + sp], bb)) continue;
+    if ((uint64_t)(asup + sp) < (uint64_t)A.cc_nsup && boxes_disjoint(A.cc_sup[asup + sp], bb))
+      continue;
     const int k0 = max(sp * (kCcSuper / kCcBlock), a0 / kCcBlock);
     const int k1 = min((sp + 1) * (kCcSuper / kCcBlock), (a_end + kCcBlock - 1) / kCcBlock);
     for (int k = k0; k < k1; ++k) {
-      if (ablk + k < A.cc_nblk && boxes_disjoint(A.cc_blk[ablk + k], bb)) continue;
+      if ((uint64_t)(ablk + k) < (uint64_t)A.cc_nblk && boxes_disjoint(A.cc_blk[ablk + k], bb))
+        continue;
       const int v0 = k * kCcBlock;
       __syncthreads();
       for (int t = lane; t <= kCcBlock; t += kWave) {

@@ -415,3 +415,17 @@ hipError_t launch_verify_scatter(const int32_t* pairs, const int32_t* lk, int64_
                                  hipStream_t s);
 
 }  // namespace lk
+
+// Runtime internals the verification server uses (lk_runtime.hip).
+struct lk_ctx;
+namespace lk {
+// Device bytes the context's workspace holds now.
+int64_t ctx_workspace_bytes(const lk_ctx* ctx);
+// Device bytes a context's workspace may grow to for one request in `mode`
+// (pair search, direct sum and verification of n_verify entries).
+int64_t ctx_workspace_need(int mode, int32_t n_loops, int64_t n_pairs, int64_t n_vertices,
+                           int64_t n_verify);
+// Drop the cached vertex count of the last offsets array (the next CROSSINGS
+// or BARNES_HUT call reads and validates it again).
+void ctx_forget_offsets(lk_ctx* ctx);
+}  // namespace lk

@@ -88,6 +88,11 @@ struct lk_ctx {
   double bh_beta_max = 10.0;
   double bh_target = 0.2;
   uint64_t ws_epoch = 0;  // bumped whenever a workspace buffer moves
+  // completion of the context's last enqueued work (calls on one context do
+  // not overlap, so it covers every earlier call): a buffer that grows waits
+  // for it instead of for the whole device
+  hipEvent_t done = nullptr;
+  bool done_pending = false;
   // graphs
   struct Cached {
     hipGraphExec_t exec = nullptr;
@@ -131,9 +136,13 @@ lk_status ensure(lk_ctx* ctx, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes) return LK_OK;
   size_t want = bytes + bytes / 4;
   if (b.p) {
-    // buffers may be referenced by work still in flight on any stream
-    if (hipDeviceSynchronize() != hipSuccess) return ctx->fail(LK_EDEVICE, "sync before realloc");
-    hipFree(b.p);
+    // the buffer may be referenced by this context's work still in flight
+    if (ctx->done_pending) {
+      if (hipEventSynchronize(ctx->done) != hipSuccess)
+        return ctx->fail(LK_EDEVICE, "sync before realloc");
+      ctx->done_pending = false;
+    }
+    (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -145,6 +154,15 @@ lk_status ensure(lk_ctx* ctx, DevBuf& b, size_t bytes) {
   b.bytes = want;
   ctx->ws_epoch++;
   return LK_OK;
+}
+
+// Mark the end of the work just enqueued on `s` (not while `s` is being
+// captured: that work runs when the caller launches its graph).
+void mark_done(lk_ctx* ctx, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s && hipStreamIsCapturing(s, &cs) != hipSuccess) return;
+  if (cs != hipStreamCaptureStatusNone || !ctx->done) return;
+  if (hipEventRecord(ctx->done, s) == hipSuccess) ctx->done_pending = true;
 }
 
 int default_tile(bool f64) { return f64 ? 256 : 512; }
@@ -703,6 +721,10 @@ lk_status lk_create(lk_ctx** out, int device) {
   // messages are formatted into at most 512 bytes: with the capacity reserved
   // here, reporting an error later allocates nothing
   ctx->err.reserve(512);
+  if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return LK_EDEVICE;
+  }
   // the no-allocation entry point's device address of `scratch` on this
   // device (a failure is reported by that entry point, not here)
   scratch_setup(device);
@@ -716,8 +738,9 @@ lk_status lk_create(lk_ctx** out, int device) {
 
 void lk_destroy(lk_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(ctx->device);
+  // the context's own work must end before its buffers go
+  if (ctx->done_pending) (void)hipEventSynchronize(ctx->done);
   for (auto& kv : ctx->graphs)
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   DevBuf* bufs[] = {&ctx->loop_flags, &ctx->minseg2, &ctx->xi,      &ctx->recs,
@@ -732,6 +755,7 @@ void lk_destroy(lk_ctx* ctx) {
     if (b->p) hipFree(b->p);
   for (auto& e : ctx->ring)
     if (e) hipEventDestroy(e);
+  if (ctx->done) hipEventDestroy(ctx->done);
   delete ctx;
 }
 
@@ -870,10 +894,10 @@ lk_status lk_get_view_direction(const lk_ctx* ctx, double* dir) {
 
 namespace {
 
-lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
-                          int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
-                          double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream,
-                          const Check& ck) {
+lk_status direct_sum_enqueue(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                             int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                             double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream,
+                             const Check& ck) {
   if (!ctx) return LK_EINVAL;
   ctx->err.clear();
   if (!check_dtype(dtype)) return ctx->fail(LK_EINVAL, "unknown dtype %d", dtype);
@@ -979,6 +1003,16 @@ lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t
   ctx->graphs[key] = {ex, ctx->ws_epoch};
   LK_HIP(hipGraphLaunch(ex, s));
   return LK_OK;
+}
+
+lk_status direct_sum_call(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* off,
+                          int32_t n_loops, const int32_t* pairs, int64_t n_pairs, int mode,
+                          double* lk_real, int32_t* lk_int, uint32_t* flags, void* stream,
+                          const Check& ck) {
+  const lk_status st = direct_sum_enqueue(ctx, xyz, dtype, off, n_loops, pairs, n_pairs, mode,
+                                          lk_real, lk_int, flags, stream, ck);
+  if (st == LK_OK) mark_done(ctx, (hipStream_t)stream);
+  return st;
 }
 
 }  // namespace
@@ -1327,6 +1361,7 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
   *n_vertices = n;
   lk::DzArgs a = args(cur, n, nu);
   LK_HIP(lk::launch_dz_finish(a, xyz_out, capacity, offsets_out, loop_flags, s));
+  mark_done(ctx, s);
   if (info) {
     memset(info, 0, sizeof(*info));
     info->passes = passes;
@@ -1597,3 +1632,45 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
 }  // extern "C"
 
 
+// ------------------------------------------- runtime internals for the server
+namespace lk {
+
+int64_t ctx_workspace_bytes(const lk_ctx* ctx) {
+  const DevBuf* bufs[] = {&ctx->loop_flags, &ctx->minseg2, &ctx->xi,       &ctx->recs,
+                          &ctx->big_prefix, &ctx->meta,    &ctx->acc,      &ctx->flags,
+                          &ctx->refit_list, &ctx->boxes,   &ctx->vcounts,  &ctx->vprefix,
+                          &ctx->cc_blk,     &ctx->cc_sup,  &ctx->bh_nodes, &ctx->bh_lists,
+                          &ctx->bh_counts,  &ctx->bh_adapt, &ctx->pls_grid};
+  int64_t b = 0;
+  for (const DevBuf* d : bufs) b += (int64_t)d->bytes;
+  return b;
+}
+
+int64_t ctx_workspace_need(int mode, int32_t n_loops, int64_t n_pairs, int64_t n_vertices,
+                           int64_t n_verify) {
+  const double L = (double)n_loops, P = (double)n_pairs, V = (double)n_vertices;
+  // the direct sum's own arrays (ensure_workspace) and its flags
+  double b = 12.0 * L + 8.0 * (kPrepMaxBlocks + 1) + 3.0 * sizeof(WorkRec) * P + 8.0 * (P + 1) +
+             (double)kMetaBytes + 16.0 * P + 8.0 * P + 4.0 * P;
+  // the pair search: boxes, counts, prefix, and the grid (buckets <= 8 L)
+  b += 48.0 * L + 8.0 * L + 8.0 * (L + 1) + (n_loops >= 2048 ? 192.0 * L + 4096.0 : 0.0);
+  // verification's flags and prefix over current + expected pairs
+  b += 16.0 * (double)(n_verify + 1);
+  if (mode == LK_CROSSINGS)
+    b += 16.0 * (V / kCcBlock + L + 1) + 16.0 * (V / kCcSuper + L + 1);
+  if (mode == LK_BARNES_HUT) {
+    const BhLayout Y = bh_layout(n_vertices, n_loops, n_pairs);
+    b += (double)sizeof(BhNode) * (double)Y.nodes +
+         (double)sizeof(BhPair) * (double)(2 * Y.list_cap + Y.near_cap) + 24.0 * (P + 1) +
+         4.0 * (kBhMaxIters + 3);
+  }
+  return (int64_t)(1.25 * b);  // ensure() allocates a quarter more than asked
+}
+
+void ctx_forget_offsets(lk_ctx* ctx) {
+  ctx->cc_off_key = nullptr;
+  ctx->cc_loops_key = -1;
+  ctx->cc_vertices = 0;
+}
+
+}  // namespace lk

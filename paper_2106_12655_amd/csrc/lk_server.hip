@@ -11,6 +11,15 @@
 // synchronisation when they come and go).  Large requests cap their
 // persistent grid at three quarters of the resident waves and small ones at a
 // quarter, so a large job never blocks the device for the small ones behind it.
+//
+// Memory admission: a request is charged its own buffers for a first guess of
+// its pair count, and its slot the workspace its context would grow to
+// (pair search, direct sum, verification, and the Barnes-Hut trees or
+// crossing-count boxes of the mode); sessions are charged their resident
+// arrays.  Once the request's pairs are counted the charge is corrected,
+// waiting for memory if it grew, and after the request the slot's real
+// workspace replaces the estimate.  The workspace reserved when the server is
+// created lies outside the budget.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -27,6 +36,7 @@
 #include <vector>
 
 #include "../../include/lk.h"
+#include "lk_internal.h"
 
 namespace {
 
@@ -68,7 +78,11 @@ struct lk_server {
   int device = 0;
   int mode = LK_MIXED;
   int64_t budget = 0;
+  // bytes charged against the budget: sessions, admitted requests, and the
+  // slots' workspace growth beyond what the server reserved at creation
   int64_t in_use = 0;
+  int running = 0;  // admitted requests not yet finished
+  int waiting = 0;  // of those, waiting for memory after their pair count came in
   int32_t max_loops = 0;
   int64_t max_pairs = 0;
   std::mutex mu;
@@ -84,6 +98,9 @@ struct lk_server {
     lk_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
     std::thread th;
+    int64_t ws_base = 0;     // workspace reserved at creation (outside the budget)
+    int64_t ws_charged = 0;  // growth beyond ws_base, charged to in_use
+    int64_t last_session = 0;
   };
   std::vector<Slot> slots;
 
@@ -102,14 +119,45 @@ namespace {
 
 size_t dtype_size(int dtype) { return dtype == LK_F64 ? 8 : 4; }
 
-// Device bytes a request is charged before its pair count is known.
-int64_t estimate_bytes(const lk_server* srv, const Session& S, int dtype, int where) {
+// First guess of a request's candidate pairs (corrected once they are counted).
+int64_t guess_pairs(const lk_server* srv, const Session& S) {
+  int64_t pairs = 16 * (int64_t)S.n_loops;
+  return pairs > srv->max_pairs ? srv->max_pairs : pairs;
+}
+
+// Device bytes of a request's own buffers for `pairs` candidate pairs: the
+// geometry copy (host input), pairs, values, integers, flags and mismatch
+// records (as run_request allocates them).
+int64_t request_bytes(const Session& S, int dtype, int where, int64_t pairs) {
   int64_t b = 0;
   if (where == LK_MEM_HOST) b += S.n_vert * 3 * (int64_t)dtype_size(dtype);
-  int64_t pairs = 16 * (int64_t)S.n_loops;
-  if (pairs > srv->max_pairs) pairs = srv->max_pairs;
-  b += pairs * (8 + 8 + 4 + 4) + 16 * (pairs + S.n_exp);
-  return b;
+  return b + pairs * (8 + 8 + 4 + 4) + 16 * (pairs + S.n_exp) + 64;
+}
+
+// Workspace growth a slot's context may need for a request with `pairs`
+// pairs beyond what it already holds (charged when the request is admitted).
+int64_t workspace_extra(const lk_server* srv, const lk_server::Slot& slot, const Session& S,
+                        int64_t pairs) {
+  const int64_t need =
+      lk::ctx_workspace_need(srv->mode, S.n_loops, pairs, S.n_vert, pairs + S.n_exp);
+  const int64_t have = slot.ws_base + slot.ws_charged;
+  return need > have ? need - have : 0;
+}
+
+// Charge `delta` more bytes (negative: release).  A request whose real size
+// came out larger than its charge waits until the others have freed enough,
+// unless every other running request is waiting too (then it goes over the
+// budget rather than deadlock).  Called with the lock held.
+void recharge(lk_server* srv, std::unique_lock<std::mutex>& lock, int64_t delta) {
+  if (delta > 0 && srv->in_use + delta > srv->budget) {
+    ++srv->waiting;
+    srv->cv_done.notify_all();  // other waiters re-check whether everyone waits
+    srv->cv_done.wait(lock, [&] {
+      return srv->in_use + delta <= srv->budget || srv->running - srv->waiting <= 0;
+    });
+    --srv->waiting;
+  }
+  srv->in_use += delta;
 }
 
 // Run one request on a slot (called without the server lock held).
@@ -121,7 +169,13 @@ void run_request(lk_server* srv, lk_server::Slot& slot, Request& R, const Sessio
     res.status = status;
     return;
   };
-  hipSetDevice(srv->device);
+  (void)hipSetDevice(srv->device);
+  if (slot.last_session != R.session) {
+    // another session's offsets may sit at a freed session's address: the
+    // context must not reuse the vertex count it cached for that address
+    lk::ctx_forget_offsets(ctx);
+    slot.last_session = R.session;
+  }
   void* xyz = const_cast<void*>(R.xyz);
   void* xyz_copy = nullptr;
   const size_t xyz_bytes = (size_t)S.n_vert * 3 * dtype_size(R.dtype);
@@ -143,6 +197,16 @@ void run_request(lk_server* srv, lk_server::Slot& slot, Request& R, const Sessio
   if (n > srv->max_pairs) {
     if (xyz_copy) hipFreeAsync(xyz_copy, st);
     return failed(LK_ECAPACITY);
+  }
+  {
+    // the charge made on admission guessed the pair count: correct it, for
+    // the request's buffers and for the workspace its context grows to
+    std::unique_lock<std::mutex> lock(srv->mu);
+    const int64_t real = request_bytes(S, R.dtype, R.where, n);
+    const int64_t ws = workspace_extra(srv, slot, S, n);
+    recharge(srv, lock, (real - R.bytes) + ws);
+    R.bytes = real;
+    slot.ws_charged += ws;
   }
   const int64_t cap_m = n + S.n_exp;
   char* buf = nullptr;
@@ -218,22 +282,32 @@ void slot_loop(lk_server* srv, int index) {
     Session S;
     {
       std::unique_lock<std::mutex> lock(srv->mu);
+      int64_t extra = 0;
       srv->cv_work.wait(lock, [&] {
         if (srv->pending.empty()) return srv->stopping;
         const auto& head = srv->pending.front();
-        return srv->in_use + head->bytes <= srv->budget || srv->in_use == 0;
+        const Session& hs = srv->sessions[head->session];
+        extra = workspace_extra(srv, slot, hs, guess_pairs(srv, hs));
+        return srv->in_use + head->bytes + extra <= srv->budget || srv->running == 0;
       });
       if (srv->pending.empty()) return;  // stopping and drained
       R = srv->pending.front();
       srv->pending.pop_front();
-      srv->in_use += R->bytes;
+      srv->in_use += R->bytes + extra;
+      slot.ws_charged += extra;
+      ++srv->running;
       R->res.t_admit = now_s(srv->t0);
       R->res.slot = index;
       S = srv->sessions[R->session];  // copy of the descriptor (device pointers stay valid)
     }
     run_request(srv, slot, *R, S);
+    // the workspace the context really holds now (it only grows)
+    const int64_t grown = lk::ctx_workspace_bytes(slot.ctx) - slot.ws_base;
     {
       std::lock_guard<std::mutex> lock(srv->mu);
+      srv->in_use += grown - slot.ws_charged;
+      slot.ws_charged = grown;
+      --srv->running;
       srv->in_use -= R->bytes;
       R->res.bytes = R->bytes;
       R->res.t_done = now_s(srv->t0);
@@ -285,6 +359,7 @@ lk_status lk_server_create(lk_server** out, int device, int32_t slots, int64_t m
     if (st == LK_OK) st = lk_reserve(sl.ctx, max_loops, max_pairs, 2 * max_pairs + max_loops);
     if (st == LK_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
       st = LK_EDEVICE;
+    if (st == LK_OK) sl.ws_base = lk::ctx_workspace_bytes(sl.ctx);
     if (st != LK_OK) {
       for (auto& s2 : srv->slots) {
         if (s2.ctx) lk_destroy(s2.ctx);
@@ -403,7 +478,7 @@ lk_status lk_server_submit(lk_server* srv, int64_t session, const void* xyz, int
     R->xyz = xyz;
     R->dtype = dtype;
     R->where = where;
-    R->bytes = estimate_bytes(srv, it->second, dtype, where);
+    R->bytes = request_bytes(it->second, dtype, where, guess_pairs(srv, it->second));
     if (R->bytes > srv->budget)
       return srv->fail(LK_ECAPACITY, "request needs %lld bytes, budget %lld",
                        (long long)R->bytes, (long long)srv->budget);

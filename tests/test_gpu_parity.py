@@ -427,3 +427,28 @@ def test_decreasing_offsets(ctx):
     f = flags.cpu().numpy().view(np.uint32)
     assert f[1] & lk_mod.FLAG_BADLOOP and f[0] == 0 and f[2] == 0
     assert int(lk[0].item()) == int(ls.expected_for(np.array([[0, 1]]))[0])
+
+
+def test_offsets_buffer_reused_with_other_loops():
+    """The crossing-count and Barnes-Hut modes size their boxes and trees from
+    the vertex count, read once per offsets address.  A caller that writes a
+    different loop structure into the same offsets buffer gets exact results
+    (slots beyond the sizing are refused, which only costs speed)."""
+    import torch
+    import paper_2106_12655_amd as lk_mod
+    small = I.ring_grid(3)                                # 64 loops x 32
+    big = I.ring_grid(4, rows=8, cols=8, nseg=96)         # 64 loops x 96: 3x the vertices
+    for mode in ("crossings", "barnes_hut"):
+        c = lk_mod.Context(0)
+        off = torch.empty(65, dtype=torch.int64, device="cuda")
+        for ls in (small, big, small):
+            pairs = oracle.aabb_pairs(ls.xyz, ls.offsets)
+            off.copy_(torch.from_numpy(ls.offsets))
+            xyz = torch.from_numpy(np.ascontiguousarray(ls.xyz)).cuda()
+            pr = torch.from_numpy(pairs).cuda()
+            real, lk, flags = c.direct_sum(xyz, off, pr, mode)
+            torch.cuda.synchronize()
+            olk = oracle.direct_sum(ls.xyz, ls.offsets, pairs)[1]
+            assert np.array_equal(lk.cpu().numpy(), olk), (mode, int(ls.offsets[-1]))
+            assert np.array_equal(olk, ls.expected_for(pairs))
+        c.close()

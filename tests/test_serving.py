@@ -97,3 +97,24 @@ def test_stream_in_other_modes(mode):
     print("stream (%s):" % mode, summ, flush=True)
     assert summ["exact"] == 16
     srv.close()
+
+
+@pytest.mark.parametrize("mode", ["crossings", "barnes_hut"])
+def test_sessions_come_and_go(mode):
+    """Sessions opened and closed in turn (their resident offsets may reuse a
+    closed session's device address): every request stays exact.  The budget
+    (96 MiB) holds one request with the workspace its mode grows to (the
+    Barnes-Hut lists of the largest scene are about 60 MB), so the second slot
+    waits for it rather than allocate beside it."""
+    pool = _pool(steps=1)
+    srv = serve.Server(slots=2, mode=mode, budget=96 << 20)
+    for rep in range(2):
+        for e in pool:
+            b = e["base"]
+            sid = srv.open_session(b.offsets, b.exp_pairs, b.exp_lk)
+            x, changed = e["steps"][0]
+            r = srv.wait(srv.submit(sid, x), fetch=True, cap=400000)
+            assert r["status"] == 0, (mode, rep, e["kind"])
+            assert {(m[0], m[1]) for m in r["mismatches"].tolist()} == {tuple(c) for c in changed.tolist()}
+            srv.close_session(sid)
+    srv.close()
