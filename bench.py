@@ -16,10 +16,12 @@ mode; the plain FP64 mode is timed on the same input and reported beside it.
 Before timing, the library's autotuner picks the kernel configuration for
 the workload (on a seeded subset of pairs for the two largest workloads).
 
-``--config serving`` instead drives the continuous-batching server with a
-Poisson stream of verification requests (chainmail / knit timesteps of
-500-20,000 loops x 32-4,096 segments) at a fraction of its measured capacity
-and reports throughput beside p50/p99 latency.
+The default run adds two companion objects: ``knit`` (the knit-like
+workload, 2,000 B-spline rows of 512-16,128 segments, mixed and plain, each
+with its roofline fraction) and ``serving`` (a Poisson stream of 1,000
+verification requests against the continuous-batching server at 0.7 of its
+capacity: throughput, p50/p99 latency, queueing and service per size class).
+``--config serving`` makes the stream the headline instead.
 
 Prints ONE JSON line.  Options:
   --steps K --warmup W   timed / untimed steps (default 20 / 3)
@@ -29,7 +31,8 @@ Prints ONE JSON line.  Options:
                          plain FP64, the crossing count (Alg. 4) and Barnes-Hut
                          (Alg. 6: beta 4, and the adaptive beta from 2) are timed
                          on the same input and reported beside it
-  --no-plain, --no-crossings, --no-bh, --no-dz   skip those companion legs
+  --no-plain, --no-crossings, --no-bh, --no-dz, --no-knit, --no-serving
+                         skip those companion legs
                          (dz: the discretization of Alg. 3, timed on the knit
                          workload's B-spline control points, 314k spans)
   --dz-only              only the discretization leg (profiling)
@@ -89,6 +92,14 @@ WORKLOADS = {
 }
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg: str):
+    """One progress line on stderr as each leg ends (the JSON line is stdout)."""
+    print("bench %6.1fs: %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
 def kernel_isa(symbol: str):
     """Fingerprint of a kernel's assembly in the built library, or None."""
     try:
@@ -136,6 +147,12 @@ def parse():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse a stored choice instead of searching")
+    ap.add_argument("--no-knit", action="store_true",
+                    help="skip the knit companion run (mixed and plain on the knit workload)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving companion run (Poisson stream of verification requests)")
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests in the serving companion's stream")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--scenes", type=int, default=12, help="serving: distinct objects")
@@ -266,12 +283,14 @@ def main():
     tuned = None if args.no_tune or args.mode == "barnes_hut" else tune(
         ctx, ls, xyz, off, pairs, args.mode, lk, args.tune_cache)
     res = time_mode(ctx, xyz, off, pairs, args.mode, args.steps, args.warmup, lk)
+    log("%s %s: %.3f ms per step" % (args.config, args.mode, res["ms_per_step"]))
     other, tuned_plain = None, None
     if not args.no_plain and args.mode == "mixed":
         tuned_plain = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "plain", lk,
                                                      args.tune_cache)
         other = time_mode(ctx, xyz, off, pairs, "plain", max(args.steps // 2, 1),
                           min(args.warmup, 1), lk)
+        log("plain: %.3f ms per step" % other["ms_per_step"])
     bh, bha = None, None
     if not args.no_bh and args.mode == "mixed":
         bh = time_mode(ctx, xyz, off, pairs, "barnes_hut", args.steps, args.warmup, lk)
@@ -281,6 +300,7 @@ def main():
         bha = time_mode(ctx, xyz, off, pairs, "barnes_hut", args.steps, args.warmup, lk)
         ctx.set_option(lk._lib.OPT_BH_ADAPTIVE, 0)
         ctx.set_option(lk._lib.OPT_BH_BETA_MILLI, 4000)
+        log("barnes_hut: %.3f ms per step" % bh["ms_per_step"])
     cc, tuned_cc = None, None
     if not args.no_crossings and args.mode == "mixed":
         tuned_cc = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, "crossings", lk,
@@ -293,6 +313,7 @@ def main():
             cc["exhaustive"] = time_mode(ctx, xyz, off, pairs, "crossings",
                                          max(min(args.steps, 5), 1), min(args.warmup, 1), lk)
             ctx.set_option(lk._lib.OPT_CROSSING_CULL, 1)
+        log("crossings: %.3f ms per step" % cc["ms_per_step"])
 
     value = T / (res["ms_per_step"] * 1e-3)
     fp64 = args.mode == "plain"
@@ -395,10 +416,103 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"], errs = cpu_baseline(ls, pr, res, other, args.cpu_threads, cc)
         line.update(errs)
+        log("oracle baseline: %.1f s" % line["cpu_baseline"]["seconds"])
     if not args.no_dz:
         line["discretization"] = time_discretize(ctx, args, lk, inputs)
+        log("discretization: %.3f ms per call" % line["discretization"]["ms_per_call"])
     ctx.close()
+    if args.mode == "mixed" and args.config == "chainmail":
+        if not args.no_knit:
+            line["knit"] = knit_leg(args, lk, inputs)
+            log("knit: mixed %.1f ms, plain %.1f ms per step" % (
+                line["knit"]["mixed"]["ms_per_step"], line["knit"]["plain"]["ms_per_step"]))
+        if not args.no_serving:
+            line["serving"] = serving_leg(args, args.serving_requests, args.load, args.scenes,
+                                          "mixed")
+            log("serving: p50 %.1f ms, p99 %.1f ms" % (line["serving"]["latency"]["p50_ms"],
+                                                       line["serving"]["latency"]["p99_ms"]))
     print(json.dumps(line), flush=True)
+
+
+def knit_leg(args, lk, inputs):
+    """The knit-like workload (2,000 closed B-spline rows of 512-16,128
+    segments, 6,324 candidate pairs, 5.0e11 terms, FP32) on a context of its
+    own: mixed and plain FP64, each autotuned on a seeded subset of the pairs,
+    timed like the headline (graph replays, then eager calls with the main
+    kernel's HIP events)."""
+    import torch
+    ls = inputs.config("knit", args.seed)
+    ctx = lk.Context(0)
+    xyz = torch.from_numpy(ls.xyz).cuda()
+    off = torch.from_numpy(ls.offsets).cuda()
+    pairs = ctx.build_pairs(xyz, off)
+    pr = pairs.cpu().numpy()
+    T = int(np.sum(ls.sizes[pr[:, 0]].astype(np.int64) * ls.sizes[pr[:, 1]]))
+    exp = ls.expected_for(pr)
+    out = {"workload": "knit", "description": WORKLOADS["knit"], "loops": int(ls.n_loops),
+           "pairs": int(len(pr)), "terms": T, "seed": args.seed}
+    legs = {}
+    for mode, steps in (("mixed", 3), ("plain", 2)):
+        tuned = None if args.no_tune else tune(ctx, ls, xyz, off, pairs, mode, lk, args.tune_cache)
+        r = time_mode(ctx, xyz, off, pairs, mode, steps, 1, lk)
+        peak = PEAK_FP64_TFLOPS if mode == "plain" else PEAK_FP32_TFLOPS
+        ach = FLOP_PER_TERM * T / (r["kernel_ms"] * 1e-3) / 1e12 if r["kernel_ms"] > 0 else 0.0
+        legs[mode] = r
+        out[mode] = {"value": T / (r["ms_per_step"] * 1e-3), "unit": "segment-pairs/s",
+                     "ms_per_step": r["ms_per_step"], "steps": steps,
+                     "graph_replayed": r["graph_replayed"],
+                     "eager_ms_per_step": r["eager_ms_per_step"], "kernel_ms": r["kernel_ms"],
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": ach / peak},
+                     "refits": r["refits"],
+                     "int_mismatch_vs_construction": int(np.sum(r["lk"] != exp)),
+                     "tuned": tuned}
+    out["mixed"]["max_abs_diff_vs_plain"] = float(np.max(np.abs(legs["mixed"]["real"] -
+                                                               legs["plain"]["real"])))
+    out["mixed"]["int_mismatch_vs_plain"] = int(np.sum(legs["mixed"]["lk"] != legs["plain"]["lk"]))
+    ctx.close()
+    return out
+
+
+def serving_leg(args, n_requests, load, scenes, mode):
+    """A Poisson stream of verification requests against the continuous-
+    batching server (4 slots): chainmail and knit timesteps of 500-20,000
+    loops x 32-4,096 segments (at most 3e11 terms each), at `load` times the
+    rate the server sustains when each scene runs alone back to back.
+    Latency is submit to results on the host; it is split into queueing and
+    service per size class, and each request's slowdown over its scene's
+    time alone is reported."""
+    import torch
+    from paper_2106_12655_amd import serve
+    t0 = time.perf_counter()
+    pool = serve.make_pool(args.seed, scenes, max_terms=3e11)
+    gen_s = time.perf_counter() - t0
+    srv = serve.Server(slots=4, mode=mode)
+    log("serving: %d scenes built in %.1f s" % (len(pool), gen_s))
+    alone = serve.service_times(srv, pool)
+    cap = len(pool) / sum(alone)
+    log("serving: capacity %.1f requests/s alone; stream of %d at load %.2f" % (
+        cap, n_requests, load))
+    recs = serve.run_stream(srv, pool, load * cap, n_requests, args.seed)
+    summ = serve.summarize(recs, alone)
+    srv.close()
+    torch.cuda.synchronize()
+    return {
+        "workload": "serving", "description": WORKLOADS["serving"], "mode": mode,
+        "requests": n_requests, "load": load, "scenes": scenes, "slots": 4,
+        "value": summ["terms_per_s"], "unit": "segment-pairs/s",
+        "latency": {"p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
+                    "mean_ms": summ["mean_ms"], "queue_p50_ms": summ["queue_p50_ms"],
+                    "queue_p99_ms": summ["queue_p99_ms"],
+                    "slowdown_p50": summ["slowdown_p50"], "slowdown_p99": summ["slowdown_p99"]},
+        "by_class": summ["by_class"],
+        "throughput_req_s": summ["throughput_req_s"], "capacity_req_s": cap,
+        "span_s": summ["span_s"], "requests_exact": summ["exact"], "refits": summ["refits"],
+        "pool_seconds": gen_s,
+        "pool": [{"kind": e["kind"], "loops": e["n_loops"], "nseg": e["nseg"],
+                  "alone_ms": a * 1e3, "changed": int(len(e["steps"][0][1]))}
+                 for e, a in zip(pool, alone)],
+    }
 
 
 def time_discretize(ctx, args, lk, inputs):
@@ -464,26 +578,18 @@ def time_discretize(ctx, args, lk, inputs):
 
 
 def run_serving(args):
-    """Poisson stream against the continuous-batching server."""
+    """--config serving: the serving leg as the headline line."""
     import torch
-    from paper_2106_12655_amd import serve
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    pool = serve.make_pool(args.seed, args.scenes, max_terms=3e11)
-    gen_s = time.perf_counter() - t0
-    srv = serve.Server(slots=4, mode=args.mode)
-    cap = serve.capacity(srv, pool)
-    recs = serve.run_stream(srv, pool, args.load * cap, args.requests, args.seed)
-    summ = serve.summarize(recs)
-    srv.close()
+    leg = serving_leg(args, args.requests, args.load, args.scenes, args.mode)
     line = {
         "metric": "segment-pair evals/s",
-        "value": summ["terms_per_s"],
+        "value": leg["value"],
         "unit": "segment-pairs/s",
         "n_gpus": 1,
         "steps": args.requests,
-        "warmup": len(pool),
-        "ms_per_step": summ["mean_ms"],
+        "warmup": args.scenes,
+        "ms_per_step": leg["latency"]["mean_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -493,16 +599,9 @@ def run_serving(args):
         "config": {"workload": "serving", "description": WORKLOADS["serving"],
                    "requests": args.requests, "load": args.load, "scenes": args.scenes,
                    "slots": 4, "seed": args.seed, "mode": args.mode},
-        "latency": {"p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
-                    "mean_ms": summ["mean_ms"], "queue_p50_ms": summ["queue_p50_ms"]},
-        "throughput_req_s": summ["throughput_req_s"],
-        "capacity_req_s": cap,
-        "requests_exact": summ["exact"],
-        "refits": summ["refits"],
-        "pool_seconds": gen_s,
-        "pool": [{"kind": e["kind"], "loops": e["n_loops"], "nseg": e["nseg"],
-                  "changed": int(len(e["steps"][0][1]))} for e in pool],
     }
+    line.update({k: v for k, v in leg.items() if k not in ("workload", "description", "value",
+                                                             "unit", "mode")})
     print(json.dumps(line), flush=True)
 
 
@@ -556,8 +655,28 @@ def cpu_baseline(ls, pr, res, other, threads, cc=None):
     if cc is not None and len(idx):
         errs["err_vs_oracle"]["crossings_int_mismatch"] = int(np.sum(cc["lk"][idx] != olk))
     cpu = {"value": terms / dt, "unit": "segment-pairs/s", "cores": cores, "kind": "oracle",
-           "sample": timed, "seconds": dt, "terms": terms}
+           "sample": timed, "seconds": dt, "terms": terms, "threads": cores,
+           "threads_rule": "the process's CPU affinity, at most 16 (the host share of one GPU)",
+           "host": host_cpu(), "oracle_cflags": " ".join(oracle.CFLAGS)}
     return cpu, errs
+
+
+def host_cpu():
+    """Logical CPUs of the host, those this process may run on, and the model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.lower().startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity": aff, "cpu_model": model}
 
 
 if __name__ == "__main__":

@@ -214,6 +214,10 @@ lk_status lk_direct_sum_noalloc(lk_ctx* ctx, const void* xyz, int dtype,
  * written to mismatches [cap][4] as (i, j, got, expected).  With
  * early_exit != 0 the call stops at the first mismatch in pair order:
  * *n_mismatch is 0 or 1 and at most that record is written. */
+lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_t n,
+                    const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp, int early_exit,
+                    int64_t* n_mismatch /* host */, int32_t* mismatches, int64_t cap, void* stream);
+
 /* --------------------------------------------------------- discretization */
 /* Curve kinds of lk_discretize. */
 typedef enum {
@@ -266,9 +270,6 @@ lk_status lk_discretize(lk_ctx* ctx, const double* ctrl, const int64_t* ctrl_off
                         uint32_t* loop_flags, int64_t* n_vertices /* host */,
                         lk_dz_info* info /* host */, void* stream);
 
-lk_status lk_verify(lk_ctx* ctx, const int32_t* pairs, const int32_t* lk, int64_t n,
-                    const int32_t* exp_pairs, const int32_t* exp_lk, int64_t n_exp, int early_exit,
-                    int64_t* n_mismatch /* host */, int32_t* mismatches, int64_t cap, void* stream);
 
 /* ------------------------------------------------------ options and stats */
 enum {

@@ -19,6 +19,8 @@ Structures" (SIGGRAPH 2021):
 * :func:`loop_flags` -- the zero-length-segment test of Alg. 3 plus finiteness.
 * :func:`aabb_pairs` -- brute-force potential link search (Alg. 2 semantics).
 * :func:`crossings` -- brute-force signed crossing count (Sec. 2.1).
+* :func:`verify` -- the before/after comparison of two sparse linking
+  matrices (Sec. 3.1, "Fast Verification").
 """
 from __future__ import annotations
 
@@ -40,12 +42,16 @@ FLAG_NONFINITE = 4
 FLAG_BADLOOP = 16
 
 
+# Optimisation without any change of FP semantics: no fast-math, no
+# contraction into fused multiply-adds, so every operation rounds as written.
+CFLAGS = ["-O3", "-fno-fast-math", "-ffp-contract=off"]
+
+
 def build(force: bool = True) -> str:
-    """Compile lk_oracle.c into liblkoracle.so with gcc (-O2, no fast-math)."""
+    """Compile lk_oracle.c into liblkoracle.so with gcc and CFLAGS."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
-               "-pthread", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", *CFLAGS, "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -74,6 +80,8 @@ def _load():
         lib.lko_loop_flags.argtypes = [p, p, i32, d, p]
         lib.lko_aabb_pairs.restype = i64
         lib.lko_aabb_pairs.argtypes = [p, p, i32, p, i64]
+        lib.lko_verify.restype = i64
+        lib.lko_verify.argtypes = [p, p, i64, p, p, i64, p, i64]
         lib.lko_crossings.restype = d
         lib.lko_crossings.argtypes = [p, i64, p, i64, p, ctypes.POINTER(ctypes.c_int)]
         lib.lko_bh_pair.restype = d
@@ -182,6 +190,22 @@ def aabb_pairs(xyz, offsets):
     out = np.zeros((max(n, 1), 2), dtype=np.int32)
     lib.lko_aabb_pairs(_ptr(xyz), _ptr(off), off.shape[0] - 1, _ptr(out), n)
     return out[:n]
+
+
+def verify(pairs, lk, exp_pairs, exp_lk):
+    """Mismatches between the current (pairs, lk) and the expected
+    (exp_pairs, exp_lk) sparse matrices, both sorted by (i, j); a pair missing
+    on one side counts as 0 there.  Returns int32[m, 4] rows
+    (i, j, current, expected) in pair order."""
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32)).reshape(-1, 2)
+    v = np.ascontiguousarray(np.asarray(lk, dtype=np.int32)).reshape(-1)
+    ep = np.ascontiguousarray(np.asarray(exp_pairs, dtype=np.int32)).reshape(-1, 2)
+    ev = np.ascontiguousarray(np.asarray(exp_lk, dtype=np.int32)).reshape(-1)
+    lib = _load()
+    m = lib.lko_verify(_ptr(pr), _ptr(v), pr.shape[0], _ptr(ep), _ptr(ev), ep.shape[0], None, 0)
+    out = np.zeros((max(m, 1), 4), dtype=np.int32)
+    lib.lko_verify(_ptr(pr), _ptr(v), pr.shape[0], _ptr(ep), _ptr(ev), ep.shape[0], _ptr(out), m)
+    return out[:m]
 
 
 def crossings(L, K, R):

@@ -346,6 +346,53 @@ int lko_direct_sum(const double* xyz, const int64_t* off, int32_t nloops, const 
   return 0;
 }
 
+/* ----------------------------------------------------------- verification */
+/*
+ * The before/after comparison of Sec. 3.1 ("Fast Verification"): the current
+ * sparse linking matrix (pairs, lk)[n] against the expected one
+ * (exp_pairs, exp_lk)[n_exp], both sorted lexicographically by (i, j) with no
+ * duplicates.  A pair missing from one side has the value 0 there (a pair
+ * the potential link search no longer lists has separated boxes, so its
+ * linking number is 0).  Every pair whose two values differ is a mismatch.
+ * The first `cap` mismatches in pair order go to out[cap][4] as
+ * (i, j, current, expected); returns their total count.
+ */
+static int key_cmp(const int32_t* a, const int32_t* b) {
+  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+  if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+  return 0;
+}
+
+int64_t lko_verify(const int32_t* pairs, const int32_t* lk, int64_t n, const int32_t* exp_pairs,
+                   const int32_t* exp_lk, int64_t n_exp, int32_t* out, int64_t cap) {
+  int64_t a = 0, b = 0, count = 0;
+  while (a < n || b < n_exp) {
+    int c;
+    if (a == n)
+      c = 1;
+    else if (b == n_exp)
+      c = -1;
+    else
+      c = key_cmp(&pairs[2 * a], &exp_pairs[2 * b]);
+    const int32_t* key = c <= 0 ? &pairs[2 * a] : &exp_pairs[2 * b];
+    /* mutation 14: a pair only in the expected list takes its expected value */
+    const int32_t got = c <= 0 ? lk[a] : (g_mutation == 14 ? exp_lk[b] : 0);
+    const int32_t want = c >= 0 ? exp_lk[b] : 0;
+    if (got != want) {
+      if (count < cap) {
+        out[4 * count] = key[0];
+        out[4 * count + 1] = key[1];
+        out[4 * count + 2] = got;
+        out[4 * count + 3] = want;
+      }
+      ++count;
+    }
+    if (c <= 0) ++a;
+    if (c >= 0) ++b;
+  }
+  return count;
+}
+
 /* ----------------------------------------------------------- validation */
 /* Loop flags: 16 = bad loop (fewer than 3 vertices, or a segment of length
  * below eps * xi, Alg. 3's zero-length test), 4 = non-finite coordinate.

@@ -220,7 +220,8 @@ def run_stream(server: Server, pool, rate: float, n_requests: int, seed: int = 0
             want = {(int(a), int(b)) for a, b in changed}
             records[k] = {"scene": int(p), "kind": pool[p]["kind"], "loops": pool[p]["n_loops"],
                           "nseg": pool[p]["nseg"], "latency": r["t_done"] - r["t_submit"],
-                          "queue": r["t_admit"] - r["t_submit"], "terms": r["terms"],
+                          "queue": r["t_admit"] - r["t_submit"],
+                          "service": r["t_done"] - r["t_admit"], "terms": r["terms"],
                           "pairs": r["n_pairs"], "mismatch": r["n_mismatch"],
                           "exact": got == want and r["status"] == 0, "status": r["status"],
                           "t_submit": r["t_submit"], "t_done": r["t_done"],
@@ -244,31 +245,68 @@ def run_stream(server: Server, pool, rate: float, n_requests: int, seed: int = 0
     return records
 
 
-def summarize(records):
+def _pct(v, q):
+    return float(np.percentile(v, q) * 1e3) if len(v) else 0.0
+
+
+def summarize(records, alone=None):
+    """Latency percentiles beside throughput.  With `alone` (each scene's
+    service time when it runs by itself), also the slowdown of every request
+    (latency / alone) and, per size class of that alone time, the split of
+    latency into queueing (submit to admission) and service (admission to
+    results on the host)."""
     lat = np.array([r["latency"] for r in records])
     terms = np.array([r["terms"] for r in records])
     span = max(r["t_done"] for r in records) - min(r["t_submit"] for r in records)
-    return {"requests": len(records), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "queue_p50_ms": float(np.percentile([r["queue"] for r in records], 50) * 1e3),
-            "throughput_req_s": len(records) / span, "terms_per_s": float(terms.sum() / span),
-            "exact": int(sum(r["exact"] for r in records)),
-            "refits": int(sum(r["refits"] for r in records)), "span_s": span}
+    out = {"requests": len(records), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+           "mean_ms": float(lat.mean() * 1e3),
+           "queue_p50_ms": _pct([r["queue"] for r in records], 50),
+           "queue_p99_ms": _pct([r["queue"] for r in records], 99),
+           "throughput_req_s": len(records) / span, "terms_per_s": float(terms.sum() / span),
+           "exact": int(sum(r["exact"] for r in records)),
+           "refits": int(sum(r["refits"] for r in records)), "span_s": span}
+    if alone is not None:
+        slow = np.array([r["latency"] / alone[r["scene"]] for r in records])
+        out["slowdown_p50"] = float(np.percentile(slow, 50))
+        out["slowdown_p99"] = float(np.percentile(slow, 99))
+        classes = {}
+        for name, lo, hi in (("alone<10ms", 0.0, 0.01), ("alone 10-100ms", 0.01, 0.1),
+                             ("alone>=100ms", 0.1, np.inf)):
+            rs = [r for r in records if lo <= alone[r["scene"]] < hi]
+            if not rs:
+                continue
+            classes[name] = {
+                "requests": len(rs),
+                "latency_p50_ms": _pct([r["latency"] for r in rs], 50),
+                "latency_p99_ms": _pct([r["latency"] for r in rs], 99),
+                "queue_p50_ms": _pct([r["queue"] for r in rs], 50),
+                "queue_p99_ms": _pct([r["queue"] for r in rs], 99),
+                "service_p50_ms": _pct([r["service"] for r in rs], 50),
+                "service_p99_ms": _pct([r["service"] for r in rs], 99),
+            }
+        out["by_class"] = classes
+    return out
 
 
-def capacity(server: Server, pool) -> float:
-    """Requests per second the server sustains when each pool entry is run
-    alone, back to back (the service rate the offered load is scaled to)."""
+def service_times(server: Server, pool) -> list:
+    """Each pool entry's service time (admission to results on the host)
+    when it runs alone on the server."""
     import torch
-    total = 0.0
+    out = []
     for e in pool:
         b = e["base"]
         sid = server.open_session(b.offsets, b.exp_pairs, b.exp_lk)
         x = torch.from_numpy(e["steps"][0][0]).cuda()
         r = server.wait(server.submit(sid, x))
-        total += r["t_done"] - r["t_admit"]
+        out.append(r["t_done"] - r["t_admit"])
         server.close_session(sid)
-    return len(pool) / total
+    return out
+
+
+def capacity(server: Server, pool) -> float:
+    """Requests per second the server sustains when each pool entry is run
+    alone, back to back (the service rate the offered load is scaled to)."""
+    return len(pool) / sum(service_times(server, pool))
 
 
 def main():

@@ -454,9 +454,39 @@ def pin_bh_estimate():
     return None
 
 
+def pin_verify():
+    """The comparison of Sec. 3.1 against its definition written out over the
+    union of keys (a pair missing on one side is 0 there), on seeded sparse
+    matrices and on the cases where one side is empty."""
+    rng = np.random.default_rng(17)
+    for trial in range(20):
+        keys = np.unique(rng.integers(0, 60, size=(120, 2)), axis=0)
+        keys = keys[keys[:, 0] < keys[:, 1]]
+        vals = rng.integers(-2, 3, size=len(keys)).astype(np.int32)
+        cur = rng.uniform(size=len(keys)) < 0.7
+        exp = rng.uniform(size=len(keys)) < 0.7
+        ev = vals.copy()
+        ev[rng.uniform(size=len(ev)) < 0.15] += 1
+        cases = [(keys[cur], vals[cur], keys[exp], ev[exp])]
+        if trial == 0:
+            cases += [(keys[:0], vals[:0], keys[exp], ev[exp]),
+                      (keys[cur], vals[cur], keys[:0], vals[:0]),
+                      (keys[exp], ev[exp], keys[exp], ev[exp])]
+        for cp, cv, ep, evv in cases:
+            a = {tuple(k): v for k, v in zip(cp.tolist(), cv.tolist())}
+            b = {tuple(k): v for k, v in zip(ep.tolist(), evv.tolist())}
+            want = [[k[0], k[1], a.get(k, 0), b.get(k, 0)] for k in sorted(set(a) | set(b))
+                    if a.get(k, 0) != b.get(k, 0)]
+            got = oracle.verify(cp, cv, ep, evv).tolist()
+            if got != want:
+                return "verify: %d records, want %d" % (len(got), len(want))
+    return None
+
+
 def run_pins():
     fails = []
     for f in (pin_segment_terms, pin_hopf, pin_torus, pin_crossings, pin_integer_and_refinement,
+              pin_verify,
               pin_bh_exact_limit, pin_bh_segment_moments, pin_bh_shift_rule,
               pin_bh_expansion_order, pin_bh_accuracy, pin_bh_estimate, pin_dz_on_curve,
               pin_dz_separated,
@@ -628,14 +658,15 @@ def test_loop_flags():
     assert f[1] & oracle.FLAG_NONFINITE
 
 
-@pytest.mark.parametrize("mutation", list(range(1, 14)))
+@pytest.mark.parametrize("mutation", list(range(1, 15)))
 def test_planted_mistakes_are_caught(mutation):
     """A dropped term, a wrong sign, a wrong index, a transposed operand, an
     open loop, a wrong normalisation, a wrong sign of the Barnes-Hut dipole
     term, a dropped part of the segment quadrupole moment, a discretization
     that refines only one loop of a pair, a wrong de Casteljau midpoint, a
-    wrong B-spline end point, halves out of order or a dropped term of the
-    Barnes-Hut error estimate each break at least one pin."""
+    wrong B-spline end point, halves out of order, a dropped term of the
+    Barnes-Hut error estimate or a comparison that ignores pairs whose boxes
+    separated each break at least one pin."""
     oracle.set_mutation(mutation)
     try:
         fails = run_pins()

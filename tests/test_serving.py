@@ -4,6 +4,7 @@ request reports exactly its pulled-through pairs."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2106_12655_amd import serve
 
 pytestmark = pytest.mark.gpu
@@ -42,6 +43,10 @@ def test_alone_equals_mix():
         changed = {tuple(x) for x in pool[j[0]]["steps"][j[1]][1].tolist()}
         assert {(r[0], r[1]) for r in m["mismatches"].tolist()} == changed
         assert len(changed) > 0
+        # the server's comparison against the oracle's, on the request's own matrix
+        b = pool[j[0]]["base"]
+        assert m["mismatches"].tolist() == oracle.verify(m["pairs"], m["lk"], b.exp_pairs,
+                                                         b.exp_lk).tolist()
     starts = sorted((mix[j]["t_admit"], mix[j]["t_done"]) for j in jobs)
     for a, b in zip(starts, starts[1:]):
         overlap += b[0] < a[1]
