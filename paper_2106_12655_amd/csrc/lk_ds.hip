@@ -203,14 +203,13 @@ struct Frame {
 
 // The R consecutive segments of loop B owned by a lane: vertices k_0..k_R,
 // segment vectors s_r = k_{r+1} - k_r and the constants s_r x (k_r - k_0) of
-// the numerator p.  Segments past the end of the item are evaluated on
-// repeated vertices and masked out.
+// the numerator p.  Segments past the end of the item have zero length
+// (repeated vertices) and add exactly 0.
 template <typename T, int R>
 struct Segs {
   V3<T> k[R + 1];
   V3<T> s[R];
   V3<T> m[R];
-  bool valid[R];
 };
 
 // Walk state at vertex l_j of loop A, for all R + 1 vertices of the lane:
@@ -292,16 +291,10 @@ __device__ __forceinline__ T walk_step(Walk<T, R>& w, const V3<T>& l1, const Seg
 #pragma unroll
     for (int r = 0; r < R; ++r) inv[r] = __builtin_amdgcn_rcpf(mx[r]);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const T th = atan2_reduced(Y[r], X[r], mn[r] * inv[r]);
-      sum += g.valid[r] ? th : (T)0;
-    }
+    for (int r = 0; r < R; ++r) sum += atan2_reduced(Y[r], X[r], mn[r] * inv[r]);
   } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const T th = angle<T, AT>(Y[r], X[r]);
-      sum += g.valid[r] ? th : (T)0;
-    }
+    for (int r = 0; r < R; ++r) sum += angle<T, AT>(Y[r], X[r]);
   }
   w.l = l1;
 #pragma unroll
@@ -347,31 +340,32 @@ __device__ __forceinline__ Layout layout(const WorkRec& r, int64_t local, int ch
   return L;
 }
 
-// Vertex k_{b0 + bi R + r} of loop B for r = 0..R (cyclic; padding lanes
-// repeat the last vertex and are masked by Segs::valid).
+// Vertex k_{b0 + bi R + r} of loop B for r = 0..R (cyclic).  Past the end
+// of the block the lane repeats the block's end vertex, so its padding
+// segments have zero length: their Eq. 4 term is exactly 0 (p = 0 and
+// d1 d2 > 0 unless a vertex of loop A sits on that vertex, which only
+// touching loops do), and the sum needs no mask.  The crossing count still
+// masks them (Segs::valid), since a zero-length segment has no certain side.
 template <typename Tin, typename Tc, int R>
 __device__ __forceinline__ void load_b(const Tin* X, const WorkRec& w, const Layout& L,
                                        const Frame<Tin, Tc>& F, V3<Tc>* k) {
   const int first = L.bi * R;
 #pragma unroll
   for (int r = 0; r <= R; ++r) {
-    int64_t i = L.b0 + first + r;
+    int64_t i = L.b0 + (first + r < L.nbh ? first + r : L.nbh);
     if (i >= w.nb) i -= w.nb;
-    if (i >= w.nb) i = w.nb - 1;
     k[r] = F.load(X, w.ob + i);
   }
 }
 
 template <typename Tc, int R>
-__device__ __forceinline__ void make_segs(const V3<Tc>* k, const Layout& L, Segs<Tc, R>& sg) {
-  const int first = L.bi * R;
+__device__ __forceinline__ void make_segs(const V3<Tc>* k, Segs<Tc, R>& sg) {
 #pragma unroll
   for (int r = 0; r <= R; ++r) sg.k[r] = k[r];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     sg.s[r] = sg.k[r + 1] - sg.k[r];
     sg.m[r] = cross(sg.s[r], sg.k[r] - sg.k[0]);
-    sg.valid[r] = first + r < L.nbh;
   }
 }
 
@@ -627,7 +621,7 @@ struct LaneOf<Tc, kCrossings, R> {
 template <typename Tc, int R>
 __device__ __forceinline__ void make_lane(const V3<Tc>* k, const Layout& L, const DsArgs&,
                                           Segs<Tc, R>& sg) {
-  make_segs<Tc, R>(k, L, sg);
+  make_segs<Tc, R>(k, sg);
 }
 
 // Scale from the lane sums to the pair's value: 1 / (2 pi) for the direct
@@ -679,20 +673,21 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   const int64_t n_small = A.s.counts[0];
   const int64_t total = big_total + (n_small + A.batch - 1) / A.batch;
 
-  // the next work index is fetched one item ahead so the atomic's latency
-  // overlaps the current item's arithmetic; a fused check's stop flag is read
-  // with it (device-scope load, so another wave's store is seen)
-  unsigned long long wnext = 0;
+  // A wave's first work index is its workgroup index, so a launch with fewer
+  // items than waves costs no atomic at all; later indices come from the
+  // device counter, offset by the grid.  The next index is fetched one item
+  // ahead so the atomic's latency overlaps the current item's arithmetic; a
+  // fused check's stop flag is read with it (device-scope load, so another
+  // wave's store is seen).
+  unsigned long long wnext = blockIdx.x;
   int stopnext = 0;
-  if (lane == 0) {
-    wnext = atomicAdd(A.s.counter, 1ull);
-    if (A.out.stop) stopnext = __hip_atomic_load(A.out.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (lane == 0 && A.out.stop)
+    stopnext = __hip_atomic_load(A.out.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
     const int64_t w = (int64_t)__shfl(wnext, 0);
     if (w >= total || __shfl(stopnext, 0)) break;
     if (lane == 0) {
-      wnext = atomicAdd(A.s.counter, 1ull);
+      wnext = gridDim.x + atomicAdd(A.s.counter, 1ull);
       if (A.out.stop)
         stopnext = __hip_atomic_load(A.out.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -876,7 +871,6 @@ __global__ __launch_bounds__(kWave) void bh_near_k(BhArgs A) {
         for (int r = 0; r < R; ++r) {
           sg.s[r] = sg.k[r + 1] - sg.k[r];
           sg.m[r] = cross(sg.s[r], sg.k[r] - sg.k[0]);
-          sg.valid[r] = first + r < mb;
         }
       }
       __syncthreads();
