@@ -70,7 +70,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 # a recorded launch configuration: anything else reports traffic as null.
 TRAFFIC = {
     ("chainmail", "mixed"): {
-        "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4EEEvNS_6DsArgsE",
+        "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4ELb1EEEvNS_6DsArgsE",
         "isa": "f19f906333a9a1db",
         "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "atan_form": 2},
         "fetch_scale": 2.000, "write_scale": 1.000,

@@ -345,26 +345,31 @@ __device__ void schedule(const Sched& S, int32_t* zero_next) {
 __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo li, Sched S,
                                                int refit) {
   // xi = mean |coordinate|: every block reduces the preparation kernel's
-  // partials in the same fixed order (cheaper than another launch)
+  // partials in the same fixed order (cheaper than another launch); a refit
+  // pass validates nothing and skips it
   __shared__ double red[1024];
-  double part = 0.0;
-  for (int k = threadIdx.x; k < li.n_part; k += 1024) part += li.part[k];
-  red[threadIdx.x] = part;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  double xi = 0.0;
+  if (!refit) {
+    double part = 0.0;
+    for (int k = threadIdx.x; k < li.n_part; k += 1024) part += li.part[k];
+    red[threadIdx.x] = part;
     __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    const int64_t nv = A.off[L] - A.off[0];
+    xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
   }
-  const int64_t nv = A.off[L] - A.off[0];
-  const double xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
   int64_t n = A.n_list;
   if (A.n_list_dev) {
     const int64_t nd = *A.n_list_dev;
     n = nd < n ? nd : n;
   }
-  // grid stride with the same trip count in every thread (the appends below
-  // are workgroup-collective)
-  for (int64_t base = (int64_t)blockIdx.x * 1024; base < A.n_list;
+  // grid stride over the list's length on the device (the same in every
+  // thread: the appends below are workgroup-collective), so an empty refit
+  // list costs each workgroup one load
+  for (int64_t base = (int64_t)blockIdx.x * 1024; base < n;
        base += (int64_t)gridDim.x * 1024) {
     const int64_t q = base + threadIdx.x;
     bool small = false, big = false;
@@ -963,13 +968,16 @@ hipError_t launch_cc_boxes(const void* xyz, bool in_f64, const int64_t* off, int
 
 hipError_t launch_plan(const PlanArgs& a, int32_t n_loops, const LoopInfo& li, const Sched& sc,
                        bool refit, hipStream_t s) {
-  plan_k<<<blocks_for(a.n_list, 1024, 8192), 1024, 0, s>>>(a, n_loops, li, sc, refit ? 1 : 0);
+  // a refit list is short (pairs far from an integer): a few workgroups
+  plan_k<<<blocks_for(a.n_list, 1024, refit ? 16 : 8192), 1024, 0, s>>>(a, n_loops, li, sc,
+                                                                       refit ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize_split(const Sched& sc, const unsigned long long* acc, const Outs& o,
                                  int64_t n_pairs, hipStream_t s) {
-  finalize_split_k<<<blocks_for(n_pairs, 256, 1024), 256, 0, s>>>(sc, acc, o);
+  // only multi-item pairs remain, at most a few thousand: grid stride
+  finalize_split_k<<<blocks_for(n_pairs, 256, 64), 256, 0, s>>>(sc, acc, o);
   return hipGetLastError();
 }
 

@@ -662,7 +662,10 @@ __device__ __forceinline__ void finish_item(double acc, int32_t p, int lane, con
 // test checks the compiled register counts.  No occupancy attribute is set:
 // capping the compiler's register budget made it spread the transcendental
 // instructions through the loop, which measured slower.
-template <typename Tin, typename Tc, int AT, int R>
+// PK: R small pairs whose loop B fits one wave's lanes share a wave (the
+// throughput layout); without it every small pair gets a whole wave of its
+// own, which shortens each lane's walk (the layout for calls with few pairs).
+template <typename Tin, typename Tc, int AT, int R, bool PK = true>
 __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Vtx<Tc>* lds = reinterpret_cast<Vtx<Tc>*>(lds_raw);
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
       const int cnt = (int)((n_small - m0) < A.batch ? (n_small - m0) : A.batch);
       const WorkRec* recs = A.s.small + m0;
       const int32_t nb_l = lane < cnt ? recs[lane].nb : 0;
-      const unsigned long long pmask = __ballot(R > 1 && lane < cnt && nb_l <= kWave);
+      const unsigned long long pmask = __ballot(PK && R > 1 && lane < cnt && nb_l <= kWave);
       unsigned long long smask = __ballot(lane < cnt) & ~pmask;
       const int npk = __popcll(pmask);
       if (npk > 0) {
@@ -922,20 +925,27 @@ size_t lds_bytes(int tile) {
   return (size_t)n * sizeof(Vtx<Tc>);
 }
 
-template <typename Tin, typename Tc, int AT, int R>
+template <typename Tin, typename Tc, int AT, int R, bool PK>
 hipError_t launch_t(const DsArgs& a, int grid, hipStream_t s) {
   const size_t shm = lds_bytes<Tc, R>(a.tile);
-  ds_persistent<Tin, Tc, AT, R><<<dim3(grid), dim3(kWave), shm, s>>>(a);
+  if constexpr (PK)
+    ds_persistent<Tin, Tc, AT, R><<<dim3(grid), dim3(kWave), shm, s>>>(a);
+  else
+    ds_persistent<Tin, Tc, AT, R, false><<<dim3(grid), dim3(kWave), shm, s>>>(a);
   return hipGetLastError();
 }
 
-template <typename Tin, typename Tc, int AT, int R>
+template <typename Tin, typename Tc, int AT, int R, bool PK>
 int grid_t(int tile, int n_cu, int waves_per_cu) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT, R>, kWave,
-                                                   lds_bytes<Tc, R>(tile)) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  hipError_t e;
+  if constexpr (PK)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT, R>, kWave,
+                                                     lds_bytes<Tc, R>(tile));
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ds_persistent<Tin, Tc, AT, R, false>,
+                                                     kWave, lds_bytes<Tc, R>(tile));
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   if (waves_per_cu > 0 && waves_per_cu < per_cu) per_cu = waves_per_cu;
   return per_cu * n_cu;
 }
@@ -946,12 +956,31 @@ struct Variant {
   int (*grid)(int, int, int);
 };
 
-template <typename Tin, typename Tc, int AT, int R>
+template <typename Tin, typename Tc, int AT, int R, bool PK = true>
 constexpr Variant variant() {
-  return Variant{launch_t<Tin, Tc, AT, R>, grid_t<Tin, Tc, AT, R>};
+  return Variant{launch_t<Tin, Tc, AT, R, PK>, grid_t<Tin, Tc, AT, R, PK>};
 }
 
-Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs) {
+// Unpacked layout for calls with few pairs: the direct-sum forms only (the
+// FP32 arctangent forms 0 and 2 give the same values, so both map to 2;
+// with R = 1 nothing is packed anyway).
+bool pick_unpacked(bool in_f64, bool compute_f64, int atan_form, int segs, Variant* v) {
+  if (atan_form == kCrossings || segs < 2) return false;
+  if (compute_f64) {
+    *v = in_f64 ? variant<double, double, 0, 2, false>() : variant<float, double, 0, 2, false>();
+    return true;
+  }
+  if (atan_form == 1) return false;
+  if (segs >= 4)
+    *v = in_f64 ? variant<double, float, 2, 4, false>() : variant<float, float, 2, 4, false>();
+  else
+    *v = in_f64 ? variant<double, float, 2, 2, false>() : variant<float, float, 2, 2, false>();
+  return true;
+}
+
+Variant pick(bool in_f64, bool compute_f64, int atan_form, int segs, bool unpacked = false) {
+  Variant u;
+  if (unpacked && pick_unpacked(in_f64, compute_f64, atan_form, segs, &u)) return u;
   if (compute_f64 && atan_form == kCrossings) {
     constexpr int C = kCrossings;
     if (segs >= 2) return in_f64 ? variant<double, double, C, 2>() : variant<float, double, C, 2>();
@@ -1000,13 +1029,13 @@ hipError_t launch_bh_near(const BhArgs& a, bool in_f64, hipStream_t s) {
 }
 
 hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,
-                             int segs, int grid, hipStream_t s) {
-  return pick(in_f64, compute_f64, atan_form, segs).launch(a, grid, s);
+                             int segs, int grid, hipStream_t s, bool unpacked) {
+  return pick(in_f64, compute_f64, atan_form, segs, unpacked).launch(a, grid, s);
 }
 
 int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int segs, int tile, int n_cu,
-                    int waves_per_cu) {
-  return pick(in_f64, compute_f64, atan_form, segs).grid(tile, n_cu, waves_per_cu);
+                    int waves_per_cu, bool unpacked) {
+  return pick(in_f64, compute_f64, atan_form, segs, unpacked).grid(tile, n_cu, waves_per_cu);
 }
 
 }  // namespace lk

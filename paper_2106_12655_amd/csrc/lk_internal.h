@@ -318,11 +318,13 @@ hipError_t launch_bh_adapt(const BhArgs& a, int64_t n_pairs, double target, doub
 // form (FP32 only): 0 / 2 = own minimax arctangent (phased / inline), 1 = HIP
 // atan2f, 3 = crossing count instead of the Eq. 4 sum; segs: segments of loop
 // B per lane (register blocking; rounded down to a built variant).
+// unpacked: every small pair on a whole wave (the layout for calls with few
+// pairs; the crossing count and R = 1 ignore it).
 hipError_t launch_direct_sum(const DsArgs& a, bool in_f64, bool compute_f64, int atan_form,
-                             int segs, int grid, hipStream_t s);
+                             int segs, int grid, hipStream_t s, bool unpacked = false);
 // Largest co-resident grid for the persistent kernel on this device.
 int direct_sum_grid(bool in_f64, bool compute_f64, int atan_form, int segs, int tile, int n_cu,
-                    int waves_per_cu);
+                    int waves_per_cu, bool unpacked = false);
 // Segments per lane of the variant that `segs` selects (the crossing count
 // also has 8).
 int segs_supported(bool compute_f64, int segs, bool crossings = false);

@@ -176,6 +176,7 @@ struct Plan {
   int tile, chunk, grid, grid64, grid_refit, atan_form;
   int segs, segs64;  // segments of loop B per lane, FP32 and FP64 kernels
   int grid_cc64;     // CROSSINGS: grid of the FP64 crossing count
+  bool unpacked;     // few pairs: every small pair on a whole wave
 };
 
 constexpr int kDefaultSegs32 = 4;
@@ -383,6 +384,17 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
   A.batch = ctx->opt_batch ? ctx->opt_batch : kDefaultBatch;
   // R small pairs share a wave in the FP32 kernel: a batch below R idles lanes
   if (P.mixed && A.batch < P.segs) A.batch = P.segs;
+  // A call with few pairs is latency-bound: unpacked, one pair per work
+  // item; up to R pairs per persistent wave, one packed round per item.
+  // Either way the pairs spread over the most waves.  (The batch only groups
+  // pairs; a pair's lane layout, and so its value, does not depend on it.)
+  if (P.unpacked) {
+    A.batch = 1;
+  } else {
+    const int waves = P.mixed ? P.grid : P.grid64;
+    const int r = P.mixed ? P.segs : P.segs64;
+    if (n_pairs <= (int64_t)waves * r && A.batch > r) A.batch = r;
+  }
   A.view[0] = ctx->view[0];
   A.view[1] = ctx->view[1];
   A.view[2] = ctx->view[2];
@@ -471,7 +483,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
     LK_HIP(launch_sched(A.s, W.at<int32_t>(kMetaCountsRefit), s));
     if (timed) LK_HIP(hipEventRecord(ev[0], s));
     LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
-                             P.mixed ? P.grid : P.grid64, s));
+                             P.mixed ? P.grid : P.grid64, s, P.unpacked));
     if (timed) LK_HIP(hipEventRecord(ev[1], s));
     LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
   }
@@ -508,7 +520,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
     // the FP64 crossing count gets the whole grid: its pairs are the ones
     // with shallow crossings, often the largest
     LK_HIP(launch_direct_sum(B, P.in_f64, true, P.crossings ? kFormCrossings : 0, P.segs64,
-                             P.crossings ? P.grid_cc64 : P.grid_refit, s));
+                             P.crossings ? P.grid_cc64 : P.grid_refit, s, P.unpacked));
     if (timed) LK_HIP(hipEventRecord(ev[3], s));
     LK_HIP(launch_finalize_split(B.s, acc, ro, n_pairs, s));
     if (P.crossings) {
@@ -528,7 +540,7 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
       B2.out = r2;
       LK_HIP(launch_plan(R2, n_loops, li, B2.s, true, s));
       LK_HIP(launch_sched(B2.s, nullptr, s));
-      LK_HIP(launch_direct_sum(B2, P.in_f64, true, 0, P.segs64, P.grid_refit, s));
+      LK_HIP(launch_direct_sum(B2, P.in_f64, true, 0, P.segs64, P.grid_refit, s, P.unpacked));
       LK_HIP(launch_finalize_split(B2.s, acc, r2, n_pairs, s));
     }
   }
@@ -536,9 +548,18 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
 }
 
 // Kernel configuration of a call from the context's options (0 = default).
-Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
+// Up to two pairs per compute unit a call is latency-bound: every small pair
+// then gets a whole wave (64 lanes, so each walks a quarter or less of loop
+// A) instead of sharing one with R - 1 others.  The choice depends only on
+// the pair count and the device, and both passes of a call make it, so a
+// pair's lane layout, and with it its value, is the same in the plain mode
+// and in a refit.
+bool few_pairs(const lk_ctx* ctx, int64_t n_pairs) { return n_pairs <= 2 * (int64_t)ctx->n_cu; }
+
+Plan make_plan(lk_ctx* ctx, bool in_f64, int mode, int64_t n_pairs) {
   const bool mixed = mode != LK_PLAIN_F64;
   Plan P;
+  P.unpacked = few_pairs(ctx, n_pairs);
   P.in_f64 = in_f64;
   P.mixed = mixed;
   P.crossings = mode == LK_CROSSINGS;
@@ -551,9 +572,9 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, int mode) {
   P.segs = lk::segs_supported(false, ctx->opt_segs ? ctx->opt_segs : kDefaultSegs32, P.crossings);
   P.segs64 = lk::segs_supported(true, ctx->opt_segs64 ? ctx->opt_segs64 : kDefaultSegs64);
   P.grid = lk::direct_sum_grid(in_f64, false, P.atan_form, P.segs, P.tile, ctx->n_cu,
-                               ctx->opt_waves);
+                               ctx->opt_waves, P.unpacked);
   P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, mixed ? default_tile(true) : P.tile,
-                                 ctx->n_cu, ctx->opt_waves);
+                                 ctx->n_cu, ctx->opt_waves, P.unpacked);
   // refits are rare: a small persistent grid keeps the empty refit pass cheap
   P.grid_refit = ctx->n_cu < P.grid64 ? ctx->n_cu : P.grid64;
   P.grid_cc64 = P.crossings ? lk::direct_sum_grid(in_f64, true, kFormCrossings, P.segs64,
@@ -919,7 +940,7 @@ lk_status direct_sum_enqueue(lk_ctx* ctx, const void* xyz, int dtype, const int6
 
   const bool in_f64 = dtype == LK_F64;
   const bool mixed = mode != LK_PLAIN_F64;
-  const Plan P = make_plan(ctx, in_f64, mode);
+  const Plan P = make_plan(ctx, in_f64, mode, n_pairs);
   if ((st = ensure_workspace(ctx, n_loops, n_pairs)) != LK_OK) return st;
   if (P.crossings || P.bh) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1091,7 +1112,7 @@ lk_status lk_direct_sum_noalloc(lk_ctx* ctx, const void* xyz, int dtype, const i
   if (!flags) flags = (uint32_t*)(base + y.flags);
 
   const bool mixed = mode == LK_MIXED;
-  const Plan P = make_plan(ctx, dtype == LK_F64, mode);
+  const Plan P = make_plan(ctx, dtype == LK_F64, mode, n_pairs);
   ctx->stats.tile_a = P.tile;
   ctx->stats.chunk_a = P.chunk;
   ctx->stats.waves_per_cu = (mixed ? P.grid : P.grid64) / (ctx->n_cu > 0 ? ctx->n_cu : 1);
@@ -1534,7 +1555,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   int evaluated = 0;
   auto measure = [&](const lk_tuning& t, double* ms) -> lk_status {
     apply(t);
-    const Plan P = make_plan(ctx, in_f64, mode);
+    const Plan P = make_plan(ctx, in_f64, mode, n_pairs);
     double best = 1e30;
     int reps = 3;
     for (int r = 0; r <= reps; ++r) {
@@ -1613,7 +1634,7 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
   apply(cur);
   // leave the outputs as a valid result of the chosen configuration
   {
-    const Plan P = make_plan(ctx, in_f64, mode);
+    const Plan P = make_plan(ctx, in_f64, mode, n_pairs);
     if ((st = enqueue_direct_sum(ctx, ctx_ws(ctx), P, xyz, off, n_loops, pairs, n_pairs, lk_real, lk_int,
                                  flags, s, nullptr)) != LK_OK)
       return st;

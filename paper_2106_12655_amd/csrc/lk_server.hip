@@ -41,6 +41,13 @@
 namespace {
 
 constexpr double kBigTerms = 1.0e9;  // requests above this many terms count as large
+// A large request's direct sum runs as consecutive calls over runs of its
+// pair list of at most this many terms (a few milliseconds of the device
+// each): between two of them the other slots' kernels get the compute units,
+// so a small request never waits for a whole large one.  A pair's value does
+// not depend on the run it is in (its lane layout depends only on its own
+// sizes and the run's pair count, which depends only on the request).
+constexpr double kRunTerms = 2.0e9;
 
 struct Session {
   int32_t n_loops = 0;
@@ -239,16 +246,27 @@ void run_request(lk_server* srv, lk_server::Slot& slot, Request& R, const Sessio
     }
     res.terms = terms;
     if (s == LK_OK) s = lk_set_option(ctx, LK_OPT_WAVES_PER_CU, terms >= kBigTerms ? 12 : 4);
-    if (s == LK_OK)
-      s = lk_direct_sum(ctx, xyz, R.dtype, S.d_off, S.n_loops, d_pairs, n, srv->mode, d_real, d_lk,
-                        d_flags, st);
+    // runs of at most kRunTerms terms (a single larger pair is a run alone)
+    int64_t q0 = 0;
+    while (s == LK_OK && q0 < n) {
+      int64_t q1 = q0;
+      double run = 0.0;
+      while (q1 < n) {
+        const int32_t i = R.pairs[2 * q1], j = R.pairs[2 * q1 + 1];
+        const double t = (double)(S.off[i + 1] - S.off[i]) * (double)(S.off[j + 1] - S.off[j]);
+        if (q1 > q0 && run + t > kRunTerms) break;
+        run += t;
+        ++q1;
+      }
+      s = lk_direct_sum(ctx, xyz, R.dtype, S.d_off, S.n_loops, d_pairs + 2 * q0, q1 - q0,
+                        srv->mode, d_real + q0, d_lk + q0, d_flags + q0, st);
+      q0 = q1;
+    }
   }
   if (s == LK_OK)
     s = lk_verify(ctx, d_pairs, d_lk, n, S.d_exp_pairs, S.d_exp_lk, S.n_exp, 0, &n_mis, d_mism,
                   cap_m, st);
   if (s == LK_OK && n > 0) {
-    lk_stats stats;
-    if (lk_get_stats(ctx, &stats) == LK_OK) res.refits = stats.refits;
     if (hipMemcpyAsync(R.lk.data(), d_lk, 4 * (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipMemcpyAsync(R.real.data(), d_real, 8 * (size_t)n, hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
@@ -265,9 +283,12 @@ void run_request(lk_server* srv, lk_server::Slot& slot, Request& R, const Sessio
   if (hipStreamSynchronize(st) != hipSuccess && s == LK_OK) s = LK_EDEVICE;
   hipFreeAsync(buf, st);
   if (xyz_copy) hipFreeAsync(xyz_copy, st);
-  int64_t flagged = 0;
-  for (uint32_t f : flags)
+  int64_t flagged = 0, refits = 0;
+  for (uint32_t f : flags) {
     if (f & (LK_FLAG_NONFINITE | LK_FLAG_BADPAIR | LK_FLAG_BADLOOP | LK_FLAG_AMBIGUOUS)) ++flagged;
+    if (f & LK_FLAG_REFIT) ++refits;
+  }
+  res.refits = refits;
   res.n_pairs = n;
   res.n_mismatch = n_mis;
   res.n_flagged = flagged;
