@@ -42,12 +42,12 @@ namespace {
 
 constexpr double kBigTerms = 1.0e9;  // requests above this many terms count as large
 // A large request's direct sum runs as consecutive calls over runs of its
-// pair list of at most this many terms (a few milliseconds of the device
-// each): between two of them the other slots' kernels get the compute units,
+// pair list of at most this many terms (about 11 ms of the device each):
+// between two of them the other slots' kernels get the compute units,
 // so a small request never waits for a whole large one.  A pair's value does
 // not depend on the run it is in (its lane layout depends only on its own
 // sizes and the run's pair count, which depends only on the request).
-constexpr double kRunTerms = 2.0e9;
+constexpr double kRunTerms = 1.0e10;
 
 struct Session {
   int32_t n_loops = 0;
