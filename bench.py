@@ -62,23 +62,23 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 
 # HBM bytes per launch of the direct-sum kernel, from two rocprofv3 --pmc runs
 # of the chainmail command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
-# averaged over the timed dispatches), each scaled by what the same counter read
-# for one 256 MiB device copy in that run (fetch x2.000, write x1.000), for each
-# of the launch configurations the autotuner picks on this workload.  A record
-# only holds for the machine code it was taken on (the fingerprint of the
-# kernel's gfx950 assembly that the build writes to liblk.kernels.json) and for
-# a recorded launch configuration: anything else reports traffic as null.
+# averaged over the kernel's dispatches), each scaled by what the same counter
+# read for one 256 MiB elementwise copy in that run (fetch x2.000, write
+# x1.000), for the launch configuration the autotuner picked.  A record only
+# holds for the machine code it was taken on (the fingerprint of the kernel's
+# gfx950 assembly that the build writes to liblk.kernels.json) and for its
+# launch configuration: anything else reports traffic as null.
 TRAFFIC = {
     ("chainmail", "mixed"): {
         "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4ELb1EEEvNS_6DsArgsE",
-        "isa": "f19f906333a9a1db",
+        "isa": "692da477f89576ca",
         "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "atan_form": 2},
         "fetch_scale": 2.000, "write_scale": 1.000,
         # (effective small batch, waves_per_cu) -> (FETCH_SIZE, WRITE_SIZE) KiB
         # per launch.  The runtime raises a batch below segs_per_lane to it,
-        # so batches 2 and 4 launch the same work here; each entry is the
-        # mean of the runs at batch 2 and at batch 4.
-        "by_launch": {(4, 0): (21755.1, 2503.7), (4, 12): (21827.1, 2503.8)},
+        # so batches 1, 2 and 4 launch the same work here.
+        "by_launch": {(4, 12): (23848.7, 2550.6)},
+        "source": "profiles/ds_persistent_chainmail_hbm_traffic.txt",
     },
 }
 
@@ -240,13 +240,15 @@ def main():
     stream = torch.cuda.Stream()  # a real stream: the null stream cannot be captured
     torch.cuda.set_stream(stream)
     if args.copy_probe_mib > 0:
-        # one plain copy kernel that reads and writes exactly this many bytes, so
-        # that profiler byte counters can be scaled against a known transfer
+        # one plain elementwise kernel that reads and writes exactly this many
+        # bytes (dst = src * 1; a same-type copy_ would go to the DMA engine,
+        # which the kernel counters do not see), so that profiler byte
+        # counters can be scaled against a known transfer
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     ctx = lk.Context(0)
@@ -340,6 +342,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": measured_traffic(args.config, args.mode, tuned),
+                     "traffic_source": (TRAFFIC[(args.config, args.mode)]["source"]
+                                        if measured_traffic(args.config, args.mode, tuned)
+                                        is not None else None),
                      "kernel": "ds_persistent (%s)" % ("FP64" if fp64 else (
                          "FP32 crossing count" if args.mode == "crossings" else "FP32 terms")),
                      "kernel_ms": res["kernel_ms"], "flop_per_term": fpt},
