@@ -77,7 +77,9 @@ TRAFFIC = {
         # (effective small batch, waves_per_cu) -> (FETCH_SIZE, WRITE_SIZE) KiB
         # per launch.  The runtime raises a batch below segs_per_lane to it,
         # so batches 1, 2 and 4 launch the same work here.
-        "by_launch": {(4, 12): (23848.7, 2550.6)},
+        "by_launch": {(4, 0): (23995.6, 2564.7), (4, 8): (23970.4, 2585.4),
+                      (4, 12): (23848.7, 2550.6), (8, 0): (21291.8, 1968.0),
+                      (8, 12): (21426.1, 1965.2)},
         "source": "profiles/ds_persistent_chainmail_hbm_traffic.txt",
     },
 }
