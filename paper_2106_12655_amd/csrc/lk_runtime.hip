@@ -1625,6 +1625,16 @@ lk_status lk_autotune(lk_ctx* ctx, const void* xyz, int dtype, const int64_t* of
     } else if ((st = sweep(&lk_tuning::chunk_a, {1024, 2048, 4096, 8192, 16384})) != LK_OK) {
       return st;
     }
+    if (mixed && !crossings) {
+      // the arctangent form was chosen at the starting chunk; the best form
+      // can change with the chunk (big pairs walk longer per item), so it is
+      // swept again, and the chunk with it when the form changes
+      const int32_t form = cur.atan_form;
+      if ((st = sweep(&lk_tuning::atan_form, {0, 2})) != LK_OK) return st;
+      if (cur.atan_form != form &&
+          (st = sweep(&lk_tuning::chunk_a, {1024, 2048, 4096, 8192, 16384})) != LK_OK)
+        return st;
+    }
   }
   if ((st = sweep(&lk_tuning::waves_per_cu, {0, 8, 12})) != LK_OK) return st;
 
