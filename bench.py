@@ -71,15 +71,15 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 TRAFFIC = {
     ("chainmail", "mixed"): {
         "kernel": "_ZN2lk12_GLOBAL__N_113ds_persistentIffLi2ELi4ELb1EEEvNS_6DsArgsE",
-        "isa": "692da477f89576ca",
+        "isa": "69e07da7d58f865f",
         "config": {"segs_per_lane": 4, "tile_a": 512, "chunk_a": 4096, "atan_form": 2},
         "fetch_scale": 2.000, "write_scale": 1.000,
         # (effective small batch, waves_per_cu) -> (FETCH_SIZE, WRITE_SIZE) KiB
         # per launch.  The runtime raises a batch below segs_per_lane to it,
         # so batches 1, 2 and 4 launch the same work here.
-        "by_launch": {(4, 0): (23995.6, 2564.7), (4, 8): (23970.4, 2585.4),
-                      (4, 12): (23848.7, 2550.6), (8, 0): (21291.8, 1968.0),
-                      (8, 12): (21426.1, 1965.2)},
+        "by_launch": {(4, 0): (24062.6, 2578.0), (4, 8): (24043.7, 2561.1),
+                      (4, 12): (23789.7, 2563.9), (8, 0): (21175.3, 1963.6),
+                      (8, 12): (21192.9, 1959.5)},
         "source": "profiles/ds_persistent_chainmail_hbm_traffic.txt",
     },
 }

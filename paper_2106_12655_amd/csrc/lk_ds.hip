@@ -723,6 +723,15 @@ __global__ __launch_bounds__(kWave) void ds_persistent(DsArgs A) {
           culled = true;
         }
       }
+      // Code placement of the big-item walk loop of the FP32 kernel that
+      // big pairs run (R = 4, arctangent form 2): with these four no-ops its
+      // first instruction sits 12 bytes past a 32-byte boundary of the
+      // kernel, where it measured 570 ms per knit-workload call against
+      // 598-645 ms at the other offsets (same instructions, a sweep of 0-16
+      // no-ops).  The other walk loops come earlier in the code and do not
+      // move; a CPU test checks the placements.
+      if constexpr (PK && sizeof(Tin) == 4 && sizeof(Tc) == 4 && AT == 2 && R == 4)
+        asm volatile(".rept 4\n s_nop 0\n.endr");
       if (!culled)
       for (int t0 = 0; t0 < L.nah; t0 += A.tile) {
         const int tl = (L.nah - t0) < A.tile ? (L.nah - t0) : A.tile;
