@@ -306,7 +306,9 @@ __device__ void schedule(const Sched& S, int32_t* zero_next) {
   __shared__ int cur[32];
   __shared__ int64_t wsum[16];
   const int t = threadIdx.x;
-  const int nb = S.counts[1];
+  // a device-scope load: in the fused launch below the count was built by
+  // atomics of the same kernel
+  const int nb = __hip_atomic_load(&S.counts[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (t < 32) hist[t] = 0;
   __syncthreads();
   for (int k = t; k < nb; k += 1024) atomicAdd(&hist[cost_bucket(S.big_in[k].items)], 1);
@@ -338,39 +340,13 @@ __device__ void schedule(const Sched& S, int32_t* zero_next) {
   }
 }
 
-// One thread per list position, 1024-thread workgroups.  The schedule is a
-// separate single-workgroup launch: handing it to the plan's last workgroup
-// (a fence and a ticket in every workgroup) measured slower on MI355X, where
-// a device-scope fence writes back the XCD's L2.
-__global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo li, Sched S,
-                                               int refit) {
-  // xi = mean |coordinate|: every block reduces the preparation kernel's
-  // partials in the same fixed order (cheaper than another launch); a refit
-  // pass validates nothing and skips it
-  __shared__ double red[1024];
-  double xi = 0.0;
-  if (!refit) {
-    double part = 0.0;
-    for (int k = threadIdx.x; k < li.n_part; k += 1024) part += li.part[k];
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    const int64_t nv = A.off[L] - A.off[0];
-    xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
-  }
-  int64_t n = A.n_list;
-  if (A.n_list_dev) {
-    const int64_t nd = *A.n_list_dev;
-    n = nd < n ? nd : n;
-  }
-  // grid stride over the list's length on the device (the same in every
-  // thread: the appends below are workgroup-collective), so an empty refit
-  // list costs each workgroup one load
-  for (int64_t base = (int64_t)blockIdx.x * 1024; base < n;
-       base += (int64_t)gridDim.x * 1024) {
+// The plan's work over list positions base = first, first + stride, ...
+// below n, one thread per position (every thread of the workgroup takes part:
+// the appends are workgroup-collective, so n and the loop bounds must be the
+// same in every thread).
+__device__ void plan_positions(const PlanArgs& A, int32_t L, const LoopInfo& li, const Sched& S,
+                               int refit, double xi, int64_t n, int64_t first, int64_t stride) {
+  for (int64_t base = first; base < n; base += stride) {
     const int64_t q = base + threadIdx.x;
     bool small = false, big = false;
     WorkRec r{};
@@ -451,16 +427,77 @@ __global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo l
   }
 }
 
-__global__ __launch_bounds__(256) void finalize_split_k(Sched S, const unsigned long long* acc,
-                                                        Outs o) {
+// One thread per list position, 1024-thread workgroups.  The schedule is a
+// separate single-workgroup launch: handing it to the plan's last workgroup
+// (a fence and a ticket in every workgroup) measured slower on MI355X, where
+// a device-scope fence writes back the XCD's L2.
+__global__ __launch_bounds__(1024) void plan_k(PlanArgs A, int32_t L, LoopInfo li, Sched S,
+                                               int refit) {
+  // xi = mean |coordinate|: every block reduces the preparation kernel's
+  // partials in the same fixed order (cheaper than another launch); a refit
+  // pass validates nothing and skips it
+  __shared__ double red[1024];
+  double xi = 0.0;
+  if (!refit) {
+    double part = 0.0;
+    for (int k = threadIdx.x; k < li.n_part; k += 1024) part += li.part[k];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    const int64_t nv = A.off[L] - A.off[0];
+    xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
+  }
+  int64_t n = A.n_list;
+  if (A.n_list_dev) {
+    const int64_t nd = __hip_atomic_load(A.n_list_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    n = nd < n ? nd : n;
+  }
+  // grid stride over the list's length on the device (the same in every
+  // thread), so an empty refit list costs each workgroup one load
+  plan_positions(A, L, li, S, refit, xi, n, (int64_t)blockIdx.x * 1024, (int64_t)gridDim.x * 1024);
+}
+
+// Finalises the big-list pairs that were split over several work items,
+// positions first, first + stride, ...
+__device__ void finalize_split_range(const Sched& S, const unsigned long long* acc, const Outs& o,
+                                     int32_t first, int32_t stride) {
   if (o.stop && *o.stop) return;  // a fused check stopped early: sums may be partial
   const int32_t nb = S.counts[1];
-  for (int32_t k = blockIdx.x * 256 + threadIdx.x; k < nb; k += gridDim.x * 256) {
+  for (int32_t k = first; k < nb; k += stride) {
     const WorkRec r = S.big[k];
     if (r.items < 2) continue;  // single-item pairs were finalised by their wave
     const int32_t p = r.p;
     finalize_pair(o, p, from_fixed(acc[2 * (int64_t)p], acc[2 * (int64_t)p + 1]), o.flags[p]);
   }
+}
+
+__global__ __launch_bounds__(256) void finalize_split_k(Sched S, const unsigned long long* acc,
+                                                        Outs o) {
+  finalize_split_range(S, acc, o, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
+}
+
+// The end of one pass and the start of the next in one launch of a single
+// workgroup: the pass's split pairs are finalised (queuing their refits), then
+// the refit list is planned and scheduled.  Every write that a later step
+// reads comes from the same workgroup, so barriers order the three steps and
+// no grid-wide synchronisation is needed.  This saves two kernel boundaries
+// per call (each a few microseconds on MI355X); the steps are short (a refit
+// list is usually empty, and the split pairs number a few thousand at most).
+__global__ __launch_bounds__(1024) void finalize_replan_k(Sched S, const unsigned long long* acc,
+                                                          Outs o, PlanArgs R, int32_t L,
+                                                          LoopInfo li, Sched SR,
+                                                          int32_t* zero_next) {
+  finalize_split_range(S, acc, o, threadIdx.x, 1024);
+  __syncthreads();
+  int64_t n = R.n_list;
+  const int64_t nd = __hip_atomic_load(R.n_list_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  n = nd < n ? nd : n;
+  plan_positions(R, L, li, SR, 1, 0.0, n, 0, 1024);
+  __syncthreads();
+  schedule(SR, zero_next);
 }
 
 __global__ __launch_bounds__(1024) void sched_k(Sched S, int32_t* zero_next) {
@@ -983,6 +1020,14 @@ hipError_t launch_finalize_split(const Sched& sc, const unsigned long long* acc,
 
 hipError_t launch_sched(const Sched& sc, int32_t* zero_next, hipStream_t s) {
   sched_k<<<1, 1024, 0, s>>>(sc, zero_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_replan(const Sched& sc, const unsigned long long* acc, const Outs& o,
+                                  const PlanArgs& r, int32_t n_loops, const LoopInfo& li,
+                                  const Sched& sr, int32_t* zero_next, hipStream_t s) {
+  if (!r.n_list_dev) return hipErrorInvalidValue;
+  finalize_replan_k<<<1, 1024, 0, s>>>(sc, acc, o, r, n_loops, li, sr, zero_next);
   return hipGetLastError();
 }
 

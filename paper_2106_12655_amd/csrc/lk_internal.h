@@ -367,6 +367,12 @@ hipError_t launch_finalize_split(const Sched& s, const unsigned long long* acc, 
 // work counter and (optionally) three int32 of the next pass: its two
 // schedule counts and the refit count that follows them in memory.
 hipError_t launch_sched(const Sched& s, int32_t* zero_counts_next, hipStream_t st);
+// finalize_split of one pass, then the plan (refit semantics, list and its
+// length on the device) and the schedule of the next, as one single-workgroup
+// launch.
+hipError_t launch_finalize_replan(const Sched& s, const unsigned long long* acc, const Outs& o,
+                                  const PlanArgs& r, int32_t n_loops, const LoopInfo& li,
+                                  const Sched& sr, int32_t* zero_counts_next, hipStream_t st);
 // *p = 0 with a kernel (safe inside a captured sequence).
 hipError_t launch_zero_i64(int64_t* p, hipStream_t s);
 // Exclusive scan of counts[0..n) into prefix[0..n] (single workgroup).

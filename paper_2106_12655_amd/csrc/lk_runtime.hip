@@ -485,7 +485,9 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
     LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
                              P.mixed ? P.grid : P.grid64, s, P.unpacked));
     if (timed) LK_HIP(hipEventRecord(ev[1], s));
-    LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
+    // a mixed call finalises its split pairs in the launch that plans the
+    // refit pass (below)
+    if (!P.mixed) LK_HIP(launch_finalize_split(A.s, acc, out, n_pairs, s));
   }
   if (P.mixed) {
     // refit: the FP64 direct sum (MIXED), or the FP64 crossing count
@@ -514,15 +516,21 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
     // over the most waves
     B.batch = 1;
     B.out = ro;
-    LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
-    LK_HIP(launch_sched(B.s, P.crossings ? W.at<int32_t>(kMetaCountsRefit2) : nullptr, s));
+    int32_t* zero_next = P.crossings ? W.at<int32_t>(kMetaCountsRefit2) : nullptr;
+    if (P.bh) {
+      // the Barnes-Hut pass finalised its pairs itself
+      LK_HIP(launch_plan(R, n_loops, li, B.s, true, s));
+      LK_HIP(launch_sched(B.s, zero_next, s));
+    } else {
+      LK_HIP(launch_finalize_replan(A.s, acc, out, R, n_loops, li, B.s, zero_next, s));
+    }
     if (timed) LK_HIP(hipEventRecord(ev[2], s));
     // the FP64 crossing count gets the whole grid: its pairs are the ones
     // with shallow crossings, often the largest
     LK_HIP(launch_direct_sum(B, P.in_f64, true, P.crossings ? kFormCrossings : 0, P.segs64,
                              P.crossings ? P.grid_cc64 : P.grid_refit, s, P.unpacked));
     if (timed) LK_HIP(hipEventRecord(ev[3], s));
-    LK_HIP(launch_finalize_split(B.s, acc, ro, n_pairs, s));
+    if (!P.crossings) LK_HIP(launch_finalize_split(B.s, acc, ro, n_pairs, s));
     if (P.crossings) {
       Outs r2 = out;
       r2.refit_list = nullptr;
@@ -538,8 +546,9 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
       B2.s = make_sched(W, n_pairs, 2);
       B2.chunk = R2.chunk;
       B2.out = r2;
-      LK_HIP(launch_plan(R2, n_loops, li, B2.s, true, s));
-      LK_HIP(launch_sched(B2.s, nullptr, s));
+      // the FP64 crossing count's split pairs are finalised (queuing what it
+      // cannot decide) in the launch that plans the direct sum of those
+      LK_HIP(launch_finalize_replan(B.s, acc, ro, R2, n_loops, li, B2.s, nullptr, s));
       LK_HIP(launch_direct_sum(B2, P.in_f64, true, 0, P.segs64, P.grid_refit, s, P.unpacked));
       LK_HIP(launch_finalize_split(B2.s, acc, r2, n_pairs, s));
     }
