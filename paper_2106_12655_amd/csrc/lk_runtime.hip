@@ -584,8 +584,12 @@ Plan make_plan(lk_ctx* ctx, bool in_f64, int mode, int64_t n_pairs) {
                                ctx->opt_waves, P.unpacked);
   P.grid64 = lk::direct_sum_grid(in_f64, true, 0, P.segs64, mixed ? default_tile(true) : P.tile,
                                  ctx->n_cu, ctx->opt_waves, P.unpacked);
-  // refits are rare: a small persistent grid keeps the empty refit pass cheap
-  P.grid_refit = ctx->n_cu < P.grid64 ? ctx->n_cu : P.grid64;
+  // refits of the direct sum are rare: one wave per CU keeps the empty refit
+  // pass cheap (4.7 instead of 7.8 us on chainmail).  Barnes-Hut sends every
+  // pair whose far-field error estimate stays too large there (hundreds of
+  // big pairs on knit with adaptive beta), so its refit pass gets the whole
+  // grid.
+  P.grid_refit = P.bh || ctx->n_cu >= P.grid64 ? P.grid64 : ctx->n_cu;
   P.grid_cc64 = P.crossings ? lk::direct_sum_grid(in_f64, true, kFormCrossings, P.segs64,
                                                   default_tile(true), ctx->n_cu, 0)
                             : 0;
