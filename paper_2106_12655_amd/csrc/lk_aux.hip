@@ -42,6 +42,39 @@ __device__ __forceinline__ void block_sum_to(double v, double* red, double* part
 // itself.  When the crossing count's box kernel does the per-loop scan, this
 // kernel sums xi over a flat grid stride and only initialises the per-loop
 // entries.  Block 0 also zeroes the main pass's schedule counts.
+// One wavefront's scan of loop l: its flags that do not depend on xi (fewer
+// than 3 vertices, non-finite coordinates) and its shortest squared segment,
+// written by lane 0; returns the lane's sum of |x| + |y| + |z| over the
+// vertices it read.
+template <typename Tin>
+__device__ double scan_loop(const Tin* X, const int64_t* off, int64_t l, int lane, uint32_t* lf,
+                            double* minseg2) {
+  double s = 0.0;
+  const int64_t o = off[l], n = off[l + 1] - o;
+  uint32_t f = (n < 3) ? kFlagBadloop : 0u;
+  double mn = INFINITY;
+  for (int64_t q = lane; q < n; q += 64) {
+    const int64_t t = (q + 1 == n) ? 0 : q + 1;
+    const double x0 = (double)X[3 * (o + q)], y0 = (double)X[3 * (o + q) + 1],
+                 z0 = (double)X[3 * (o + q) + 2];
+    const double x1 = (double)X[3 * (o + t)], y1 = (double)X[3 * (o + t) + 1],
+                 z1 = (double)X[3 * (o + t) + 2];
+    if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0)) f |= kFlagNonfinite | kFlagBadloop;
+    s += fabs(x0) + fabs(y0) + fabs(z0);
+    const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+    mn = fmin(mn, dx * dx + dy * dy + dz * dz);
+  }
+  for (int o2 = 32; o2 > 0; o2 >>= 1) {
+    f |= (uint32_t)__shfl_xor((int)f, o2);
+    mn = fmin(mn, __shfl_xor(mn, o2));
+  }
+  if (lane == 0) {
+    lf[l] = f;
+    minseg2[l] = mn;
+  }
+  return s;
+}
+
 template <typename Tin>
 __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, int32_t L,
                                               double* part, uint32_t* lf, double* minseg2,
@@ -75,30 +108,7 @@ __global__ __launch_bounds__(256) void prep_k(const Tin* X, const int64_t* off, 
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
-  for (int64_t l = wave; l < L; l += nwaves) {
-    const int64_t o = off[l], n = off[l + 1] - o;
-    uint32_t f = (n < 3) ? kFlagBadloop : 0u;
-    double mn = INFINITY;
-    for (int64_t q = lane; q < n; q += 64) {
-      const int64_t t = (q + 1 == n) ? 0 : q + 1;
-      const double x0 = (double)X[3 * (o + q)], y0 = (double)X[3 * (o + q) + 1],
-                   z0 = (double)X[3 * (o + q) + 2];
-      const double x1 = (double)X[3 * (o + t)], y1 = (double)X[3 * (o + t) + 1],
-                   z1 = (double)X[3 * (o + t) + 2];
-      if (!isfinite(x0) || !isfinite(y0) || !isfinite(z0)) f |= kFlagNonfinite | kFlagBadloop;
-      s += fabs(x0) + fabs(y0) + fabs(z0);
-      const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
-      mn = fmin(mn, dx * dx + dy * dy + dz * dz);
-    }
-    for (int o2 = 32; o2 > 0; o2 >>= 1) {
-      f |= (uint32_t)__shfl_xor((int)f, o2);
-      mn = fmin(mn, __shfl_xor(mn, o2));
-    }
-    if (lane == 0) {
-      lf[l] = f;
-      minseg2[l] = mn;
-    }
-  }
+  for (int64_t l = wave; l < L; l += nwaves) s += scan_loop(X, off, l, lane, lf, minseg2);
   block_sum_to(s, red, part);
 }
 
@@ -960,6 +970,40 @@ __global__ __launch_bounds__(256) void verify_scatter_k(const int32_t* pr, const
   }
 }
 
+// Preparation, plan and schedule of a call with few pairs in one launch of a
+// single workgroup: the per-loop scan of prep_k (16 wavefronts over the
+// loops), xi as this workgroup's fixed-order sum, then the plan and the
+// schedule.  Each step reads only what the workgroup wrote before a barrier.
+// Used where the pairs are at most two per compute unit: there three launches
+// cost more than their work (a call with few but very long loops scans them
+// with 16 wavefronts only, which its direct sum dwarfs).
+template <typename Tin>
+__global__ __launch_bounds__(1024) void prep_plan_k(const Tin* X, PlanArgs A, int32_t L,
+                                                    LoopInfo li, uint32_t* lf, double* minseg2,
+                                                    Sched S, unsigned long long* zero_mismatch,
+                                                    int32_t* zero_stop, int32_t* zero_next) {
+  __shared__ double red[1024];
+  if (threadIdx.x < 2) S.counts[threadIdx.x] = 0;
+  if (threadIdx.x == 0 && zero_mismatch) {
+    *zero_mismatch = 0ull;
+    *zero_stop = 0;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int64_t l = wave; l < L; l += 16) s += scan_loop(X, A.off, l, lane, lf, minseg2);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const int64_t nv = A.off[L] - A.off[0];
+  const double xi = nv > 0 ? red[0] / (3.0 * (double)nv) : 0.0;
+  plan_positions(A, L, li, S, 0, xi, A.n_list, 0, 1024);
+  __syncthreads();
+  schedule(S, zero_next);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1020,6 +1064,20 @@ hipError_t launch_finalize_split(const Sched& sc, const unsigned long long* acc,
 
 hipError_t launch_sched(const Sched& sc, int32_t* zero_next, hipStream_t s) {
   sched_k<<<1, 1024, 0, s>>>(sc, zero_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_plan(const void* xyz, bool in_f64, const PlanArgs& a, int32_t n_loops,
+                            const LoopInfo& li, uint32_t* lf, double* minseg2, const Sched& sc,
+                            unsigned long long* zero_mismatch, int32_t* zero_stop,
+                            int32_t* zero_next, hipStream_t s) {
+  if (a.list || a.n_list_dev) return hipErrorInvalidValue;  // the main pass only
+  if (in_f64)
+    prep_plan_k<double><<<1, 1024, 0, s>>>((const double*)xyz, a, n_loops, li, lf, minseg2, sc,
+                                          zero_mismatch, zero_stop, zero_next);
+  else
+    prep_plan_k<float><<<1, 1024, 0, s>>>((const float*)xyz, a, n_loops, li, lf, minseg2, sc,
+                                         zero_mismatch, zero_stop, zero_next);
   return hipGetLastError();
 }
 

@@ -367,6 +367,12 @@ hipError_t launch_finalize_split(const Sched& s, const unsigned long long* acc, 
 // work counter and (optionally) three int32 of the next pass: its two
 // schedule counts and the refit count that follows them in memory.
 hipError_t launch_sched(const Sched& s, int32_t* zero_counts_next, hipStream_t st);
+// prep, plan (main pass) and sched as one single-workgroup launch, for calls
+// with few pairs; the per-loop scan runs on 16 wavefronts.
+hipError_t launch_prep_plan(const void* xyz, bool in_f64, const PlanArgs& a, int32_t n_loops,
+                            const LoopInfo& li, uint32_t* lf, double* minseg2, const Sched& sc,
+                            unsigned long long* zero_mismatch, int32_t* zero_stop,
+                            int32_t* zero_counts_next, hipStream_t st);
 // finalize_split of one pass, then the plan (refit semantics, list and its
 // length on the device) and the schedule of the next, as one single-workgroup
 // launch.

@@ -409,9 +409,12 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
   A.out = out;
 
   // the crossing count's box kernel and the Barnes-Hut leaf kernel validate
-  // the loops in parallel; the preparation kernel then only initialises
-  LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, W.minseg2, A.s.counts,
-                     out.n_mismatch, out.stop, !cull && !P.bh, li.n_part, s));
+  // the loops in parallel; the preparation kernel then only initialises.  A
+  // direct sum with few pairs prepares, plans and schedules in one launch.
+  const bool one_launch_start = P.unpacked && !cull && !P.bh;
+  if (!one_launch_start)
+    LK_HIP(launch_prep(xyz, P.in_f64, off, n_loops, xi, lf, W.minseg2, A.s.counts,
+                       out.n_mismatch, out.stop, !cull && !P.bh, li.n_part, s));
   if (cull)
     LK_HIP(launch_cc_boxes(xyz, P.in_f64, off, n_loops, cc_projection(ctx->view),
                            (float4*)ctx->cc_blk.p, A.cc_nblk, (float4*)ctx->cc_sup.p, A.cc_nsup,
@@ -479,8 +482,13 @@ lk_status enqueue_direct_sum(lk_ctx* ctx, const Ws& W, const Plan& P, const void
     if (timed) LK_HIP(hipEventRecord(ev[1], s));
     LK_HIP(launch_bh_finalize(H, n_pairs, s));
   } else {
-    LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
-    LK_HIP(launch_sched(A.s, W.at<int32_t>(kMetaCountsRefit), s));
+    if (one_launch_start) {
+      LK_HIP(launch_prep_plan(xyz, P.in_f64, M, n_loops, li, lf, W.minseg2, A.s, out.n_mismatch,
+                              out.stop, W.at<int32_t>(kMetaCountsRefit), s));
+    } else {
+      LK_HIP(launch_plan(M, n_loops, li, A.s, false, s));
+      LK_HIP(launch_sched(A.s, W.at<int32_t>(kMetaCountsRefit), s));
+    }
     if (timed) LK_HIP(hipEventRecord(ev[0], s));
     LK_HIP(launch_direct_sum(A, P.in_f64, !P.mixed, P.atan_form, P.mixed ? P.segs : P.segs64,
                              P.mixed ? P.grid : P.grid64, s, P.unpacked));
