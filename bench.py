@@ -79,7 +79,9 @@ TRAFFIC = {
         # so batches 1, 2 and 4 launch the same work here.
         "by_launch": {(4, 0): (24062.6, 2578.0), (4, 8): (24043.7, 2561.1),
                       (4, 12): (23789.7, 2563.9), (8, 0): (21175.3, 1963.6),
-                      (8, 12): (21192.9, 1959.5)},
+                      (8, 8): (21215.4, 1951.1), (8, 12): (21192.9, 1959.5),
+                      (16, 0): (19740.0, 1598.0), (16, 8): (19742.0, 1605.9),
+                      (16, 12): (19707.8, 1608.5)},
         "source": "profiles/ds_persistent_chainmail_hbm_traffic.txt",
     },
 }
