@@ -46,14 +46,16 @@ __device__ __forceinline__ void block_sum_to(double v, double* red, double* part
 // than 3 vertices, non-finite coordinates) and its shortest squared segment,
 // written by lane 0; returns the lane's sum of |x| + |y| + |z| over the
 // vertices it read.
-template <typename Tin>
+// W: lanes per loop (a power of two up to 64, aligned within the wavefront;
+// every lane of the group calls it).
+template <typename Tin, int W = 64>
 __device__ double scan_loop(const Tin* X, const int64_t* off, int64_t l, int lane, uint32_t* lf,
                             double* minseg2) {
   double s = 0.0;
   const int64_t o = off[l], n = off[l + 1] - o;
   uint32_t f = (n < 3) ? kFlagBadloop : 0u;
   double mn = INFINITY;
-  for (int64_t q = lane; q < n; q += 64) {
+  for (int64_t q = lane; q < n; q += W) {
     const int64_t t = (q + 1 == n) ? 0 : q + 1;
     const double x0 = (double)X[3 * (o + q)], y0 = (double)X[3 * (o + q) + 1],
                  z0 = (double)X[3 * (o + q) + 2];
@@ -64,7 +66,7 @@ __device__ double scan_loop(const Tin* X, const int64_t* off, int64_t l, int lan
     const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
     mn = fmin(mn, dx * dx + dy * dy + dz * dz);
   }
-  for (int o2 = 32; o2 > 0; o2 >>= 1) {
+  for (int o2 = W / 2; o2 > 0; o2 >>= 1) {
     f |= (uint32_t)__shfl_xor((int)f, o2);
     mn = fmin(mn, __shfl_xor(mn, o2));
   }
@@ -971,12 +973,13 @@ __global__ __launch_bounds__(256) void verify_scatter_k(const int32_t* pr, const
 }
 
 // Preparation, plan and schedule of a call with few pairs in one launch of a
-// single workgroup: the per-loop scan of prep_k (16 wavefronts over the
-// loops), xi as this workgroup's fixed-order sum, then the plan and the
-// schedule.  Each step reads only what the workgroup wrote before a barrier.
-// Used where the pairs are at most two per compute unit: there three launches
-// cost more than their work (a call with few but very long loops scans them
-// with 16 wavefronts only, which its direct sum dwarfs).
+// single workgroup: the per-loop scan of prep_k (16 lanes per loop, so 64
+// loops are scanned at once and their loads overlap), xi as this workgroup's
+// fixed-order sum, then the plan and the schedule.  Each step reads only
+// what the workgroup wrote before a barrier.  Used where the pairs are at
+// most two per compute unit: there three launches cost more than their work
+// (a call with few but very long loops scans them with one workgroup only,
+// which its direct sum dwarfs).
 template <typename Tin>
 __global__ __launch_bounds__(1024) void prep_plan_k(const Tin* X, PlanArgs A, int32_t L,
                                                     LoopInfo li, uint32_t* lf, double* minseg2,
@@ -988,9 +991,9 @@ __global__ __launch_bounds__(1024) void prep_plan_k(const Tin* X, PlanArgs A, in
     *zero_mismatch = 0ull;
     *zero_stop = 0;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = threadIdx.x & 15, group = threadIdx.x >> 4;
   double s = 0.0;
-  for (int64_t l = wave; l < L; l += 16) s += scan_loop(X, A.off, l, lane, lf, minseg2);
+  for (int64_t l = group; l < L; l += 64) s += scan_loop<Tin, 16>(X, A.off, l, sub, lf, minseg2);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
