@@ -81,7 +81,11 @@ typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
  * blocks of 64 consecutive vertices (and of 4096) whose projected boxes are
  * disjoint from the other loop's block (LK_OPT_CROSSING_CULL).  To size those
  * boxes the first CROSSINGS call with a given offsets array reads its
- * vertex count from the device, which synchronises the stream once. */
+ * vertex count from the device, which synchronises the stream once.  The
+ * count is kept per (offsets pointer, loop count): if later offsets at the
+ * same address describe more vertices (a reused allocation), results stay
+ * exact, but culling covers only the slots counted first and the pairs
+ * beyond them are counted without it. */
 /* BARNES_HUT: the two-tree Barnes-Hut method (Sec. 3.4.4, Alg. 6), an
  * approximation with the direct sum's Eq. 4 at the leaves: trees over runs of
  * 64 consecutive segments (8 children per node), node pairs farther apart
@@ -90,7 +94,9 @@ typedef enum { LK_F32 = 0, LK_F64 = 1 } lk_dtype;
  * quadrupole order) in FP64, leaf pairs the FP32 term with FP64 sums.  Pairs
  * whose value is farther than the refit threshold from an integer are
  * recomputed by the FP64 direct sum, as in MIXED.  Like CROSSINGS, the first
- * call for an offsets array reads its vertex count (one synchronisation). */
+ * call for an offsets array reads its vertex count (one synchronisation);
+ * trees that a reused allocation with more vertices would outgrow are not
+ * built, and those pairs go to the FP64 direct sum. */
 typedef enum { LK_PLAIN_F64 = 0, LK_MIXED = 1, LK_CROSSINGS = 2, LK_BARNES_HUT = 3 } lk_mode;
 
 /* Per-pair flags (bit set). */
